@@ -1,0 +1,364 @@
+"""Pins for the CPU oracle, checked against things other than the oracle itself:
+published hash vectors, hand-worked parses, an independent brute-force
+(dynamic-programming) formulation of the greedy parse on tiny inputs,
+container bytes laid out by hand, closed-form entropies, and a schedule
+simulation for the dependency levels."""
+import os
+import struct
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ FNV-1a 64
+
+def test_fnv_published_vectors():
+    n = 0
+    with open(os.path.join(GOLD, "fnv1a64_vectors.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            lit, h = line.rstrip("\n").split("\t")
+            data = eval(lit)  # python bytes literal from the fixture
+            assert oracle.fnv1a64(data) == int(h, 16), lit
+            n += 1
+    assert n >= 5
+
+
+# ---------------------------------------------------------- greedy parse pins
+
+def _cls(d, bounds):
+    return 0 if d < bounds[0] else 1 if d < bounds[1] else 2 if d < bounds[2] else 3
+
+
+def greedy_by_dp(x, bs, thr, bounds):
+    """Greedy parse from a longest-common-prefix table (a different
+    formulation from the oracle's forward scan): lcp[i][j] is filled from the
+    end of the string, then each position takes the longest valid source,
+    nearest on ties."""
+    x = list(int(v) for v in x)
+    n = len(x)
+    lcp = np.zeros((n + 1, n + 1), dtype=np.int64)
+    for i in range(n - 1, -1, -1):
+        for j in range(n - 1, -1, -1):
+            if x[i] == x[j]:
+                lcp[i, j] = lcp[i + 1, j + 1] + 1
+    toks = []
+    for b0 in range(0, n, bs):
+        end = min(n, b0 + bs)
+        pos, run = b0, 0
+        while pos < end:
+            best = None
+            for src in range(pos):
+                L = min(int(lcp[src, pos]), end - pos)
+                if L >= thr[_cls(pos - src, bounds)]:
+                    if best is None or L > best[0] or (L == best[0] and src > best[1]):
+                        best = (L, src)
+            if best:
+                toks.append((run, best[0], best[1]))
+                run = 0
+                pos += best[0]
+            else:
+                run += 1
+                pos += 1
+        if run:
+            toks.append((run, 0, 0))
+    return toks
+
+
+def _otoks(x, log2_bs, thr, bounds):
+    ll, ml, sr, lit = oracle.encode(np.asarray(x, dtype=np.uint8), log2_bs, thr, bounds)
+    return [(int(a), int(b), int(c) if b else 0) for a, b, c in zip(ll, ml, sr)], lit
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_greedy_matches_dp_bruteforce(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 160))
+    alpha = int(rng.integers(1, 5))
+    x = rng.integers(0, alpha, size=n).astype(np.uint8)
+    # sometimes splice in a repeat to get long matches
+    if n > 40 and seed % 2:
+        x[n // 2:n // 2 + 20] = x[3:23]
+    log2_bs = int(rng.integers(4, 8))
+    thr = tuple(sorted(int(v) for v in rng.integers(1, 7, size=4)))
+    bounds = (int(rng.integers(1, 8)), int(rng.integers(8, 32)), int(rng.integers(32, 96)))
+    got, lit = _otoks(x, log2_bs, thr, bounds)
+    want = greedy_by_dp(x, 1 << log2_bs, thr, bounds)
+    assert got == want
+    # literal stream = the bytes not covered by matches, in order
+    pos, lits = 0, []
+    for a, b, c in want:
+        lits.extend(x[pos:pos + a])
+        pos += a + b
+    assert np.array_equal(lit, np.array(lits, dtype=np.uint8))
+
+
+def test_greedy_hand_worked():
+    """Parses worked by hand from the definition."""
+    B = (4096, 65536, 1 << 20)
+    # period-3 text: three literals, then one overlapping match to the end
+    got, _ = _otoks(np.frombuffer(b"abcabcabcabc", np.uint8), 4, (3, 3, 3, 3), B)
+    assert got == [(3, 9, 0)]
+    # run of one byte: a literal then a distance-1 match
+    got, _ = _otoks(np.frombuffer(b"aaaaaaaa", np.uint8), 4, (2, 2, 2, 2), B)
+    assert got == [(1, 7, 0)]
+    # thresholds above any possible length: all literal
+    got, _ = _otoks(np.frombuffer(b"aaaaaaaa", np.uint8), 4, (99, 99, 99, 99), B)
+    assert got == [(8, 0, 0)]
+    # block size 16 cuts the run: each block restarts; the second block can
+    # reach back into the first (absolute sources, whole-prefix window)
+    got, _ = _otoks(np.frombuffer(b"a" * 20, np.uint8), 4, (2, 2, 2, 2), B)
+    assert got == [(1, 15, 0), (0, 4, 15)]
+    # distance classes: "wxyz" repeats at distance 4 (class 0, thr 4) and
+    # its second copy at distance 8 would be class 1 (thr 5): only the
+    # nearest is valid and nearest wins ties anyway
+    got, _ = _otoks(np.frombuffer(b"wxyzwxyzwxyz", np.uint8), 4, (4, 5, 5, 5), (5, 64, 128))
+    assert got == [(4, 8, 0)]
+    # raising the class-0 threshold above 8 forbids the distance-4 source,
+    # and nothing else can reach 9
+    got, _ = _otoks(np.frombuffer(b"wxyzwxyzwxyz", np.uint8), 4, (9, 9, 9, 9), (5, 64, 128))
+    assert got == [(12, 0, 0)]
+    # longest wins over nearest: "abcd" at 0, "abc" at 5, then "abcd"
+    got, _ = _otoks(np.frombuffer(b"abcdXabcYabcd", np.uint8), 4, (3, 3, 3, 3), B)
+    assert got == [(5, 3, 0), (1, 4, 0)]
+
+
+def test_greedy_invariants_zipf():
+    x = synth.zipf_text(12000, seed=11)
+    thr, B = (6, 8, 10, 12), (512, 4096, 8192)
+    ll, ml, sr, lit = oracle.encode(x, 11, thr, B)
+    arc = oracle.write_archive(x.size, 11, ll, ml, sr, lit, min_match=6, thr=thr, bounds=B)
+    T = oracle.tokens(arc)
+    bs = 1 << 11
+    m = T["mlen"] > 0
+    mstart = T["dst"] + T["lit_len"]
+    assert np.all(T["src"][m] < mstart[m])
+    cls = np.array([_cls(int(d), B) for d in (mstart[m] - T["src"][m])])
+    assert np.all(T["mlen"][m] >= np.array(thr)[cls])
+    # tokens tile each block and never cross a block end
+    ends = mstart + T["mlen"]
+    assert np.all((ends - 1) // bs == T["dst"] // bs)
+    assert np.array_equal(oracle.decode(arc), x)
+
+
+# ------------------------------------------------------------ container pins
+
+def _hand_archive():
+    """Container bytes laid out by hand from the format statement: n = 29,
+    one block of 32 bytes holding two tokens, min_match 3.
+    token 0: 3 literals "xyz", match code 2 (length 3 + 2 = 5) from 0,
+             an overlapping copy -> "xyz" + "xyzxy"
+    token 1 (last): 17 literals via code 15 + x16 value 2, then a match of
+             the implied length 29 - 8 - 17 = 4 from position 10."""
+    lits = b"xyz" + b"ABCDEFGHIJKLMNOPQ"
+    n = 3 + 5 + 17 + 4
+    hdr = bytearray(128)
+    struct.pack_into("<IIQIIII", hdr, 0, 0x314D5A4C, 1, n, 5, 1, 3, 0)
+    struct.pack_into("<QQQQ", hdr, 32, 2, 1, 0, len(lits))
+    table = struct.pack("<4Q", 0, 0, 0, 0) + struct.pack("<4Q", 2, len(lits), 1, 0)
+    body = bytearray(hdr) + table
+    def pad(b):
+        b += bytes((16 - len(b) % 16) % 16)
+    pad(body)
+    body += bytes([0x32, 0xF0])        # cmd: (3,2) then (15,0)
+    pad(body)
+    body += struct.pack("<H", 2)      # x16: 15 + 2 = 17 literals
+    pad(body)
+    pad(body)                          # x32: empty
+    body += struct.pack("<II", 0, 10)  # src_lo: token 0 from 0, token 1 from 10
+    pad(body)
+    body += lits
+    pad(body)
+    body += bytes(16)
+    expect = bytearray(b"xyz")
+    for i in range(5):
+        expect.append(expect[0 + i])
+    expect += b"ABCDEFGHIJKLMNOPQ"
+    for i in range(4):
+        expect.append(expect[10 + i])
+    return np.frombuffer(bytes(body), np.uint8), np.frombuffer(bytes(expect), np.uint8)
+
+
+def test_decode_hand_built_archive():
+    arc, expect = _hand_archive()
+    assert expect.size == 29
+    out = oracle.decode(arc)
+    assert bytes(out) == bytes(expect)
+    assert bytes(out) == b"xyzxyzxyABCDEFGHIJKLMNOPQCDEF"
+
+
+def test_decode_rejects_corruption():
+    arc, _ = _hand_archive()
+    assert oracle.decode_rc(arc) == 0
+    bad = arc.copy(); bad[0] ^= 1
+    assert oracle.decode_rc(bad) == oracle.OR_E_CORRUPT
+    assert oracle.decode_rc(arc[:100]) == oracle.OR_E_CORRUPT
+    assert oracle.decode_rc(arc[:-17]) == oracle.OR_E_CORRUPT
+    # source not before its destination: token 0 from 3 (its own start)
+    i = arc.size - 16 - 32 - 16  # start of src_lo
+    bad = arc.copy(); bad[i] = 3
+    assert oracle.decode_rc(bad) == oracle.OR_E_CORRUPT
+    # last token with a non-zero match code
+    j = 128 + 64
+    bad = arc.copy(); bad[j + 1] = 0xF1
+    assert oracle.decode_rc(bad) == oracle.OR_E_CORRUPT
+    # match code that overruns the block
+    bad = arc.copy(); bad[j] = 0x3E
+    assert oracle.decode_rc(bad) == oracle.OR_E_CORRUPT
+
+
+@pytest.mark.parametrize("log2_bs", [4, 6, 12, 16])
+def test_roundtrip_sizes(log2_bs):
+    bs = 1 << log2_bs
+    rng = np.random.default_rng(log2_bs)
+    for n in [0, 1, bs - 1, bs, bs + 1, 3 * bs]:
+        if n > 3000:
+            continue
+        x = rng.integers(0, 3, size=n).astype(np.uint8)
+        ll, ml, sr, lit = oracle.encode(x, log2_bs, (2, 3, 4, 5))
+        arc = oracle.write_archive(n, log2_bs, ll, ml, sr, lit)
+        assert np.array_equal(oracle.decode(arc), x)
+    z = np.zeros(2000, np.uint8)
+    ll, ml, sr, lit = oracle.encode(z, log2_bs, (4, 4, 4, 4))
+    arc = oracle.write_archive(z.size, log2_bs, ll, ml, sr, lit)
+    assert np.array_equal(oracle.decode(arc), z)
+    # one literal + distance-1 matches: in each block, the first token reaches
+    # back to the previous byte (or is the single literal at position 0)
+    T = oracle.tokens(arc)
+    m = T["mlen"] > 0
+    assert int(T["lit_len"].sum()) == 1
+    assert np.all(T["dst"][m] + T["lit_len"][m] - T["src"][m] == 1)
+
+
+def test_split_matches_unsplit_execution():
+    """Cutting a generated token stream at block ends leaves the output as
+    executing the uncut stream."""
+    n = 200_000
+    ll, ml, sr, lit = synth.geo_tokens(n, 64, seed=5, lit_prefix=4096, min_back=4096)
+    ref = oracle.exec_tokens(n, ll, ml, sr, lit)
+    for lb in (10, 14, 16):
+        arc = oracle.write_archive(n, lb, ll, ml, sr, lit)
+        assert np.array_equal(oracle.decode(arc), ref)
+    # a plain python execution of the first tokens agrees
+    out = bytearray()
+    lo = 0
+    for t in range(40):
+        out += bytes(lit[lo:lo + ll[t]]); lo += int(ll[t])
+        for i in range(int(ml[t])):
+            out.append(out[int(sr[t]) + i])
+    assert bytes(ref[:len(out)]) == bytes(out)
+
+
+# -------------------------------------------------------------- levels pins
+
+def simulate_levels_ok(arc, lv):
+    """Replays the schedule: in pass p every block runs its level-p matches in
+    order (literals in pass 0).  A match may read a byte of another block only
+    if that byte was final before the pass began, and a byte of its own block
+    only if it was written earlier in the same or an earlier pass.  Also
+    checks each level is the smallest that works."""
+    T = oracle.tokens(arc)
+    n = oracle.info(arc)["n"]
+    bs = 1 << oracle.info(arc)["log2_bs"]
+    wlev = np.full(n, -1, dtype=np.int64)
+    for t in range(T["dst"].size):
+        d, L = int(T["dst"][t]), int(T["lit_len"][t])
+        wlev[d:d + L] = 0
+        m0, M, s = d + L, int(T["mlen"][t]), int(T["src"][t])
+        if M == 0:
+            continue
+        p = int(lv[t])
+        need = 0
+        for q in range(s, min(s + M, m0)):
+            assert wlev[q] >= 0
+            if q // bs != T["blk"][t]:
+                need = max(need, wlev[q] + 1)
+                assert wlev[q] < p
+            else:
+                need = max(need, wlev[q])
+                assert wlev[q] <= p
+        assert p == need
+        wlev[m0:m0 + M] = p
+    return True
+
+
+def test_levels_schedule_simulation():
+    x = synth.zipf_text(6000, seed=4)
+    for lb in (9, 10, 12):
+        ll, ml, sr, lit = oracle.encode(x, lb, (4, 6, 8, 10), (256, 1024, 4096))
+        arc = oracle.write_archive(x.size, lb, ll, ml, sr, lit)
+        lv, mx = oracle.levels(arc)
+        assert mx == lv.max()
+        assert simulate_levels_ok(arc, lv)
+    # generated stream: sources always >= 4 KiB back, so with 4 KiB blocks
+    # every match crosses blocks and levels grow by one per hop
+    n = 100_000
+    ll, ml, sr, lit = synth.geo_tokens(n, 32, seed=9, lit_prefix=4096, min_back=4096)
+    arc = oracle.write_archive(n, 12, ll, ml, sr, lit)
+    lv, mx = oracle.levels(arc)
+    assert simulate_levels_ok(arc, lv)
+    assert mx >= 2
+
+
+def test_levels_single_block_is_flat():
+    """Within one block nothing crosses blocks, so every level is 0."""
+    x = synth.zipf_text(4000, seed=8)
+    ll, ml, sr, lit = oracle.encode(x, 12, (4, 4, 4, 4))
+    arc = oracle.write_archive(x.size, 12, ll, ml, sr, lit)
+    lv, mx = oracle.levels(arc)
+    assert mx == 0
+
+
+# ------------------------------------------------------------- entropy pins
+
+def _literal_archive(data, log2_bs=16):
+    n = len(data)
+    return oracle.write_archive(n, log2_bs, [n], [0], [0], np.asarray(data, np.uint8))
+
+
+def test_entropy_closed_forms():
+    # constant bytes: H = 0 -> 0 bytes + table charge 1 + 2*1 per tile
+    arc = _literal_archive(np.full(65536, 7, np.uint8))
+    tot, parts = oracle.entropy_size(arc)
+    assert parts[4] == 3.0
+    # two symbols, equally often: exactly one bit each -> N/8 + 1 + 4
+    two = np.tile(np.array([1, 2], np.uint8), 32768)
+    tot, parts = oracle.entropy_size(_literal_archive(two))
+    assert parts[4] == 65536 / 8 + 5
+    # all 256 byte values equally often: 8 bits each -> N + 1 + 512
+    allv = np.tile(np.arange(256, dtype=np.uint8), 256)
+    tot, parts = oracle.entropy_size(_literal_archive(allv))
+    assert parts[4] == 65536 + 513
+    # two tiles are charged separately
+    tot, parts = oracle.entropy_size(_literal_archive(np.full(65537, 3, np.uint8), 17))
+    assert parts[4] == 3.0 + 3.0
+    # header + table verbatim; one token in cmd (1 symbol) and 4 src planes
+    assert parts[5] == 128 + 32 * 2
+    assert parts[0] == 3.0 and parts[3] == 12.0
+    assert tot == pytest.approx(parts.sum())
+
+
+# --------------------------------------------------------------- pure copy
+
+def test_purecopy_definition():
+    rng = np.random.default_rng(3)
+    ref = rng.integers(0, 256, 5000).astype(np.uint8)
+    lit = rng.integers(0, 256, 300).astype(np.uint8)
+    dst = np.array([0, 100, 2000], np.uint64)
+    lo = np.array([0, 10, 20], np.uint64)
+    ll = np.array([10, 10, 5], np.uint32)
+    src = np.array([4000, 7, 3], np.uint64)
+    ml = np.array([90, 1000, 2995], np.uint32)
+    out = oracle.purecopy(5000, dst, lo, ll, src, ml, lit, ref)
+    exp = np.zeros(5000, np.uint8)
+    for t in range(3):
+        d = int(dst[t]); a = int(ll[t]); b = int(ml[t])
+        exp[d:d + a] = lit[int(lo[t]):int(lo[t]) + a]
+        exp[d + a:d + a + b] = ref[int(src[t]):int(src[t]) + b]
+    assert np.array_equal(out, exp)
