@@ -1,0 +1,212 @@
+"""Match-phase decode throughput on one MI355X.
+
+Default workload: FASTQ-like reads, 1 GiB (whole records), 64 KiB LZ blocks,
+G = 32, encoded twice -- with the base thresholds 6/8/10/12 and the tuned
+12/16/24/32 (distance classes <4 KiB, <64 KiB, <1 MiB, >=1 MiB) -- and decoded
+from device-resident archives into a device buffer.  A step is one full
+decode of one archive; `value` is the tuned archive's output GB/s (10^9
+output bytes per second), the base archive is timed the same way and both
+ratios are reported.  Also: `--workload sweep` runs the match-length sweep
+(256 MiB generated streams, mean match length 32..1024).
+
+Prints one JSON line (rank 0).  Single GPU only.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def header_counts(arc):
+    h = np.frombuffer(arc[:128].tobytes(), dtype=np.uint64)
+    return {"n_tok": int(h[4]), "n_x16": int(h[5]), "n_x32": int(h[6]), "n_lit": int(h[7])}
+
+
+def algorithmic_bytes(arc, info):
+    """Bytes the method must move per decode: every output byte written once,
+    every match byte and literal byte read once, every token header, length
+    extension and source offset read once, plus the block table."""
+    c = header_counts(arc)
+    src_w = 5 if info["n"] > 0xFFFFFFFF else 4
+    tok_bytes = c["n_tok"] * (1 + src_w) + 2 * c["n_x16"] + 4 * c["n_x32"] + 32 * (info["n_blocks"] + 1)
+    return info["n"] + info["match_bytes"] + c["n_lit"] + tok_bytes, tok_bytes
+
+
+def time_decode(torch, da, out, G, U, sched, warmup, steps):
+    for _ in range(warmup):
+        da.decode_async(out, G=G, unroll=U, schedule=sched)
+    da.check()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        da.decode_async(out, G=G, unroll=U, schedule=sched)
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    da.check()
+    ms = [a.elapsed_time(b) for a, b in ev]
+    return float(np.mean(ms)), float(np.median(ms)), wall
+
+
+def cpu_oracle_time(arc, n):
+    import oracle
+    t0 = time.perf_counter()
+    out = oracle.decode(arc)
+    dt = time.perf_counter() - t0
+    return dt, out
+
+
+def run_fastq(args, torch, lz):
+    import synth
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    x = synth.fastq(args.size, seed=3)
+    n = int(x.size)
+    log = {"gen_s": round(time.perf_counter() - t0, 2)}
+    res = {}
+    for name, thr in (("base", lz.BASE_THR), ("tuned", lz.TUNED_THR)):
+        t0 = time.perf_counter()
+        arc = lz.encode(x, args.log2_bs, thr, lz.BOUNDS_CFG, max_chain=args.max_chain)
+        enc_s = time.perf_counter() - t0
+        info = lz.archive_info(arc)
+        ent, _ = lz.entropy_size(arc)
+        t0 = time.perf_counter()
+        da = lz.DeviceArchive(arc, device=dev)
+        open_s = time.perf_counter() - t0
+        out = torch.empty(n, dtype=torch.uint8, device=dev)
+        mean_ms, med_ms, wall = time_decode(torch, da, out, args.G, args.unroll, args.schedule, args.warmup,
+                                            args.steps)
+        # bit-exact check outside the timer: device compare with the input
+        ok = bool(torch.equal(out, torch.from_numpy(x).to(dev)))
+        if not ok:
+            raise SystemExit(f"{name}: GPU decode differs from the input")
+        alg, tok_bytes = algorithmic_bytes(arc, info)
+        res[name] = {
+            "arc": arc, "info": info, "mean_ms": mean_ms, "median_ms": med_ms, "wall_s": wall,
+            "gbps": n / (mean_ms * 1e-3) / 1e9, "alg_bytes": alg, "tok_bytes": tok_bytes,
+            "ratio_raw": n / arc.size, "ratio_entropy": n / ent, "enc_s": enc_s, "open_s": open_s,
+            "levels": da.levels,
+        }
+        da.close()
+        del out
+        torch.cuda.empty_cache()
+    t = res["tuned"]
+    b = res["base"]
+    achieved = t["alg_bytes"] / (t["mean_ms"] * 1e-3) / 1e9
+    line = {
+        "metric": "match-phase decode GB/s (device-resident) + ratio, 6/8/10/12 vs 12/16/24/32",
+        "value": round(t["gbps"], 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t["mean_ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": "FASTQ-like reads %d B, 64 KiB blocks, G=%d, 12/16/24/32 (value) vs 6/8/10/12"
+                        % (n, args.G),
+            "n_bytes": n, "log2_bs": args.log2_bs, "G": args.G, "unroll": args.unroll,
+            "schedule": args.schedule, "bounds": list(lz.BOUNDS_CFG), "max_chain": args.max_chain,
+        },
+        "detail": {
+            "tuned_gbps": round(t["gbps"], 3), "base_gbps": round(b["gbps"], 3),
+            "tuned_ratio_raw": round(t["ratio_raw"], 4), "base_ratio_raw": round(b["ratio_raw"], 4),
+            "tuned_ratio_entropy": round(t["ratio_entropy"], 4), "base_ratio_entropy": round(b["ratio_entropy"], 4),
+            "tuned_mean_match": round(t["info"]["mean_match"], 2), "base_mean_match": round(b["info"]["mean_match"], 2),
+            "tuned_coverage": round(t["info"]["coverage"], 4), "base_coverage": round(b["info"]["coverage"], 4),
+            "tuned_levels": t["levels"], "base_levels": b["levels"],
+            "base_ms": round(b["mean_ms"], 4), "encode_s": [round(b["enc_s"], 2), round(t["enc_s"], 2)],
+            "bit_exact": True, **log,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "alg_bytes_per_launch": t["alg_bytes"],
+        },
+    }
+    if not args.no_cpu:
+        dt, out = cpu_oracle_time(t["arc"], n)
+        assert np.array_equal(out, x)
+        line["cpu_baseline"] = {"value": round(n / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                                "sample": "whole tuned archive (%d output bytes), one sequential decode incl. "
+                                          "validation" % n}
+    return line
+
+
+def run_sweep(args, torch, lz):
+    """Granularity sweep: generated 256 MiB streams with mean match length m."""
+    import synth
+    dev = torch.device("cuda:0")
+    n = args.size
+    rows = []
+    for i, m in enumerate((32, 64, 128, 256, 512, 1024)):
+        ll, ml, sr, lit = synth.geo_tokens(n, m, seed=2 + i)
+        for lb in (14, 16, 18, 20):
+            arc = lz.build_archive(n, lb, ll, ml, sr, lit)
+            info = lz.archive_info(arc)
+            da = lz.DeviceArchive(arc, device=dev)
+            out = torch.empty(n, dtype=torch.uint8, device=dev)
+            for G in (8, 16, 32, 64):
+                mean_ms, med_ms, wall = time_decode(torch, da, out, G, args.unroll, args.schedule, 2, args.steps)
+                alg, _ = algorithmic_bytes(arc, info)
+                rows.append({"m": m, "log2_bs": lb, "G": G, "lanes": G * info["n_blocks"],
+                             "gbps": round(n / mean_ms / 1e6, 2),
+                             "alg_gbps": round(alg / mean_ms / 1e6, 2), "levels": da.levels,
+                             "realized_m": round(info["mean_match"], 1)})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            da.close()
+    best = max(r["gbps"] for r in rows if r["m"] >= 256)
+    return {"metric": "match-phase decode GB/s vs mean match length", "value": best, "unit": "GB/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": 2, "ms_per_step": None, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "match-length sweep, %d B streams" % n}, "rows": rows}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fastq", choices=["fastq", "sweep"])
+    ap.add_argument("--size", type=int, default=1 << 30)
+    ap.add_argument("--log2-bs", dest="log2_bs", type=int, default=16)
+    ap.add_argument("--G", type=int, default=32)
+    ap.add_argument("--unroll", type=int, default=2)
+    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--max-chain", dest="max_chain", type=int, default=32)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only; multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2607_18541_amd import lz
+    if not torch.cuda.is_available():
+        print("no GPU", file=sys.stderr)
+        sys.exit(1)
+    lz.lib()
+    if args.workload == "sweep":
+        if args.size == 1 << 30:
+            args.size = 1 << 28
+        line = run_sweep(args, torch, lz)
+    else:
+        line = run_fastq(args, torch, lz)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * lz.h -- C ABI of liblz: absolute-offset LZ77 with a gfx950 match-phase decoder.
+ *
+ * The method (arxiv 2607.18541): an LZ77 stream whose every back-reference
+ * names an ABSOLUTE output position (Abstract; Sec. 1 "Positioning"), cut into
+ * LZ blocks of an encode-time size (Sec. 2; Sec. 5, last paragraph), decoded
+ * on the GPU by groups of G cooperating lanes per block (Sec. 2, Sec. 3.1:
+ * lanes = G x N_blocks), with a per-distance-class minimum match length chosen
+ * at encode time (Sec. 4.2, e.g. 6/8/10/12 or 12/16/24/32).
+ *
+ * Conventions for every entry point:
+ *  - Return 0 on success or a negative LZ_E_* code; lz_last_error() gives a
+ *    thread-local message.  Nothing throws across the ABI.
+ *  - Host buffers written by the library (archives) are allocated here and
+ *    released with lz_free.  Device memory is always the caller's: pass raw
+ *    device pointers and sizes; the library never allocates device memory on
+ *    the decode path.
+ *  - `stream` is a hipStream_t passed as void*; device work is enqueued on it
+ *    asynchronously and the caller synchronises.
+ *  - Decoders never read outside the archive or write outside
+ *    [d_out, d_out + out_cap): every archive is fully validated on the host by
+ *    lz_device_open before any kernel sees it.
+ *
+ * Container format, version 1 (integers little-endian).  The paper gives no
+ * byte layout; this is the layout of this library.
+ *   header [0,128): u32 magic 0x314D5A4C ("LZM1"), u32 version 1, u64 n
+ *     (decoded bytes), u32 log2_bs (4..24), u32 n_blocks = ceil(n/bs),
+ *     u32 min_match (>=1, base of match-length codes), u32 flags (bit0: src_hi
+ *     plane present, bit1: per-block info bytes present), u64 n_tok, u64 n_x16,
+ *     u64 n_x32, u64 n_lit, u8 thr[4], u32 reserved, u64 bound[3], zeros.
+ *   block table at 128: n_blocks+1 entries {u64 tok, u64 lit, u64 x16, u64 x32}
+ *     of cumulative stream starts (entry 0 zero, last entry the totals).
+ *   streams, each 16-byte aligned, in order: cmd u8[n_tok], x16 u16[n_x16],
+ *     x32 u32[n_x32], src_lo u32[n_tok], src_hi u8[n_tok] (flag bit0),
+ *     lit u8[n_lit], info u8[n_blocks] (flag bit1), 16 zero bytes; the size is
+ *     a multiple of 16.
+ *   token t of block b (covering [b*bs, min(n,(b+1)*bs))): c = cmd[t];
+ *     literal code c>>4, match code c&15; code 15 is extended: v = next x16,
+ *     if v == 0xFFFF then v = 0xFFFF + next x32; value = 15 + v (literal
+ *     extension read first).  The block's last token has match code 0 and
+ *     match length = block end - (token start + literal length); other tokens
+ *     have match length min_match + match value.  The match source is
+ *     src_lo[t] | src_hi[t]<<32 and must be below the match start; overlap
+ *     (source + length past the start) repeats the period start-source.
+ */
+#ifndef LZ_H
+#define LZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LZ_OK 0
+#define LZ_E_INVAL (-1)   /* bad argument (sizes, capacities, parameters) */
+#define LZ_E_CORRUPT (-2) /* archive fails validation */
+#define LZ_E_RANGE (-3)   /* requested range outside [0, n) */
+#define LZ_E_NOMEM (-4)   /* host allocation failed or buffer too small */
+#define LZ_E_HIP (-5)     /* HIP runtime error */
+#define LZ_E_BUSY (-6)    /* a bounded device-side wait expired */
+
+/* Encoder parameters (Sec. 4.2): thresholds thr[c] apply to distance class
+ * c = 0 if d < bound[0], 1 if d < bound[1], 2 if d < bound[2], else 3, with
+ * d = destination - source. */
+typedef struct lz_params {
+  uint32_t log2_bs;    /* LZ block size 2^log2_bs bytes (Sec. 2), 4..24 */
+  uint32_t thr[4];     /* minimum match length per distance class, >= 1 */
+  uint64_t bound[3];   /* class bounds, increasing */
+  uint32_t max_chain;  /* candidates walked per hash chain; 0 = all (exact greedy) */
+  uint32_t n_threads;  /* encoder threads; 0 = hardware concurrency */
+  uint64_t segment;    /* 0 = whole-prefix window; else sources stay inside
+                          aligned segments of this many bytes (multiple of bs) */
+} lz_params;
+
+/* Fills the defaults: 64 KiB blocks, thresholds 6/8/10/12, bounds 4 KiB /
+ * 64 KiB / 1 MiB, max_chain 32, all threads, whole-prefix window. */
+int lz_params_default(lz_params* p);
+
+/* Greedy LZ77 parse of in[0,n) with per-class thresholds (Sec. 4.2) into a
+ * library-allocated archive (*arc, *arc_size); free with lz_free.  Host only,
+ * multithreaded over blocks; with max_chain = 0 the match lengths equal the
+ * exhaustive greedy parse. */
+int lz_encode(const uint8_t* in, uint64_t n, const lz_params* p, uint8_t** arc, uint64_t* arc_size);
+
+/* Same, but each block b is parsed with its own threshold tuple
+ * thr_per_block[4*b .. 4*b+3]; tuple_id[b] (may be NULL) is stored in the
+ * per-block info bytes.  Used by the learned threshold selector. */
+int lz_encode_blockwise(const uint8_t* in, uint64_t n, const lz_params* p, const uint32_t* thr_per_block,
+                        const uint8_t* tuple_id, uint8_t** arc, uint64_t* arc_size);
+
+/* Serialises a given token stream (token t: lit_len[t] literals taken in
+ * order from lit, then mlen[t] bytes copied from absolute position src[t])
+ * covering n bytes; tokens may straddle block ends and are cut there.
+ * min_match = 0 picks the smallest match length that needs a code. */
+int lz_build_archive(uint64_t n, uint32_t log2_bs, uint32_t min_match, uint64_t ntok, const uint32_t* lit_len,
+                     const uint32_t* mlen, const uint64_t* src, const uint8_t* lit, uint64_t nlit, uint8_t** arc,
+                     uint64_t* arc_size);
+
+void lz_free(void* p);
+
+typedef struct lz_info {
+  uint64_t n, n_blocks, n_tok, n_lit, n_match, match_bytes, archive_bytes;
+  uint32_t log2_bs, min_match;
+  uint32_t thr[4];
+  uint64_t bound[3];
+  double mean_match;     /* mean match length (Sec. 4.1) */
+  double frac_lt32;      /* fraction of matches shorter than 32 bytes */
+  double coverage;       /* fraction of output bytes produced by matches */
+  uint64_t src_bytes;    /* bytes of absolute offsets (src_lo + src_hi planes) */
+  uint64_t hist[4][16];  /* matches per distance class x length bin (bins:
+                            [4,6) [6,8) [8,10) [10,12) [12,16) [16,20) [20,24)
+                            [24,32) [32,48) [48,64) [64,128) [128,256)
+                            [256,1K) [1K,4K) [4K,16K) [16K,inf); <4 goes to bin 0) */
+} lz_info;
+
+/* Validates the archive and fills statistics (Sec. 4.1 match statistics). */
+int lz_archive_info(const uint8_t* arc, uint64_t arc_size, lz_info* out);
+
+/* Entropy-bound size (bytes): header and block table verbatim plus, for each
+ * stream (cmd, x16, x32, every byte plane of the sources, lit), the order-0
+ * entropy over 64 KiB tiles (the tile size of Sec. 2) plus 1 + 2 x (distinct
+ * symbols) per tile.  parts[7] (optional): cmd, x16, x32, src_lo planes, lit,
+ * header+table, src_hi plane. */
+int lz_entropy_size(const uint8_t* arc, uint64_t arc_size, double* total, double* parts);
+
+/* Dependency levels (schedule of a block-parallel decode; not in the paper):
+ * literals are level 0; a match's level is the maximum over its source bytes
+ * of the writing token's level, plus one if that token is in another block.
+ * levels (may be NULL) receives n_tok values; *max_level the maximum. */
+int lz_plan(const uint8_t* arc, uint64_t arc_size, uint32_t* levels, uint32_t* max_level);
+
+/* FNV-1a 64 (Sec. 2 integrity hash), seed = offset basis 0xcbf29ce484222325. */
+uint64_t lz_fnv1a64(const uint8_t* p, uint64_t n, uint64_t seed);
+
+const char* lz_last_error(void);
+
+/* ------------------------------------------------------------- device side */
+
+typedef struct lz_dev lz_dev; /* opaque handle of a device-resident archive */
+
+/* Decode configuration.  G lanes cooperate on one LZ block (Sec. 2, G in
+ * {8,16,32,64}); unroll = 16-byte chunks per lane per step (1, 2, 4);
+ * schedule 0 = one launch, blocks taken in order, a block's match waits on a
+ * per-block completion flag of each block it reads; schedule 1 = one launch
+ * per dependency level (lz_plan).  NULL config = G 32, unroll 2, schedule 0. */
+typedef struct lz_decode_cfg {
+  uint32_t G;
+  uint32_t unroll;
+  uint32_t schedule;
+  uint32_t wg_size; /* threads per workgroup: 64, 128, 256; 0 = 256 */
+} lz_decode_cfg;
+
+/* Device bytes lz_device_open needs for this archive: the archive itself,
+ * per-block flags, and (for schedule 1) the level plan. */
+int lz_device_bytes(const uint8_t* arc, uint64_t arc_size, uint64_t* bytes);
+
+/* Validates the archive on the host, copies it into the caller's device buffer
+ * d_buf (>= lz_device_bytes) on `stream`, and returns a handle.  The host
+ * archive may be freed after the stream has completed the copy. */
+int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t d_cap, void* stream, lz_dev** h);
+
+/* Decodes the whole archive into d_out[0, n) (Sec. 2: match phase, device
+ * resident).  Asynchronous on `stream`.  out_cap < n gives LZ_E_INVAL. */
+int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cfg* cfg, void* stream);
+
+/* Synchronises `stream` and reports a device-side failure of the last decode
+ * on this handle (LZ_E_BUSY if a bounded wait expired), else 0. */
+int lz_device_check(lz_dev* h, void* stream);
+
+uint64_t lz_device_n(const lz_dev* h);
+uint32_t lz_device_levels(const lz_dev* h); /* number of levels (schedule 1) */
+void lz_device_close(lz_dev* h);
+
+/* Pure-copy mode (Sec. 3.3, first control): executes pre-decoded tokens on the
+ * device.  Token t (SoA, device arrays): copy lit_len[t] bytes from
+ * d_lit[lit_off[t]..] to d_out[dst[t]..], then mlen[t] bytes from
+ * d_ref[src[t]..] to d_out[dst[t]+lit_len[t]..].  Tokens must write disjoint
+ * ranges; units: tokens [unit_start[u], unit_start[u+1]) go to one group of G
+ * lanes.  Every index must lie inside the buffers (the caller checks; the
+ * Python binding does). */
+int lz_purecopy_device(uint64_t ntok, const uint64_t* d_dst, const uint64_t* d_lit_off, const uint32_t* d_lit_len,
+                       const uint64_t* d_src, const uint32_t* d_mlen, uint64_t nunits, const uint64_t* d_unit_start,
+                       const uint8_t* d_lit, uint64_t lit_size, const uint8_t* d_ref, uint64_t ref_size,
+                       uint8_t* d_out, uint64_t out_size, const lz_decode_cfg* cfg, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

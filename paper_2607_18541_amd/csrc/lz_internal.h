@@ -1,0 +1,125 @@
+// lz_internal.h -- shared host-side structures of liblz (not part of the ABI).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lz.h"
+
+namespace lz {
+
+constexpr uint32_t kMagic = 0x314D5A4Cu;
+constexpr uint64_t kHeader = 128;
+
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+
+inline uint64_t align16(uint64_t v) { return (v + 15) & ~uint64_t(15); }
+
+// Parsed header + stream offsets of a container (version 1).
+struct ArcView {
+  const uint8_t* base = nullptr;
+  uint64_t size = 0;
+  uint64_t n = 0, bs = 0, nb = 0, min_match = 0, flags = 0;
+  uint64_t n_tok = 0, n_x16 = 0, n_x32 = 0, n_lit = 0;
+  uint32_t log2_bs = 0;
+  uint32_t thr[4] = {0, 0, 0, 0};
+  uint64_t bound[3] = {0, 0, 0};
+  uint64_t off_tab = 0, off_cmd = 0, off_x16 = 0, off_x32 = 0, off_slo = 0, off_shi = 0, off_lit = 0,
+           off_info = 0, total = 0;
+  // block table entry b: {tok, lit, x16, x32}
+  const uint64_t* tab() const { return reinterpret_cast<const uint64_t*>(base + off_tab); }
+};
+
+// Header and table checks only.
+int view_archive(const uint8_t* arc, uint64_t size, ArcView* v);
+
+// A decoded token, block-local order.
+struct Tok {
+  uint64_t dst;      // token start (absolute)
+  uint64_t lit_len;
+  uint64_t lit_off;  // offset in the lit stream
+  uint64_t mlen;
+  uint64_t src;
+};
+
+// Walks block b's tokens, validating every container rule; calls f(tok_index,
+// Tok) for each.  Returns 0 or LZ_E_CORRUPT.
+template <class F>
+int walk_block(const ArcView& v, uint64_t b, F&& f);
+
+// Full validation (all blocks, multithreaded).
+int validate_archive(const ArcView& v, uint32_t n_threads);
+
+// Per-token levels (see lz_plan); returns max level.
+int compute_levels(const ArcView& v, uint32_t* levels, uint32_t* max_level);
+
+unsigned hw_threads(uint32_t requested);
+
+}  // namespace lz
+
+// ---------------------------------------------------------------- inline impl
+namespace lz {
+
+static inline uint64_t rd_le(const uint8_t* p, int k) {
+  uint64_t v = 0;
+  for (int i = 0; i < k; ++i) v |= uint64_t(p[i]) << (8 * i);
+  return v;
+}
+
+template <class F>
+int walk_block(const ArcView& v, uint64_t b, F&& f) {
+  const uint64_t* T = v.tab();
+  uint64_t t0 = T[4 * b + 0], t1 = T[4 * b + 4];
+  uint64_t lc = T[4 * b + 1], lc1 = T[4 * b + 5];
+  uint64_t xc = T[4 * b + 2], xc1 = T[4 * b + 6];
+  uint64_t yc = T[4 * b + 3], yc1 = T[4 * b + 7];
+  uint64_t pos = b * v.bs;
+  uint64_t end = pos + v.bs < v.n ? pos + v.bs : v.n;
+  if (t1 <= t0) return LZ_E_CORRUPT;
+  const uint8_t* cmd = v.base + v.off_cmd;
+  const uint8_t* x16 = v.base + v.off_x16;
+  const uint8_t* x32 = v.base + v.off_x32;
+  const uint8_t* slo = v.base + v.off_slo;
+  const uint8_t* shi = (v.flags & 1) ? v.base + v.off_shi : nullptr;
+  for (uint64_t t = t0; t < t1; ++t) {
+    uint8_t c = cmd[t];
+    uint64_t val[2] = {uint64_t(c >> 4), uint64_t(c & 15)};
+    bool last = (t + 1 == t1);
+    for (int k = 0; k < 2; ++k) {
+      if (val[k] != 15 || (k == 1 && last)) continue;
+      if (xc >= xc1) return LZ_E_CORRUPT;
+      uint64_t e = rd_le(x16 + 2 * xc, 2);
+      ++xc;
+      if (e == 0xFFFF) {
+        if (yc >= yc1) return LZ_E_CORRUPT;
+        e += rd_le(x32 + 4 * yc, 4);
+        ++yc;
+      }
+      val[k] = 15 + e;
+    }
+    uint64_t lit_len = val[0];
+    if (lit_len > end - pos || lit_len > lc1 - lc) return LZ_E_CORRUPT;
+    uint64_t mstart = pos + lit_len;
+    uint64_t mlen;
+    if (last) {
+      if ((c & 15) != 0) return LZ_E_CORRUPT;
+      mlen = end - mstart;
+    } else {
+      mlen = v.min_match + val[1];
+      if (mlen > end - mstart) return LZ_E_CORRUPT;
+    }
+    uint64_t src = rd_le(slo + 4 * t, 4);
+    if (shi) src |= uint64_t(shi[t]) << 32;
+    if (mlen > 0 && src >= mstart) return LZ_E_CORRUPT;
+    if (mlen == 0 && src != 0) return LZ_E_CORRUPT;
+    f(t, Tok{pos, lit_len, lc, mlen, src});
+    lc += lit_len;
+    pos = mstart + mlen;
+  }
+  if (pos != end || lc != lc1 || xc != xc1 || yc != yc1) return LZ_E_CORRUPT;
+  return 0;
+}
+
+}  // namespace lz

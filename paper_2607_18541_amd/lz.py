@@ -1,0 +1,290 @@
+"""ctypes binding of liblz (include/lz.h): argument marshalling only.
+
+Every step of encode, plan and decode runs in the native library; device
+memory comes from torch tensors (``.data_ptr()``) and streams from
+``torch.cuda.current_stream().cuda_stream``.  If ``liblz.so`` is missing this
+module raises on first use -- there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblz.so")
+_LIB = None
+
+LZ_OK, LZ_E_INVAL, LZ_E_CORRUPT, LZ_E_RANGE, LZ_E_NOMEM, LZ_E_HIP, LZ_E_BUSY = 0, -1, -2, -3, -4, -5, -6
+
+BOUNDS_CFG = (4096, 65536, 1 << 20)
+BASE_THR = (6, 8, 10, 12)
+TUNED_THR = (12, 16, 24, 32)
+
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_p64 = ctypes.POINTER(ctypes.c_uint64)
+
+
+class LzError(RuntimeError):
+    def __init__(self, rc, what):
+        msg = lib().lz_last_error().decode(errors="replace")
+        super().__init__(f"{what} failed ({rc}): {msg}")
+        self.rc = rc
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("log2_bs", _u32), ("thr", _u32 * 4), ("bound", _u64 * 3), ("max_chain", _u32),
+                ("n_threads", _u32), ("segment", _u64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", _u64), ("n_blocks", _u64), ("n_tok", _u64), ("n_lit", _u64), ("n_match", _u64),
+                ("match_bytes", _u64), ("archive_bytes", _u64), ("log2_bs", _u32), ("min_match", _u32),
+                ("thr", _u32 * 4), ("bound", _u64 * 3), ("mean_match", ctypes.c_double),
+                ("frac_lt32", ctypes.c_double), ("coverage", ctypes.c_double), ("src_bytes", _u64),
+                ("hist", (_u64 * 16) * 4)]
+
+
+class DecodeCfg(ctypes.Structure):
+    _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("wg_size", _u32)]
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "lz_params_default": (ctypes.c_int, [ctypes.POINTER(Params)]),
+            "lz_encode": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(Params), ctypes.POINTER(_vp), _p64]),
+            "lz_encode_blockwise": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(Params), _vp, _vp,
+                                                   ctypes.POINTER(_vp), _p64]),
+            "lz_build_archive": (ctypes.c_int, [_u64, _u32, _u32, _u64, _vp, _vp, _vp, _vp, _u64,
+                                                ctypes.POINTER(_vp), _p64]),
+            "lz_free": (None, [_vp]),
+            "lz_archive_info": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(Info)]),
+            "lz_entropy_size": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(ctypes.c_double), _vp]),
+            "lz_plan": (ctypes.c_int, [_vp, _u64, _vp, ctypes.POINTER(_u32)]),
+            "lz_fnv1a64": (_u64, [_vp, _u64, _u64]),
+            "lz_last_error": (ctypes.c_char_p, []),
+            "lz_device_bytes": (ctypes.c_int, [_vp, _u64, _p64]),
+            "lz_device_open": (ctypes.c_int, [_vp, _u64, _vp, _u64, _vp, ctypes.POINTER(_vp)]),
+            "lz_decode_device": (ctypes.c_int, [_vp, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
+            "lz_device_check": (ctypes.c_int, [_vp, _vp]),
+            "lz_device_n": (_u64, [_vp]),
+            "lz_device_levels": (_u32, [_vp]),
+            "lz_device_close": (None, [_vp]),
+            "lz_purecopy_device": (ctypes.c_int, [_u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp,
+                                                  _u64, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _u8(a):
+    if isinstance(a, (bytes, bytearray, memoryview)):
+        return np.frombuffer(bytes(a), dtype=np.uint8)
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def _take_archive(pa, size):
+    try:
+        return np.ctypeslib.as_array(ctypes.cast(pa, ctypes.POINTER(ctypes.c_uint8)), (size,)).copy()
+    finally:
+        lib().lz_free(pa)
+
+
+def params(log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0):
+    p = Params()
+    lib().lz_params_default(ctypes.byref(p))
+    p.log2_bs = log2_bs
+    for k in range(4):
+        p.thr[k] = int(thr[k])
+    for k in range(3):
+        p.bound[k] = int(bounds[k])
+    p.max_chain = max_chain
+    p.n_threads = n_threads
+    p.segment = segment
+    return p
+
+
+def encode(x, log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0):
+    """Greedy parse with per-distance-class thresholds into a container."""
+    x = _u8(x)
+    p = params(log2_bs, thr, bounds, max_chain, n_threads, segment)
+    pa = _vp()
+    sz = _u64()
+    rc = lib().lz_encode(x.ctypes.data, x.size, ctypes.byref(p), ctypes.byref(pa), ctypes.byref(sz))
+    if rc:
+        raise LzError(rc, "lz_encode")
+    return _take_archive(pa, sz.value)
+
+
+def encode_blockwise(x, thr_per_block, tuple_id=None, log2_bs=16, bounds=BOUNDS_CFG, max_chain=32, n_threads=0):
+    x = _u8(x)
+    tb = np.ascontiguousarray(thr_per_block, dtype=np.uint32).reshape(-1)
+    tid = None if tuple_id is None else np.ascontiguousarray(tuple_id, dtype=np.uint8)
+    p = params(log2_bs, (1, 1, 1, 1), bounds, max_chain, n_threads)
+    pa = _vp()
+    sz = _u64()
+    rc = lib().lz_encode_blockwise(x.ctypes.data, x.size, ctypes.byref(p), tb.ctypes.data,
+                                   None if tid is None else tid.ctypes.data, ctypes.byref(pa), ctypes.byref(sz))
+    if rc:
+        raise LzError(rc, "lz_encode_blockwise")
+    return _take_archive(pa, sz.value)
+
+
+def build_archive(n, log2_bs, lit_len, mlen, src, lit, min_match=0):
+    ll = np.ascontiguousarray(lit_len, dtype=np.uint32)
+    ml = np.ascontiguousarray(mlen, dtype=np.uint32)
+    sr = np.ascontiguousarray(src, dtype=np.uint64)
+    lt = _u8(lit)
+    pa = _vp()
+    sz = _u64()
+    rc = lib().lz_build_archive(n, log2_bs, min_match, ll.size, ll.ctypes.data, ml.ctypes.data, sr.ctypes.data,
+                                lt.ctypes.data, lt.size, ctypes.byref(pa), ctypes.byref(sz))
+    if rc:
+        raise LzError(rc, "lz_build_archive")
+    return _take_archive(pa, sz.value)
+
+
+def archive_info(arc):
+    a = _u8(arc)
+    inf = Info()
+    rc = lib().lz_archive_info(a.ctypes.data, a.size, ctypes.byref(inf))
+    if rc:
+        raise LzError(rc, "lz_archive_info")
+    d = {k: getattr(inf, k) for k, _ in Info._fields_ if k not in ("thr", "bound", "hist")}
+    d["thr"] = tuple(inf.thr)
+    d["bound"] = tuple(inf.bound)
+    d["hist"] = np.array([[inf.hist[a][b] for b in range(16)] for a in range(4)], dtype=np.uint64)
+    return d
+
+
+def entropy_size(arc):
+    a = _u8(arc)
+    tot = ctypes.c_double()
+    parts = np.zeros(7, dtype=np.float64)
+    rc = lib().lz_entropy_size(a.ctypes.data, a.size, ctypes.byref(tot), parts.ctypes.data)
+    if rc:
+        raise LzError(rc, "lz_entropy_size")
+    return float(tot.value), parts
+
+
+def plan(arc):
+    a = _u8(arc)
+    inf = archive_info(a)
+    lv = np.zeros(max(inf["n_tok"], 1), dtype=np.uint32)
+    mx = _u32()
+    rc = lib().lz_plan(a.ctypes.data, a.size, lv.ctypes.data, ctypes.byref(mx))
+    if rc:
+        raise LzError(rc, "lz_plan")
+    return lv[:inf["n_tok"]], int(mx.value)
+
+
+def fnv1a64(data, seed=0xcbf29ce484222325):
+    a = _u8(data)
+    return int(lib().lz_fnv1a64(a.ctypes.data, a.size, seed))
+
+
+def _cfg(G=32, unroll=2, schedule=0):
+    c = DecodeCfg()
+    c.G, c.unroll, c.schedule, c.wg_size = G, unroll, schedule, 0
+    return c
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class DeviceArchive:
+    """A validated archive resident in device memory (torch-owned buffer)."""
+
+    def __init__(self, arc, device="cuda", stream=None):
+        import torch
+        self.arc = _u8(arc)
+        nb = _u64()
+        rc = lib().lz_device_bytes(self.arc.ctypes.data, self.arc.size, ctypes.byref(nb))
+        if rc:
+            raise LzError(rc, "lz_device_bytes")
+        self.buf = torch.empty(nb.value, dtype=torch.uint8, device=device)
+        h = _vp()
+        rc = lib().lz_device_open(self.arc.ctypes.data, self.arc.size, ctypes.c_void_p(self.buf.data_ptr()),
+                                  nb.value, _stream(stream), ctypes.byref(h))
+        if rc:
+            raise LzError(rc, "lz_device_open")
+        self.h = h
+        self.n = int(lib().lz_device_n(h))
+        self.levels = int(lib().lz_device_levels(h))
+        self.device_bytes = nb.value
+
+    def decode(self, out=None, G=32, unroll=2, schedule=0, stream=None, check=True):
+        import torch
+        if out is None:
+            out = torch.empty(max(self.n, 1), dtype=torch.uint8, device=self.buf.device)
+        c = _cfg(G, unroll, schedule)
+        rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
+                                    _stream(stream))
+        if rc:
+            raise LzError(rc, "lz_decode_device")
+        if check:
+            self.check(stream)
+        return out[:self.n]
+
+    def decode_async(self, out, G=32, unroll=2, schedule=0, stream=None):
+        c = _cfg(G, unroll, schedule)
+        rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
+                                    _stream(stream))
+        if rc:
+            raise LzError(rc, "lz_decode_device")
+
+    def check(self, stream=None):
+        rc = lib().lz_device_check(self.h, _stream(stream))
+        if rc:
+            raise LzError(rc, "lz_device_check")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lz_device_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def purecopy(dst, lit_off, lit_len, src, mlen, unit_start, lit, ref, out, G=32, unroll=2, stream=None):
+    """Runs pre-decoded tokens on the device (all arguments torch cuda tensors).
+    Bounds are checked here on the host copies before launch."""
+    import torch
+    T = dst.numel()
+    for t in (lit_off, lit_len, src, mlen):
+        assert t.numel() == T
+    if T:
+        ends = (dst.to(torch.int64) + lit_len.to(torch.int64) + mlen.to(torch.int64)).max().item()
+        lend = (lit_off.to(torch.int64) + lit_len.to(torch.int64)).max().item()
+        send = (src.to(torch.int64) + mlen.to(torch.int64)).max().item()
+        if ends > out.numel() or lend > lit.numel() or send > ref.numel():
+            raise ValueError("pre-decoded tokens index outside their buffers")
+        us = unit_start.to("cpu").to(torch.int64)
+        if us[0].item() != 0 or us[-1].item() != T or bool((us[1:] < us[:-1]).any()):
+            raise ValueError("unit starts must run from 0 to ntok")
+    c = _cfg(G, unroll, 0)
+    rc = lib().lz_purecopy_device(T, ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(lit_off.data_ptr()),
+                                  ctypes.c_void_p(lit_len.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                  ctypes.c_void_p(mlen.data_ptr()), unit_start.numel() - 1,
+                                  ctypes.c_void_p(unit_start.data_ptr()), ctypes.c_void_p(lit.data_ptr()),
+                                  lit.numel(), ctypes.c_void_p(ref.data_ptr()), ref.numel(),
+                                  ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c), _stream(stream))
+    if rc:
+        raise LzError(rc, "lz_purecopy_device")

@@ -1,0 +1,173 @@
+"""Host side of liblz against the oracle (CPU only): encoder, container writer,
+validation, statistics, planner, entropy bound, and that the C-ABI library
+loads and exports every symbol include/lz.h declares."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2607_18541_amd import lz
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    hdrs = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")]
+    names = set()
+    for h in hdrs:
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"\b(lz_[a-z0-9_]+)\s*\(", txt):
+            names.add(m.group(1))
+    assert len(names) >= 15
+    L = ctypes.CDLL(lz.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("thr", [(6, 8, 10, 12), (12, 16, 24, 32), (4, 6, 8, 10)])
+def test_exact_encoder_equals_oracle(thr):
+    """With whole hash chains the library parse is the exhaustive greedy
+    parse: the archive is byte-identical to the oracle's."""
+    x = synth.zipf_text(24000, seed=21)
+    bounds = (512, 4096, 16384)
+    a = lz.encode(x, 12, thr, bounds, max_chain=0)
+    ll, ml, sr, lit = oracle.encode(x, 12, thr, bounds)
+    b = oracle.write_archive(x.size, 12, ll, ml, sr, lit, min_match=min(thr), thr=thr, bounds=bounds)
+    assert np.array_equal(a, b)
+
+
+def test_exact_encoder_fastq_and_binary():
+    for x in (synth.fastq(30000, seed=7), synth.random_bytes(5000, 3),
+              np.zeros(7000, np.uint8), np.tile(np.arange(7, dtype=np.uint8), 900)):
+        for lb in (8, 12):
+            a = lz.encode(x, lb, (4, 5, 6, 7), (64, 1024, 4096), max_chain=0)
+            ll, ml, sr, lit = oracle.encode(x, lb, (4, 5, 6, 7), (64, 1024, 4096))
+            b = oracle.write_archive(x.size, lb, ll, ml, sr, lit, min_match=4, thr=(4, 5, 6, 7),
+                                     bounds=(64, 1024, 4096))
+            assert np.array_equal(a, b)
+
+
+def test_chain_limited_encoder_roundtrips_and_keeps_invariants():
+    x = synth.fastq(1 << 20, seed=3)
+    for thr in (lz.BASE_THR, lz.TUNED_THR):
+        arc = lz.encode(x, 16, thr, max_chain=16)
+        assert np.array_equal(oracle.decode(arc), x)
+        T = oracle.tokens(arc)
+        m = T["mlen"] > 0
+        ms = T["dst"] + T["lit_len"]
+        d = ms[m] - T["src"][m]
+        B = lz.BOUNDS_CFG
+        cls = np.where(d < B[0], 0, np.where(d < B[1], 1, np.where(d < B[2], 2, 3)))
+        assert np.all(T["mlen"][m] >= np.array(thr)[cls])
+
+
+def test_segmented_encoder():
+    x = synth.zipf_text(300_000, seed=5)
+    arc = lz.encode(x, 14, segment=1 << 16)
+    assert np.array_equal(oracle.decode(arc), x)
+    T = oracle.tokens(arc)
+    m = T["mlen"] > 0
+    ms = T["dst"] + T["lit_len"]
+    assert np.all(T["src"][m] // (1 << 16) == ms[m] // (1 << 16))
+
+
+def test_build_archive_equals_oracle_writer():
+    n = 1 << 21
+    ll, ml, sr, lit = synth.geo_tokens(n, 128, seed=2)
+    for lb in (12, 14, 16, 20):
+        a = lz.build_archive(n, lb, ll, ml, sr, lit)
+        b = oracle.write_archive(n, lb, ll, ml, sr, lit)
+        assert np.array_equal(a, b)
+
+
+def test_oracle_archives_validate_in_library():
+    x = synth.zipf_text(50000, seed=9)
+    ll, ml, sr, lit = oracle.encode(x[:8000], 10, (4, 4, 4, 4))
+    arc = oracle.write_archive(8000, 10, ll, ml, sr, lit)
+    inf = lz.archive_info(arc)
+    assert inf["n"] == 8000 and inf["n_tok"] == len(ll)
+
+
+def test_corrupt_archives_rejected():
+    x = synth.zipf_text(40000, seed=2)
+    arc = lz.encode(x, 12)
+    rng = np.random.default_rng(0)
+    with pytest.raises(lz.LzError):
+        lz.archive_info(arc[:100])
+    with pytest.raises(lz.LzError):
+        lz.archive_info(arc[:-32])
+    n_bad = 0
+    for trial in range(200):
+        b = arc.copy()
+        i = int(rng.integers(0, b.size))
+        b[i] ^= np.uint8(1 << int(rng.integers(0, 8)))
+        o = oracle.decode_rc(b)
+        try:
+            lz.archive_info(b)
+            lib_ok = True
+        except lz.LzError:
+            lib_ok = False
+        # both readers agree on validity; a flipped literal byte stays valid
+        assert lib_ok == (o == 0), (trial, i)
+        n_bad += (not lib_ok)
+    assert n_bad > 10
+
+
+def test_stats_match_oracle_tokens():
+    x = synth.fastq(500_000, seed=4)
+    arc = lz.encode(x, 16, lz.TUNED_THR)
+    inf = lz.archive_info(arc)
+    T = oracle.tokens(arc)
+    m = T["mlen"] > 0
+    assert inf["n_match"] == int(m.sum())
+    assert inf["match_bytes"] == int(T["mlen"].sum())
+    assert inf["mean_match"] == pytest.approx(T["mlen"][m].mean())
+    assert inf["frac_lt32"] == pytest.approx((T["mlen"][m] < 32).mean())
+    assert int(inf["hist"].sum()) == inf["n_match"]
+
+
+def test_plan_equals_oracle_levels():
+    x = synth.zipf_text(400_000, seed=6)
+    for lb in (12, 14):
+        arc = lz.encode(x, lb)
+        a, amx = lz.plan(arc)
+        b, bmx = oracle.levels(arc)
+        assert amx == bmx and np.array_equal(a, b)
+    n = 1 << 21
+    ll, ml, sr, lit = synth.geo_tokens(n, 64, seed=8)
+    arc = lz.build_archive(n, 14, ll, ml, sr, lit)
+    a, amx = lz.plan(arc)
+    b, bmx = oracle.levels(arc)
+    assert amx == bmx and np.array_equal(a, b)
+
+
+def test_entropy_equals_oracle():
+    for x in (synth.zipf_text(300_000, seed=1), synth.fastq(300_000, seed=2)):
+        arc = lz.encode(x, 16)
+        a, pa = lz.entropy_size(arc)
+        b, pb = oracle.entropy_size(arc)
+        assert a == pytest.approx(b, abs=8)
+        assert np.allclose(pa, pb, atol=2)
+
+
+def test_fnv_agrees_with_oracle():
+    for n in (0, 1, 7, 1000, 65537):
+        x = synth.random_bytes(n, n + 1)
+        assert lz.fnv1a64(x) == oracle.fnv1a64(x)
+
+
+def test_params_rejected():
+    x = synth.zipf_text(1000, seed=1)
+    with pytest.raises(lz.LzError):
+        lz.encode(x, 3)
+    with pytest.raises(lz.LzError):
+        lz.encode(x, 12, thr=(0, 1, 1, 1))
+    with pytest.raises(lz.LzError):
+        lz.encode(x, 12, bounds=(100, 50, 200))
+    with pytest.raises(lz.LzError):
+        lz.encode(x, 12, segment=1000)
