@@ -1,7 +1,7 @@
 """Match-phase decode throughput on one MI355X.
 
 Default workload: FASTQ-like reads, 1 GiB (whole records), 64 KiB LZ blocks,
-G = 32, encoded twice -- with the base thresholds 6/8/10/12 and the tuned
+G = 64, encoded twice -- with the base thresholds 6/8/10/12 and the tuned
 12/16/24/32 (distance classes <4 KiB, <64 KiB, <1 MiB, >=1 MiB) -- and decoded
 from device-resident archives into a device buffer.  A step is one full
 decode of one archive; `value` is the tuned archive's output GB/s (10^9
@@ -184,9 +184,9 @@ def main():
     ap.add_argument("--workload", default="fastq", choices=["fastq", "sweep"])
     ap.add_argument("--size", type=int, default=1 << 30)
     ap.add_argument("--log2-bs", dest="log2_bs", type=int, default=16)
-    ap.add_argument("--G", type=int, default=32)
+    ap.add_argument("--G", type=int, default=64)
     ap.add_argument("--unroll", type=int, default=2)
-    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=1)
     ap.add_argument("--max-chain", dest="max_chain", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()

@@ -139,16 +139,20 @@ const char* lz_last_error(void);
 
 typedef struct lz_dev lz_dev; /* opaque handle of a device-resident archive */
 
-/* Decode configuration.  G lanes cooperate on one LZ block (Sec. 2, G in
- * {8,16,32,64}); unroll = 16-byte chunks per lane per step (1, 2, 4);
- * schedule 0 = one launch, blocks taken in order, a block's match waits on a
- * per-block completion flag of each block it reads; schedule 1 = one launch
- * per dependency level (lz_plan).  NULL config = G 32, unroll 2, schedule 0. */
+/* Decode configuration.  A decode is a parse launch (one group of G lanes per
+ * 256-token segment of a block: token headers, literal runs, match table)
+ * followed by the matches grouped into (level, block) units by the plan of
+ * lz_plan.  G lanes cooperate on a unit (Sec. 2, G in {8,16,32,64}); unroll =
+ * 16-byte chunks per lane per step (1, 2, 4).  schedule 0 = all units in one
+ * launch, a unit starting once the blocks it reads have finished their lower
+ * levels (per-block flags); schedule 1 = one launch per dependency level.
+ * NULL config = G 64, unroll 2, schedule 1, unit_batch 1. */
 typedef struct lz_decode_cfg {
   uint32_t G;
   uint32_t unroll;
   uint32_t schedule;
-  uint32_t wg_size; /* threads per workgroup: 64, 128, 256; 0 = 256 */
+  uint32_t wg_size;    /* threads per workgroup: 0 or 256 */
+  uint32_t unit_batch; /* (level, block) units per work item, 1..G; 0 = 1 */
 } lz_decode_cfg;
 
 /* Device bytes lz_device_open needs for this archive: the archive itself,

@@ -1,48 +1,66 @@
 // lz_device.hip -- gfx950 match-phase decoder of absolute-offset LZ77.
 //
-// One LZ block is decoded by a group of G lanes of a 64-lane wave (Sec. 2:
-// cooperation width G; Sec. 3.1: lanes = G x N_blocks).  A group works through
-// its block in token order:
-//   1. parse: each lane reads one token header (cmd byte, length extensions,
-//      absolute source); group prefix sums give every token's output position
-//      and literal offset, so G tokens are parsed per step;
-//   2. batch: the group's pending segments (literal runs and match pieces) are
-//      cut into batches whose sources lie entirely before the batch's first
-//      output byte, so a batch has no read-after-write inside it; a match whose
-//      source overlaps its own output (period d = dst - src < length) runs as
-//      pieces of length d, 2d, 4d, ... each reading the already final prefix;
-//   3. copy: a batch's output is covered by 16-byte aligned output chunks,
-//      spread over the group's lanes (`unroll` chunks per lane per step).  A
-//      lane loads the 16 source bytes of its chunk with one unaligned 16-byte
-//      load and writes a full chunk with one aligned 16-byte store; the two
-//      chunks at each segment edge are written with exact byte/short/dword/
-//      qword stores so neighbouring segments never race on a byte.
-// Schedules.  Cross-block sources (absolute offsets reach the whole prefix)
-// need the source block final first.  Schedule 0: one launch; groups claim
-// blocks in increasing order from an atomic ticket, publish a per-block
-// completion flag with an agent-scope release, and wait (bounded) on the flags
-// of the blocks a batch reads.  Claims are in order, so the lowest unfinished
-// claimed block depends only on finished blocks and always progresses.
-// Schedule 1: one launch per dependency level, each group executing only the
-// level-p matches of its block (literals in pass 0); kernel boundaries order
-// the levels.  Mode 2 runs pre-decoded tokens whose sources are in a separate
+// Work is done by groups of G lanes of a 64-lane wave (Sec. 2: cooperation
+// width G; Sec. 3.1: lanes = G x N_blocks).  A decode is two launches:
+//
+//  parse  One group per LZ block walks the block's token stream: each lane
+//         reads one token header (cmd byte, length extensions, absolute
+//         source) and group prefix sums give every token's output position
+//         and literal offset, so G tokens are parsed per step.  The group
+//         copies all literal runs of the block and writes every match as a
+//         16-byte record {offset in block, length, source} into a match table
+//         laid out in plan order (below).
+//  match  The plan (computed on the host when the archive is opened) gives
+//         each match a dependency level: literals are level 0, a match takes
+//         the largest level among the writers of its source bytes, plus one
+//         for writers in another block.  Matches of one block at one level
+//         form a unit; units are ordered by (level, block).  Schedule 0 runs
+//         all units in one launch: groups take units in order from an atomic
+//         ticket; a unit of level p of block b starts once every block it
+//         reads (and b itself) has published done_level >= p, i.e. has
+//         finished all its units below p; finishing a unit publishes the
+//         block's next level.  Every unit waits only on units taken earlier,
+//         so the earliest unfinished unit can always run.  Output bytes in
+//         this launch are read and written with agent-scope (sc1) accesses,
+//         so publishing needs only the store acknowledgements, no L2 write-
+//         back.  Schedule 1 launches each level's units separately (kernel
+//         boundaries order the levels) with ordinary cached accesses.
+//
+// Copy engine (both launches): the group's pending segments (literal runs or
+// match pieces) are cut into batches whose sources lie entirely before the
+// batch's first output byte, so a batch has no read-after-write inside it; a
+// match whose source overlaps its own output (period d = dst - src < length)
+// runs as pieces of length d, 2d, 4d, ... each reading the already final
+// prefix.  A batch's output is covered by 16-byte aligned chunks spread over
+// the group's lanes (`unroll` chunks per lane per step): one unaligned 16-byte
+// load of the source window and one aligned 16-byte store per full chunk; the
+// chunks at segment edges are written with exact byte/short/dword/qword
+// stores so neighbouring segments never race on a byte.
+//
+// Mode 2 executes pre-decoded tokens whose match sources are in a separate
 // buffer (the pure-copy control of Sec. 3.3).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <vector>
 
 #include "lz_internal.h"
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 namespace {
 
-constexpr int kModeFlags = 0;
-constexpr int kModeLevels = 1;
-constexpr int kModePure = 2;
+constexpr int kModeFlow = 0;    // all units, one launch, done_level waits
+constexpr int kModeLevels = 1;  // the units of one level, no waits
+constexpr int kModePure = 2;    // pre-decoded tokens, sources in a reference buffer
+constexpr int kModeParse = 3;   // parse blocks, copy literals, fill the match table
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint64_t kSegTok = 256;  // tokens per parse segment
 
 constexpr uint64_t kIdleTicks = 500000000ull;  // 5 s of the 100 MHz clock without progress
 constexpr int kWG = 256;
@@ -63,14 +81,24 @@ struct KArgs {
   uint8_t* out;
   const uint8_t* msrc;  // base that match sources index (out, or ref in mode 2)
   uintptr_t msrc_lo, msrc_hi;
-  // schedule 0
-  uint32_t* flags;
-  uint32_t* ticket;
+  // parse segments: per segment {t_start, t_end, blk_t_end, pos, lit, x16, x32, blk}
+  const uint64_t* seg;
+  uint64_t nseg;
+  // plan and match table
+  const uint32_t* slot;       // per token: match-table index, or kNone
+  u32x4* mtab;                // per match: {offset in block, length, src lo, src hi}
+  const uint32_t* unit_blk;   // per unit: block
+  const uint32_t* unit_lvl;   // per unit: level
+  const uint32_t* unit_next;  // per unit: the block's next level with a unit, or kNone
+  const uint32_t* unit_tok;   // per unit: first match-table index (n_units + 1 entries)
+  const uint32_t* first_lvl;  // per block: lowest level with a unit, or kNone
+  uint32_t* done_lvl;         // per block, live during schedule 0
+  const uint32_t* lvl_start;  // first unit of each level (n_levels + 1 entries)
+  uint32_t* tickets;          // per level: units taken so far (schedule 0)
   uint32_t* err;
-  // schedule 1
-  const uint16_t* lvl;
-  const uint16_t* blk_maxlvl;
-  uint32_t pass;
+  uint32_t n_levels;
+  uint32_t unit_batch;        // units per work item (<= G)
+  uint64_t unit_lo, unit_hi;  // units this launch covers (schedule 1)
   // mode 2 (pre-decoded tokens)
   const uint64_t* p_dst;
   const uint64_t* p_lit_off;
@@ -183,27 +211,104 @@ __device__ __forceinline__ void store_chunk(uintptr_t a, const u32x4& v, int lo,
   }
 }
 
+// ---- coherent output path (schedule 0) -------------------------------------
+// Output bytes are read and written with agent-scope (sc1) buffer accesses: a
+// store is written through to the device-coherent level and a load is served
+// from it, so bytes published by a group on one XCD are read correctly by a
+// group on another without L2 write-back or invalidation.  Offsets are 32-bit
+// (outputs below 4 GiB); the buffer's size also bounds every access.
+constexpr int kSC1 = 16;  // cache-policy bit of buffer intrinsics: sc1
+
+__device__ __forceinline__ u32x4 coh_load_window(__amdgpu_buffer_rsrc_t r, int64_t w, uint32_t cap, int lo, int hi) {
+  u32x4 v;
+  if (w >= 0 && w + 16 <= (int64_t)cap) {
+    v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(uint32_t)w, 0, kSC1);
+  } else {
+    uint32_t d[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i >= lo && i < hi)
+        d[i >> 2] |= uint32_t(__builtin_amdgcn_raw_buffer_load_b8(r, (int)(uint32_t)(w + i), 0, kSC1))
+                     << (8 * (i & 3));
+    v = u32x4{d[0], d[1], d[2], d[3]};
+  }
+  return v;
+}
+
+__device__ __forceinline__ void coh_store_chunk(__amdgpu_buffer_rsrc_t r, uint32_t a, const u32x4& v, int lo, int hi) {
+  if (lo == 0 && hi == 16) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)a, 0, kSC1);
+    return;
+  }
+  int i = lo;
+  if ((i & 1) && i < hi) {
+    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(dword_at(v, i >> 2) >> (8 * (i & 3))), r, (int)(a + i), 0, kSC1);
+    i += 1;
+  }
+  if ((i & 2) && i + 2 <= hi) {
+    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(dword_at(v, i >> 2) >> (8 * (i & 3))), r, (int)(a + i), 0, kSC1);
+    i += 2;
+  }
+  if ((i & 4) && i + 4 <= hi) {
+    __builtin_amdgcn_raw_buffer_store_b32(dword_at(v, i >> 2), r, (int)(a + i), 0, kSC1);
+    i += 4;
+  }
+  if ((i & 8) && i + 8 <= hi) {
+    __builtin_amdgcn_raw_buffer_store_b64(u32x2{dword_at(v, i >> 2), dword_at(v, (i >> 2) + 1)}, r, (int)(a + i), 0, kSC1);
+    i += 8;
+  }
+  if (i + 8 <= hi) {
+    __builtin_amdgcn_raw_buffer_store_b64(u32x2{dword_at(v, i >> 2), dword_at(v, (i >> 2) + 1)}, r, (int)(a + i), 0, kSC1);
+    i += 8;
+  }
+  if (i + 4 <= hi) {
+    __builtin_amdgcn_raw_buffer_store_b32(dword_at(v, i >> 2), r, (int)(a + i), 0, kSC1);
+    i += 4;
+  }
+  if (i + 2 <= hi) {
+    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(dword_at(v, i >> 2) >> (8 * (i & 3))), r, (int)(a + i), 0, kSC1);
+    i += 2;
+  }
+  if (i + 1 <= hi)
+    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(dword_at(v, i >> 2) >> (8 * (i & 3))), r, (int)(a + i), 0, kSC1);
+}
+
+__device__ __forceinline__ void compiler_barrier() { asm volatile("" ::: "memory"); }
+
 __device__ __forceinline__ void lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
 template <int G, int U, int MODE>
 __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
   static_assert(G == 8 || G == 16 || G == 32 || G == 64, "G");
+  constexpr bool kCoh = (MODE == kModeFlow);
   __shared__ Desc s_desc[kWG];
   __shared__ uint32_t s_base[kWG];
 
   const int lane = threadIdx.x & 63;
-  const int gl = lane & (G - 1);     // lane in group
-  const int gw = lane / G;           // group in wave
+  const int gl = lane & (G - 1);       // lane in group
+  const int gw = lane / G;             // group in wave
   const int gslot = threadIdx.x - gl;  // first LDS slot of this group
   const uint64_t ngroups = (uint64_t)gridDim.x * (kWG / G);
   const uint64_t gid = (uint64_t)blockIdx.x * (kWG / G) + threadIdx.x / G;
   const uint64_t bs = 1ull << A.log2_bs;
+  const uintptr_t out_b = (uintptr_t)A.out;
+  const uint32_t out_cap32 = (uint32_t)min<uint64_t>(A.msrc_hi - A.msrc_lo, 0xFFFFFFFFull);
+  __amdgpu_buffer_rsrc_t out_r = __builtin_amdgcn_make_buffer_rsrc((void*)A.out, 0, (int)out_cap32, 0x00020000);
 
-  // group state (replicated on the group's lanes)
-  bool finished = false, have_blk = false;
-  uint64_t blk = 0, unit_iter = 0;
-  uint64_t t_next = 0, t_end = 0, pos = 0, bend = 0, litc = 0, xc = 0, yc = 0;
-  uint64_t wm = 0;  // blocks below wm are known complete (schedule 0)
+  // work item state (replicated on the group's lanes)
+  bool finished = false, have_item = false, started = false;
+  uint64_t item = 0, iter = 0;
+  uint64_t blk = 0;
+  uint32_t lvl = 0, cur_lvl = 0;
+  uint64_t ua = 0, nu = 0;                 // units [ua, ua + nu) of the item
+  uint64_t u_blk = 0;                      // lane j < nu: block of unit ua + j
+  uint32_t u_next = kNone;                 // lane j < nu: that block's next level
+  if (MODE == kModeParse) {
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < A.n_levels; i += (uint64_t)gridDim.x * kWG)
+      A.tickets[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *A.err = 0u;
+  }
+  uint64_t t_next = 0, t_end = 0, blk_t_end = 0, pos = 0, bend = 0, litc = 0, xc = 0, yc = 0;
   // this lane's buffered token
   uint64_t l_dst = 0, l_src = 0, m_dst = 0, m_src = 0;
   uint32_t l_len = 0, m_len = 0, m_done = 0;
@@ -212,57 +317,69 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
   uint64_t t_last = 0;
 
   for (;;) {
-    // ---------------------------------------------------- claim a block
-    if (!finished && !have_blk) {
-      if (MODE == kModeFlags) {
-        uint32_t b = 0;
-        if (gl == 0) b = atomicAdd(A.ticket, 1u);
-        b = __shfl(b, 0, G);
-        if (b >= A.nb) {
-          finished = true;
-        } else {
-          blk = b;
-          have_blk = true;
-        }
-      } else if (MODE == kModeLevels) {
-        // grid-stride over blocks that have work in this pass
+    // ---------------------------------------------------- take a work item
+    if (!finished && !have_item) {
+      if (MODE == kModeFlow) {
+        // units are taken level by level, so every unit waited on was taken earlier
         for (;;) {
-          uint64_t b = gid + unit_iter * ngroups;
-          if (b >= A.nb) {
+          if (cur_lvl >= A.n_levels) {
             finished = true;
             break;
           }
-          ++unit_iter;
-          if (A.blk_maxlvl[b] >= A.pass) {
-            blk = b;
-            have_blk = true;
+          const uint64_t l1 = A.lvl_start[cur_lvl + 1];
+          uint64_t u = 0;
+          if (gl == 0) u = A.lvl_start[cur_lvl] + atomicAdd(A.tickets + cur_lvl, A.unit_batch);
+          u = __shfl(u, 0, G);
+          if (u < l1) {
+            ua = u;
+            nu = min(l1 - u, (uint64_t)A.unit_batch);
+            lvl = cur_lvl;
+            have_item = true;
             break;
           }
+          ++cur_lvl;
         }
-      } else {
-        uint64_t u = gid + unit_iter * ngroups;
-        ++unit_iter;
-        if (u >= A.nunits) {
+      } else if (MODE == kModeLevels) {
+        const uint64_t u = A.unit_lo + (gid + iter * ngroups) * A.unit_batch;
+        ++iter;
+        if (u >= A.unit_hi) {
           finished = true;
         } else {
-          blk = u;
-          have_blk = true;
+          ua = u;
+          nu = min(A.unit_hi - u, (uint64_t)A.unit_batch);
+          have_item = true;
         }
+      } else {
+        const uint64_t count = (MODE == kModeParse) ? A.nseg : A.nunits;
+        const uint64_t k = gid + iter * ngroups;
+        ++iter;
+        if (k >= count) finished = true;
+        else { item = k; have_item = true; }
       }
-      if (have_blk) {
-        if (MODE == kModePure) {
-          t_next = A.p_unit[blk];
-          t_end = A.p_unit[blk + 1];
-        } else {
-          const uint64_t* e = A.tab + 4 * blk;
+      if (have_item) {
+        if (MODE == kModeParse) {
+          const uint64_t* e = A.seg + 8 * item;
           t_next = e[0];
-          t_end = e[4];
-          litc = e[1];
-          xc = e[2];
-          yc = e[3];
-          pos = blk * bs;
-          bend = min(A.n, pos + bs);
+          t_end = e[1];
+          blk_t_end = e[2];
+          pos = e[3];
+          litc = e[4];
+          xc = e[5];
+          yc = e[6];
+          blk = e[7];
+          bend = min(A.n, (blk + 1) * bs);
+          if (gl == 0 && pos == blk * bs) A.done_lvl[blk] = A.first_lvl[blk];
+        } else if (MODE == kModePure) {
+          t_next = A.p_unit[item];
+          t_end = A.p_unit[item + 1];
+        } else {
+          const bool has_u = (uint64_t)gl < nu;
+          u_blk = has_u ? A.unit_blk[ua + gl] : 0;
+          u_next = has_u ? A.unit_next[ua + gl] : kNone;
+          t_next = A.unit_tok[ua];
+          t_end = A.unit_tok[ua + nu];
         }
+        started = (MODE != kModeFlow);
         l_len = m_len = m_done = 0;
         l_pend = false;
       }
@@ -270,22 +387,35 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
     if (__all(finished)) break;
 
     bool progressed = false;
-    if (have_blk) {
-      // ------------------------------------------------ anything pending?
+    if (have_item) {
       const uint32_t m_rem = m_len - m_done;
       const bool lane_pend = l_pend || (m_rem > 0);
       const uint64_t pend_bits = group_bits<G>(__ballot(lane_pend), gw);
       if (pend_bits == 0) {
-        if (t_next >= t_end) {
-          // ---------------------------------------------- block complete
-          if (MODE == kModeFlags) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            if (gl == 0) __hip_atomic_store(A.flags + blk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!started) {
+          // ---------------------------------------------- a unit waits for its own block's lower levels
+          bool ok = true;
+          if ((uint64_t)gl < nu)
+            ok = __hip_atomic_load(A.done_lvl + u_blk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= lvl;
+          if (group_bits<G>(__ballot(!ok), gw) == 0) {
+            started = true;
+            progressed = true;
+            compiler_barrier();
           }
-          have_blk = false;
+        } else if (t_next >= t_end) {
+          // ---------------------------------------------- item complete
+          if (MODE == kModeFlow) {
+            // every output store of this wave is acknowledged, then publish
+            compiler_barrier();
+            __builtin_amdgcn_s_waitcnt(0);
+            compiler_barrier();
+            if ((uint64_t)gl < nu)
+              __hip_atomic_store(A.done_lvl + u_blk, u_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          have_item = false;
           progressed = true;
         } else {
-          // ---------------------------------------------- parse G tokens
+          // ---------------------------------------------- next G tokens
           const uint64_t t = t_next + gl;
           const bool valid = t < t_end;
           if (MODE == kModePure) {
@@ -295,9 +425,9 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
             m_len = valid ? A.p_mlen[t] : 0u;
             m_src = valid ? A.p_src[t] : 0;
             m_dst = l_dst + l_len;
-          } else {
+          } else if (MODE == kModeParse) {
             const uint32_t c = valid ? A.cmd[t] : 0u;
-            const bool last = (t + 1 == t_end);
+            const bool last = (t + 1 == blk_t_end);
             const uint32_t Lc = c >> 4, Mc = c & 15u;
             const uint32_t need_l = (valid && Lc == 15u) ? 1u : 0u;
             const uint32_t need_m = (valid && !last && Mc == 15u) ? 1u : 0u;
@@ -324,17 +454,24 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
             yc += tot32;
             litc += lit_tot;
             pos += span_tot;
+            // record the match in plan order; only literal runs are copied here
+            if (valid && mlen > 0) {
+              const uint32_t sl = A.slot[t];
+              const uint64_t md = tdst + lit_len;
+              A.mtab[sl] = u32x4{(uint32_t)md, mlen, (uint32_t)src,
+                                 (uint32_t)((md >> 32) & 0xFFFFu) | (uint32_t)((src >> 32) << 16)};
+            }
             l_dst = tdst;
             l_len = lit_len;
             l_src = loff;
-            m_dst = tdst + lit_len;
-            m_len = mlen;
-            m_src = src;
-            if (MODE == kModeLevels) {
-              const uint32_t lv = valid ? A.lvl[t] : 0u;
-              if (A.pass != 0) l_len = 0;
-              if (lv != A.pass) m_len = 0;
-            }
+            m_len = 0;
+          } else {
+            // a unit's matches from the match table
+            u32x4 r = valid ? A.mtab[t] : u32x4{0u, 0u, 0u, 0u};
+            m_dst = (uint64_t)r.x | ((uint64_t)(r.w & 0xFFFFu) << 32);
+            m_len = r.y;
+            m_src = (uint64_t)r.z | ((uint64_t)(r.w >> 16) << 32);
+            l_len = 0;
           }
           const uint64_t cnt = min((uint64_t)G, t_end - t_next);
           t_next += cnt;
@@ -349,8 +486,13 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
         const uint64_t batch_start = __shfl(my_next, first, G);
         const uint32_t piece = m_rem ? min(m_rem, (uint32_t)(m_dst - m_src) + m_done) : 0u;
         const uint64_t src_end = m_src + piece;
+        // a match can only collide with bytes of its own block written in
+        // this batch (same-level matches of other blocks never feed it)
         bool hz = false;
-        if (MODE != kModePure) hz = piece > 0 && src_end > batch_start;
+        if (MODE != kModePure) {
+          const uint64_t own0 = (m_dst >> A.log2_bs) << A.log2_bs;
+          hz = piece > 0 && src_end > max(batch_start, own0);
+        }
         const uint64_t hz_bits = group_bits<G>(__ballot(hz), gw);
         const int h = hz_bits ? __builtin_ctzll(hz_bits) : G;
         const bool inc_l = l_pend && gl <= h;
@@ -358,34 +500,21 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
 
         // ------------------------------------------------ cross-block waits
         bool ready = true;
-        if (MODE == kModeFlags) {
+        if (MODE == kModeFlow) {
           const uint64_t sb0 = m_src >> A.log2_bs;
-          uint64_t sb1 = inc_m ? ((src_end - 1) >> A.log2_bs) : 0;
-          if (sb1 >= blk) sb1 = blk - 1;  // own block's bytes are ordered by the wave
-          const bool needs = inc_m && sb0 < blk && sb1 >= wm;
-          const uint64_t need_bits = group_bits<G>(__ballot(needs), gw);
-          if (need_bits) {
-            if (needs) {
-              bool ok = true;
-              for (uint64_t b = max(sb0, wm); b <= sb1; ++b)
-                ok = ok && (__hip_atomic_load(A.flags + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u);
-              ready = ok;
-            }
-            // advance the watermark over the next G blocks
-            const uint64_t wb = wm + gl;
-            const bool wdone =
-                wb < blk && __hip_atomic_load(A.flags + wb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
-            const uint64_t wbits = group_bits<G>(__ballot(wdone), gw);
-            const uint64_t run = (~wbits == 0ull) ? 64ull : (uint64_t)__builtin_ctzll(~wbits);
-            wm += min(run, (uint64_t)G);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            ready = group_bits<G>(__ballot(!ready), gw) == 0;
+          const uint64_t sb1 = inc_m ? ((src_end - 1) >> A.log2_bs) : 0;
+          if (inc_m) {
+            const uint64_t own = m_dst >> A.log2_bs;
+            for (uint64_t b = sb0; b <= sb1; ++b)
+              if (b != own)
+                ready = ready && (__hip_atomic_load(A.done_lvl + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= lvl);
           }
+          ready = group_bits<G>(__ballot(!ready), gw) == 0;
+          compiler_barrier();  // output loads stay after the done_level loads
         }
 
         if (ready) {
           // ---------------------------------------------- chunk the batch
-          const uintptr_t out_b = (uintptr_t)A.out;
           const uintptr_t a_dst = out_b + l_dst;
           const uintptr_t b_dst = out_b + m_dst + m_done;
           const uint32_t ca = inc_l ? nchunks(a_dst, l_len) : 0u;
@@ -437,12 +566,20 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
                 lo[i] = l0 > 0 ? (int)l0 : 0;
                 hi[i] = h0 < 16 ? (int)h0 : 16;
                 slot[i] = s0;
-                v[i] = load_window(S + (s0 - D), lb, hb, lo[i], hi[i]);
+                if (kCoh && q >= e.ca)
+                  v[i] = coh_load_window(out_r, (int64_t)(S + (s0 - D) - out_b), out_cap32, lo[i], hi[i]);
+                else
+                  v[i] = load_window(S + (s0 - D), lb, hb, lo[i], hi[i]);
               }
             }
 #pragma unroll
             for (int i = 0; i < U; ++i)
-              if (hi[i] > lo[i]) store_chunk(slot[i], v[i], lo[i], hi[i]);
+              if (hi[i] > lo[i]) {
+                if (kCoh)
+                  coh_store_chunk(out_r, (uint32_t)(slot[i] - out_b), v[i], lo[i], hi[i]);
+                else
+                  store_chunk(slot[i], v[i], lo[i], hi[i]);
+              }
           }
           lds_order();
           // ---------------------------------------------- retire segments
@@ -453,7 +590,7 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
       }
     }
     // -------------------------------------------------------- idle guard
-    if (MODE == kModeFlags) {
+    if (MODE == kModeFlow) {
       if (__any(progressed)) {
         idle = 0;
       } else {
@@ -472,50 +609,214 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
   }
 }
 
-__global__ void k_fill_u32(uint32_t* p, uint64_t count, uint32_t v) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i < count; i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
-}
-
 }  // namespace
 
 // ------------------------------------------------------------------ host side
 
 struct lz_dev {
-  lz::ArcView v;           // host view (base pointer is NOT kept valid)
+  lz::ArcView v;  // host view of the header (base pointer not kept)
   uint8_t* d_arc = nullptr;
-  uint32_t* d_flags = nullptr;
+  uint32_t* d_done = nullptr;
   uint32_t* d_ctrl = nullptr;  // [0] ticket, [1] err
-  uint16_t* d_lvl = nullptr;
-  uint16_t* d_bmax = nullptr;
-  uint32_t levels = 0;     // max level + 1 when the plan is present
-  bool has_plan = false;
+  uint32_t* d_slot = nullptr;
+  uint32_t* d_ublk = nullptr;
+  uint32_t* d_ulvl = nullptr;
+  uint32_t* d_unext = nullptr;
+  uint32_t* d_utok = nullptr;
+  uint32_t* d_first = nullptr;
+  uint32_t* d_lvls = nullptr;
+  uint32_t* d_tick = nullptr;
+  uint64_t* d_seg = nullptr;
+  uint64_t n_seg = 0;
+  u32x4* d_mtab = nullptr;
+  uint64_t n_units = 0, n_match = 0;
+  std::vector<uint64_t> lvl_start;  // first unit of each level, n_levels + 1 entries
   int cu_count = 0;
+  // replayable launch sequences, one per (output, config)
+  struct GraphKey {
+    uint8_t* out;
+    uint64_t cap;
+    uint32_t G, U, sched, batch;
+    bool operator==(const GraphKey& o) const {
+      return out == o.out && cap == o.cap && G == o.G && U == o.U && sched == o.sched && batch == o.batch;
+    }
+  };
+  std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
+  ~lz_dev() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+  }
 };
 
 namespace {
 
 struct DevLayout {
-  uint64_t arc, flags, ctrl, lvl, bmax, total;
+  uint64_t arc, done, ctrl, slot, ublk, ulvl, unext, utok, first, lvls, tick, seg, mtab, total;
 };
 
-DevLayout layout(const lz::ArcView& v, bool plan) {
+// Device layout for an archive; unit and match counts are bounded by n_tok.
+DevLayout layout(const lz::ArcView& v) {
   auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  const uint64_t T = v.n_tok;
   DevLayout L;
   L.arc = 0;
-  L.flags = a256(v.total);
-  L.ctrl = a256(L.flags + 4 * (v.nb + 1));
-  L.lvl = a256(L.ctrl + 256);
-  L.bmax = plan ? a256(L.lvl + 2 * v.n_tok) : L.lvl;
-  L.total = plan ? a256(L.bmax + 2 * (v.nb + 1)) : L.lvl;
+  L.done = a256(v.total);
+  L.ctrl = a256(L.done + 4 * (v.nb + 1));
+  L.slot = a256(L.ctrl + 256);
+  L.ublk = a256(L.slot + 4 * (T + 1));
+  L.ulvl = a256(L.ublk + 4 * (T + 1));
+  L.unext = a256(L.ulvl + 4 * (T + 1));
+  L.utok = a256(L.unext + 4 * (T + 1));
+  L.first = a256(L.utok + 4 * (T + 2));
+  L.lvls = a256(L.first + 4 * (v.nb + 1));
+  L.tick = a256(L.lvls + 4 * (T + 2));
+  L.seg = a256(L.tick + 4 * (T + 2));
+  L.mtab = a256(L.seg + 64 * (T / kSegTok + v.nb + 2));
+  L.total = a256(L.mtab + 16 * (T + 1));
   return L;
 }
 
-#define HIPCHK(x)                                                                  \
-  do {                                                                             \
-    hipError_t e_ = (x);                                                           \
+#define HIPCHK(x)                                                                         \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
     if (e_ != hipSuccess) return lz::fail(LZ_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
   } while (0)
+
+// Host plan: levels -> units ordered by (level, block) -> match-table slots.
+struct Plan {
+  std::vector<uint32_t> slot, ublk, ulvl, unext, utok, first, lvls32;
+  std::vector<uint64_t> seg;  // parse segments, 8 words each
+  std::vector<uint64_t> lvl_start;
+  uint64_t n_match = 0;
+};
+
+int build_plan(const lz::ArcView& v, Plan& P) {
+  const uint64_t T = v.n_tok;
+  std::vector<uint32_t> lv(T + 1, 0);
+  std::vector<uint8_t> hasm(T + 1, 0);
+  uint32_t mx = 0;
+  int rc = lz::compute_levels(v, lv.data(), &mx, hasm.data());
+  if (rc) return rc;
+  const uint64_t* tab = v.tab();
+  // per block: its match tokens sorted by (level, index); its units in level order
+  std::vector<uint64_t> mstart(v.nb + 1, 0);
+  for (uint64_t b = 0; b < v.nb; ++b) {
+    uint64_t c = 0;
+    for (uint64_t t = tab[4 * b]; t < tab[4 * b + 4]; ++t) c += hasm[t];
+    mstart[b + 1] = mstart[b] + c;
+  }
+  const uint64_t M = mstart[v.nb];
+  P.n_match = M;
+  if (M > 0xFFFFFFF0ull) return lz::fail(LZ_E_INVAL, "too many matches for 32-bit plan indices");
+  std::vector<uint64_t> order(M);  // (level << 32 | local rank) sorted per block -> token index
+  std::vector<uint32_t> ord_lvl(M);
+  std::vector<uint64_t> ustart(v.nb + 1, 0);  // per block count of units, then prefix
+  {
+    std::vector<uint64_t> nunits(v.nb, 0);
+    std::vector<std::thread> pool;
+    unsigned W = std::min<unsigned>(lz::hw_threads(0), 16);
+    std::atomic<uint64_t> next{0};
+    for (unsigned w = 0; w < W; ++w)
+      pool.emplace_back([&] {
+        std::vector<std::pair<uint32_t, uint64_t>> tmp;
+        for (;;) {
+          uint64_t b = next.fetch_add(1);
+          if (b >= v.nb) break;
+          tmp.clear();
+          for (uint64_t t = tab[4 * b]; t < tab[4 * b + 4]; ++t)
+            if (hasm[t]) tmp.emplace_back(lv[t], t);
+          std::stable_sort(tmp.begin(), tmp.end(),
+                           [](const std::pair<uint32_t, uint64_t>& x, const std::pair<uint32_t, uint64_t>& y) {
+                             return x.first < y.first;
+                           });
+          uint64_t u = 0;
+          for (size_t i = 0; i < tmp.size(); ++i) {
+            order[mstart[b] + i] = tmp[i].second;
+            ord_lvl[mstart[b] + i] = tmp[i].first;
+            if (i == 0 || tmp[i].first != tmp[i - 1].first) ++u;
+          }
+          nunits[b] = u;
+        }
+      });
+    for (auto& t : pool) t.join();
+    for (uint64_t b = 0; b < v.nb; ++b) ustart[b + 1] = ustart[b] + nunits[b];
+  }
+  const uint64_t NU = ustart[v.nb];
+  const uint64_t NL = M ? (uint64_t)mx + 1 : 0;
+  // count units per level, then place each block's units in (level, block) order
+  std::vector<uint64_t> per_lvl(NL + 1, 0);
+  std::vector<uint32_t> bu_lvl(NU), bu_cnt(NU);  // block-major unit list
+  for (uint64_t b = 0; b < v.nb; ++b) {
+    uint64_t u = ustart[b];
+    for (uint64_t i = mstart[b]; i < mstart[b + 1]; ++i) {
+      if (i == mstart[b] || ord_lvl[i] != ord_lvl[i - 1]) {
+        bu_lvl[u] = ord_lvl[i];
+        bu_cnt[u] = 0;
+        ++u;
+      }
+      bu_cnt[u - 1]++;
+    }
+  }
+  for (uint64_t u = 0; u < NU; ++u) per_lvl[bu_lvl[u] + 1]++;
+  P.lvl_start.assign(NL + 1, 0);
+  for (uint64_t p = 0; p < NL; ++p) P.lvl_start[p + 1] = P.lvl_start[p] + per_lvl[p + 1];
+  std::vector<uint64_t> cursor(P.lvl_start.begin(), P.lvl_start.end());
+  std::vector<uint32_t> uid_of(NU);  // block-major unit -> global unit id
+  P.ublk.assign(NU, 0);
+  P.ulvl.assign(NU, 0);
+  P.unext.assign(NU, kNone);
+  std::vector<uint32_t> ucnt(NU);
+  P.first.assign(v.nb + 1, kNone);
+  for (uint64_t b = 0; b < v.nb; ++b) {
+    for (uint64_t u = ustart[b]; u < ustart[b + 1]; ++u) {
+      uint64_t g = cursor[bu_lvl[u]]++;
+      uid_of[u] = (uint32_t)g;
+      P.ublk[g] = (uint32_t)b;
+      P.ulvl[g] = bu_lvl[u];
+      ucnt[g] = bu_cnt[u];
+      if (u + 1 < ustart[b + 1]) P.unext[g] = bu_lvl[u + 1];
+    }
+    if (ustart[b + 1] > ustart[b]) P.first[b] = bu_lvl[ustart[b]];
+  }
+  P.lvls32.assign(P.lvl_start.begin(), P.lvl_start.end());
+  // parse segments: every kSegTok tokens of a block, with the cursors there
+  {
+    std::vector<std::vector<uint64_t>> per(v.nb);
+    std::vector<std::thread> pool;
+    unsigned W = std::min<unsigned>(lz::hw_threads(0), 16);
+    std::atomic<uint64_t> next{0};
+    for (unsigned w = 0; w < W; ++w)
+      pool.emplace_back([&] {
+        for (;;) {
+          uint64_t b = next.fetch_add(1);
+          if (b >= v.nb) break;
+          const uint64_t t0 = tab[4 * b], t1 = tab[4 * b + 4];
+          auto& o = per[b];
+          (void)lz::walk_block(v, b, [&](uint64_t t, const lz::Tok& k) {
+            if ((t - t0) % kSegTok == 0) {
+              const uint64_t rec[8] = {t, std::min(t + kSegTok, t1), t1, k.dst, k.lit_off, k.x16_off, k.x32_off, b};
+              o.insert(o.end(), rec, rec + 8);
+            }
+          });
+        }
+      });
+    for (auto& t : pool) t.join();
+    size_t tot = 0;
+    for (auto& o : per) tot += o.size();
+    P.seg.reserve(tot);
+    for (auto& o : per) P.seg.insert(P.seg.end(), o.begin(), o.end());
+  }
+  P.utok.assign(NU + 1, 0);
+  for (uint64_t g = 0; g < NU; ++g) P.utok[g + 1] = P.utok[g] + ucnt[g];
+  P.slot.assign(T + 1, kNone);
+  for (uint64_t b = 0; b < v.nb; ++b) {
+    uint64_t i = mstart[b];
+    for (uint64_t u = ustart[b]; u < ustart[b + 1]; ++u) {
+      uint32_t g = uid_of[u];
+      for (uint32_t k = 0; k < ucnt[g]; ++k, ++i) P.slot[order[i]] = P.utok[g] + k;
+    }
+  }
+  return 0;
+}
 
 KArgs base_args(const lz_dev* h) {
   KArgs A;
@@ -534,11 +835,20 @@ KArgs base_args(const lz_dev* h) {
   A.log2_bs = v.log2_bs;
   A.nb = (uint32_t)v.nb;
   A.min_match = (uint32_t)v.min_match;
-  A.flags = h->d_flags;
-  A.ticket = h->d_ctrl;
+  A.slot = h->d_slot;
+  A.mtab = h->d_mtab;
+  A.unit_blk = h->d_ublk;
+  A.unit_lvl = h->d_ulvl;
+  A.unit_next = h->d_unext;
+  A.unit_tok = h->d_utok;
+  A.first_lvl = h->d_first;
+  A.done_lvl = h->d_done;
+  A.lvl_start = h->d_lvls;
+  A.tickets = h->d_tick;
+  A.seg = h->d_seg;
+  A.nseg = h->n_seg;
   A.err = h->d_ctrl + 1;
-  A.lvl = h->d_lvl;
-  A.blk_maxlvl = h->d_bmax;
+  A.n_levels = (uint32_t)(h->lvl_start.size() ? h->lvl_start.size() - 1 : 0);
   return A;
 }
 
@@ -553,10 +863,14 @@ kfn_t pick_kernel(uint32_t G, uint32_t U) {
   return nullptr;
 }
 
-int resolve_cfg(const lz_decode_cfg* cfg, uint32_t& G, uint32_t& U, uint32_t& sched) {
-  G = cfg ? cfg->G : 32;
+int resolve_cfg(const lz_decode_cfg* cfg, uint32_t& G, uint32_t& U, uint32_t& sched, uint32_t* batch = nullptr) {
+  G = cfg ? cfg->G : 64;
   U = cfg ? cfg->unroll : 2;
-  sched = cfg ? cfg->schedule : 0;
+  sched = cfg ? cfg->schedule : 1;
+  if (batch) {
+    *batch = (cfg && cfg->unit_batch) ? cfg->unit_batch : 1;
+    if (*batch > G) return lz::fail(LZ_E_INVAL, "unit_batch must be at most G");
+  }
   if (cfg && cfg->wg_size && cfg->wg_size != 256) return lz::fail(LZ_E_INVAL, "wg_size must be 0 or 256");
   if (!(G == 8 || G == 16 || G == 32 || G == 64)) return lz::fail(LZ_E_INVAL, "G must be 8, 16, 32 or 64");
   if (!(U == 1 || U == 2 || U == 4)) return lz::fail(LZ_E_INVAL, "unroll must be 1, 2 or 4");
@@ -564,11 +878,16 @@ int resolve_cfg(const lz_decode_cfg* cfg, uint32_t& G, uint32_t& U, uint32_t& sc
   return 0;
 }
 
-int resident_groups(kfn_t k, int cu_count, uint32_t G) {
+uint64_t resident_groups(kfn_t k, int cu_count, uint32_t G) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, kWG, 0) != hipSuccess || per_cu < 1)
     per_cu = 1;
-  return per_cu * cu_count * (kWG / (int)G);
+  return (uint64_t)per_cu * (uint64_t)std::max(cu_count, 1) * (kWG / G);
+}
+
+uint64_t grid_for(uint64_t items, uint64_t resident, uint32_t G) {
+  uint64_t groups = std::max<uint64_t>(1, std::min(items, resident));
+  return (groups + (kWG / G) - 1) / (kWG / G);
 }
 
 }  // namespace
@@ -580,7 +899,7 @@ int lz_device_bytes(const uint8_t* arc, uint64_t arc_size, uint64_t* bytes) {
   lz::ArcView v;
   int rc = lz::view_archive(arc, arc_size, &v);
   if (rc) return rc;
-  *bytes = layout(v, true).total;
+  *bytes = layout(v).total;
   return 0;
 }
 
@@ -592,70 +911,88 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
   if (rc) return rc;
   rc = lz::validate_archive(v, 0);
   if (rc) return rc;
-  if (v.nb > 0xFFFFFFF0ull) return lz::fail(LZ_E_INVAL, "too many blocks");
-  DevLayout L = layout(v, true);
+  if (v.nb > 0xFFFFFFF0ull || v.n_tok > 0xFFFFFFF0ull) return lz::fail(LZ_E_INVAL, "archive too large for 32-bit plan");
+  DevLayout L = layout(v);
   if (d_cap < L.total)
     return lz::fail(LZ_E_NOMEM, "device buffer %llu < %llu bytes", (unsigned long long)d_cap,
                     (unsigned long long)L.total);
-  // dependency levels for schedule 1 (host sweep)
-  std::vector<uint32_t> lv(v.n_tok + 1);
-  uint32_t mx = 0;
-  rc = lz::compute_levels(v, lv.data(), &mx);
+  Plan P;
+  try {
+    rc = build_plan(v, P);
+  } catch (const std::bad_alloc&) {
+    return lz::fail(LZ_E_NOMEM, "plan allocation failed");
+  }
   if (rc) return rc;
   lz_dev* h = new lz_dev();
   h->v = v;
   h->v.base = nullptr;
   uint8_t* base = (uint8_t*)d_buf;
   h->d_arc = base + L.arc;
-  h->d_flags = (uint32_t*)(base + L.flags);
+  h->d_done = (uint32_t*)(base + L.done);
   h->d_ctrl = (uint32_t*)(base + L.ctrl);
-  h->d_lvl = (uint16_t*)(base + L.lvl);
-  h->d_bmax = (uint16_t*)(base + L.bmax);
+  h->d_slot = (uint32_t*)(base + L.slot);
+  h->d_ublk = (uint32_t*)(base + L.ublk);
+  h->d_ulvl = (uint32_t*)(base + L.ulvl);
+  h->d_unext = (uint32_t*)(base + L.unext);
+  h->d_utok = (uint32_t*)(base + L.utok);
+  h->d_first = (uint32_t*)(base + L.first);
+  h->d_lvls = (uint32_t*)(base + L.lvls);
+  h->d_tick = (uint32_t*)(base + L.tick);
+  h->d_seg = (uint64_t*)(base + L.seg);
+  h->n_seg = P.seg.size() / 8;
+  h->d_mtab = (u32x4*)(base + L.mtab);
+  h->n_units = P.ublk.size();
+  h->n_match = P.n_match;
+  h->lvl_start = P.lvl_start;
   hipStream_t s = (hipStream_t)stream;
   int dev = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
-  if (mx < 65535) {
-    // u16 levels and per-block maxima, staged through pinned memory
-    uint64_t nbytes = 2 * (v.n_tok + 1) + 2 * (v.nb + 1);
-    uint16_t* hp = nullptr;
-    if (hipHostMalloc((void**)&hp, nbytes, 0) != hipSuccess) {
-      delete h;
-      return lz::fail(LZ_E_NOMEM, "pinned staging allocation failed");
-    }
-    uint16_t* bm = hp + (v.n_tok + 1);
-    for (uint64_t b = 0; b <= v.nb; ++b) bm[b] = 0;
-    const uint64_t* T = v.tab();
-    for (uint64_t b = 0; b < v.nb; ++b)
-      for (uint64_t t = T[4 * b]; t < T[4 * b + 4]; ++t) {
-        hp[t] = (uint16_t)lv[t];
-        bm[b] = std::max<uint16_t>(bm[b], (uint16_t)lv[t]);
-      }
-    hipError_t e1 = hipMemcpyAsync(h->d_lvl, hp, 2 * (v.n_tok + 1), hipMemcpyHostToDevice, s);
-    hipError_t e2 = hipMemcpyAsync(h->d_bmax, bm, 2 * (v.nb + 1), hipMemcpyHostToDevice, s);
-    hipError_t e3 = hipStreamSynchronize(s);
-    hipHostFree(hp);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-      delete h;
-      return lz::fail(LZ_E_HIP, "plan upload failed");
-    }
-    h->has_plan = true;
-    h->levels = mx + 1;
-  }
-  if (hipMemcpyAsync(h->d_arc, arc, v.total, hipMemcpyHostToDevice, s) != hipSuccess) {
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
     delete h;
-    return lz::fail(LZ_E_HIP, "archive upload failed");
+    return lz::fail(LZ_E_HIP, "device query failed");
   }
-  if (hipStreamSynchronize(s) != hipSuccess) {
+  // stage the plan through pinned memory, then the archive
+  struct Piece {
+    void* dst;
+    const void* src;
+    uint64_t bytes;
+  };
+  const Piece pieces[] = {
+      {h->d_slot, P.slot.data(), 4 * P.slot.size()},    {h->d_ublk, P.ublk.data(), 4 * P.ublk.size()},
+      {h->d_ulvl, P.ulvl.data(), 4 * P.ulvl.size()},    {h->d_unext, P.unext.data(), 4 * P.unext.size()},
+      {h->d_utok, P.utok.data(), 4 * P.utok.size()},    {h->d_first, P.first.data(), 4 * P.first.size()},
+      {h->d_lvls, P.lvls32.data(), 4 * P.lvls32.size()},
+      {h->d_seg, P.seg.data(), 8 * P.seg.size()},
+  };
+  uint64_t stage = v.total;
+  for (const Piece& q : pieces) stage += (q.bytes + 255) & ~uint64_t(255);
+  uint8_t* hp = nullptr;
+  if (hipHostMalloc((void**)&hp, stage, 0) != hipSuccess) {
     delete h;
-    return lz::fail(LZ_E_HIP, "archive upload failed");
+    return lz::fail(LZ_E_NOMEM, "pinned staging allocation of %llu bytes failed", (unsigned long long)stage);
+  }
+  uint64_t off = 0;
+  bool ok = true;
+  for (const Piece& q : pieces) {
+    if (!q.bytes) continue;
+    memcpy(hp + off, q.src, q.bytes);
+    ok = ok && hipMemcpyAsync(q.dst, hp + off, q.bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+    off += (q.bytes + 255) & ~uint64_t(255);
+  }
+  memcpy(hp + off, arc, v.total);
+  ok = ok && hipMemcpyAsync(h->d_arc, hp + off, v.total, hipMemcpyHostToDevice, s) == hipSuccess;
+  ok = ok && hipStreamSynchronize(s) == hipSuccess;
+  ok = (hipHostFree(hp) == hipSuccess) && ok;
+  if (!ok) {
+    delete h;
+    return lz::fail(LZ_E_HIP, "upload failed");
   }
   *out = h;
   return 0;
 }
 
 uint64_t lz_device_n(const lz_dev* h) { return h ? h->v.n : 0; }
-uint32_t lz_device_levels(const lz_dev* h) { return h ? h->levels : 0; }
+uint32_t lz_device_levels(const lz_dev* h) { return h ? (uint32_t)(h->lvl_start.size() ? h->lvl_start.size() - 1 : 0) : 0; }
 void lz_device_close(lz_dev* h) { delete h; }
 
 int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cfg* cfg, void* stream) {
@@ -663,37 +1000,80 @@ int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decod
   if (out_cap < h->v.n) return lz::fail(LZ_E_INVAL, "output capacity %llu < n %llu", (unsigned long long)out_cap,
                                         (unsigned long long)h->v.n);
   if (h->v.n && !d_out) return lz::fail(LZ_E_INVAL, "null output");
-  uint32_t G, U, sched;
-  int rc = resolve_cfg(cfg, G, U, sched);
+  uint32_t G, U, sched, batch;
+  int rc = resolve_cfg(cfg, G, U, sched, &batch);
   if (rc) return rc;
+  if (sched == 0 && out_cap > 0xFFFFFFFFull)
+    return lz::fail(LZ_E_INVAL, "schedule 0 addresses outputs below 4 GiB; use schedule 1");
+  if (h->v.nb == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
+  lz_dev::GraphKey key{d_out, out_cap, G, U, sched, batch};
+  for (auto& g : h->graphs)
+    if (g.first == key) {
+      HIPCHK(hipGraphLaunch(g.second, s));
+      return 0;
+    }
+  // build the launch sequence once: parse, then the match units
   KArgs A = base_args(h);
   A.out = d_out;
   A.msrc = d_out;
   A.msrc_lo = (uintptr_t)d_out;
   A.msrc_hi = (uintptr_t)d_out + out_cap;
-  // clear flags, ticket and error word (a fill kernel, also safe under capture)
-  uint64_t clear = ((uint64_t)((uint8_t*)h->d_ctrl - (uint8_t*)h->d_flags)) / 4 + 2;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>((clear + 255) / 256, 1024)), dim3(256), 0, s,
-                     h->d_flags, clear, 0u);
-  HIPCHK(hipGetLastError());
-  if (h->v.nb == 0) return 0;
-  if (sched == 0) {
-    kfn_t k = pick_kernel<kModeFlags>(G, U);
-    uint64_t groups = std::min<uint64_t>(h->v.nb, (uint64_t)resident_groups(k, h->cu_count, G));
-    uint64_t wgs = (groups + (kWG / G) - 1) / (kWG / G);
-    hipLaunchKernelGGL(k, dim3((unsigned)wgs), dim3(kWG), 0, s, A);
-    HIPCHK(hipGetLastError());
-  } else {
-    if (!h->has_plan) return lz::fail(LZ_E_INVAL, "no level plan (more than 65534 levels)");
-    kfn_t k = pick_kernel<kModeLevels>(G, U);
-    uint64_t wgs = (h->v.nb + (kWG / G) - 1) / (kWG / G);
-    for (uint32_t p = 0; p < h->levels; ++p) {
-      A.pass = p;
-      hipLaunchKernelGGL(k, dim3((unsigned)wgs), dim3(kWG), 0, s, A);
-      HIPCHK(hipGetLastError());
+  A.unit_batch = batch;
+  struct Launch {
+    kfn_t k;
+    uint64_t grid;
+    KArgs a;
+  };
+  std::vector<Launch> seq;
+  kfn_t kp = pick_kernel<kModeParse>(G, U);
+  seq.push_back({kp, grid_for(h->n_seg, resident_groups(kp, h->cu_count, G), G), A});
+  if (h->n_units) {
+    if (sched == 0) {
+      kfn_t k = pick_kernel<kModeFlow>(G, U);
+      KArgs a = A;
+      a.unit_lo = 0;
+      a.unit_hi = h->n_units;
+      seq.push_back({k, grid_for((h->n_units + batch - 1) / batch, resident_groups(k, h->cu_count, G), G), a});
+    } else {
+      kfn_t k = pick_kernel<kModeLevels>(G, U);
+      const uint64_t res = resident_groups(k, h->cu_count, G);
+      for (size_t p = 0; p + 1 < h->lvl_start.size(); ++p) {
+        KArgs a = A;
+        a.unit_lo = h->lvl_start[p];
+        a.unit_hi = h->lvl_start[p + 1];
+        if (a.unit_hi == a.unit_lo) continue;
+        seq.push_back({k, grid_for((a.unit_hi - a.unit_lo + batch - 1) / batch, res, G), a});
+      }
     }
   }
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipGraphCreate(&graph, 0));
+  hipGraphNode_t prev = nullptr;
+  for (Launch& L : seq) {
+    hipKernelNodeParams kp2;
+    memset(&kp2, 0, sizeof(kp2));
+    void* args[] = {&L.a};
+    kp2.func = (void*)L.k;
+    kp2.gridDim = dim3((unsigned)L.grid);
+    kp2.blockDim = dim3(kWG);
+    kp2.sharedMemBytes = 0;
+    kp2.kernelParams = args;
+    kp2.extra = nullptr;
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp2);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return lz::fail(LZ_E_HIP, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+    }
+    prev = node;
+  }
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return lz::fail(LZ_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  h->graphs.push_back({key, exec});
+  HIPCHK(hipGraphLaunch(exec, s));
   return 0;
 }
 
@@ -735,9 +1115,8 @@ int lz_purecopy_device(uint64_t ntok, const uint64_t* d_dst, const uint64_t* d_l
   A.nunits = nunits;
   (void)out_size;
   kfn_t k = pick_kernel<kModePure>(G, U);
-  uint64_t wgs = (nunits + (kWG / G) - 1) / (kWG / G);
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k, dim3((unsigned)wgs), dim3(kWG), 0, s, A);
+  hipLaunchKernelGGL(k, dim3((unsigned)grid_for(nunits, resident_groups(k, 256, G), G)), dim3(kWG), 0, s, A);
   HIPCHK(hipGetLastError());
   return 0;
 }

@@ -51,7 +51,7 @@ int fail(int code, const char* fmt, ...) {
 unsigned hw_threads(uint32_t requested) {
   if (requested) return requested;
   unsigned h = std::thread::hardware_concurrency();
-  return h ? h : 1;
+  return h ? std::min(h, 32u) : 1;
 }
 
 template <class F>
@@ -278,9 +278,12 @@ static int assemble(uint64_t n, uint32_t log2_bs, uint64_t min_match, const uint
 
 // ------------------------------------------------------------------ encoder
 
+// Chain entry of position p: low 32 bits = previous position + 1 with the
+// same key hash (0 = none), high 32 bits = a fingerprint of p's key, so a walk
+// rejects hash collisions from the entry it already loaded.
 struct HashIndex {
-  uint32_t key = 4;        // bytes hashed
-  std::vector<uint32_t> prev;  // prev[p] = previous position + 1 with the same hash (0 = none)
+  uint32_t key = 4;             // bytes hashed
+  std::vector<uint64_t> prev;
 };
 
 static inline uint64_t load_key(const uint8_t* p, uint32_t k) {
@@ -303,6 +306,13 @@ static inline uint32_t hash_key(uint64_t v, int bits) {
   return uint32_t(v >> (64 - bits));
 }
 
+static inline uint64_t fingerprint(uint64_t v) {
+  v ^= v >> 31;
+  v *= 0x94D049BB133111EBull;
+  v ^= v >> 29;
+  return (v & 0xFFFFFFFF00000000ull);
+}
+
 // Builds prev[] over positions [lo, hi) (sources and destinations stay in one
 // segment) for positions p with p + key <= hi, in parallel: each thread
 // chains its own range with a local head table, then ranges are stitched.
@@ -316,8 +326,9 @@ static void build_index(const uint8_t* x, uint64_t lo, uint64_t hi, uint32_t key
     for (uint64_t p = lo; p + key <= hi; ++p) {
       uint8_t tmp[16] = {0};
       memcpy(tmp, x + p, key);
-      uint32_t h = hash_key(load_key(tmp, key), bits);
-      idx.prev[p] = head[h];
+      const uint64_t kv = load_key(tmp, key);
+      uint32_t h = hash_key(kv, bits);
+      idx.prev[p] = head[h] | fingerprint(kv);
       head[h] = uint32_t(p - lo + 1);
     }
     return;
@@ -344,8 +355,9 @@ static void build_index(const uint8_t* x, uint64_t lo, uint64_t hi, uint32_t key
       head.assign(size_t(1) << bits, 0);
       first.assign(size_t(1) << bits, 0);
       for (uint64_t p = a; p < b; ++p) {
-        uint32_t h = hash_key(key_at(p), bits);
-        idx.prev[p] = head[h];
+        const uint64_t kv = key_at(p);
+        uint32_t h = hash_key(kv, bits);
+        idx.prev[p] = head[h] | fingerprint(kv);
         if (!head[h]) first[h] = uint32_t(p - lo + 1);
         head[h] = uint32_t(p - lo + 1);
       }
@@ -359,7 +371,8 @@ static void build_index(const uint8_t* x, uint64_t lo, uint64_t hi, uint32_t key
     auto& head = heads[w];
     for (size_t h = 0; h < acc.size(); ++h) {
       if (first[h]) {
-        idx.prev[lo + first[h] - 1] = acc[h];
+        uint64_t& e = idx.prev[lo + first[h] - 1];
+        e = (e & 0xFFFFFFFF00000000ull) | acc[h];
         acc[h] = head[h];
       }
     }
@@ -406,17 +419,30 @@ static void parse_block(const EncCtx& c, uint64_t b, std::vector<BTok>& toks, st
   uint64_t pos = start, run = 0;
   toks.clear();
   lit.clear();
+  lit.reserve(end - start);
   while (pos < end) {
     uint64_t best_len = 0, best_src = 0;
+    if (pos + 4 < end) {
+      __builtin_prefetch(&c.near_idx.prev[pos + 4]);
+      __builtin_prefetch(&c.far_idx.prev[pos + 4]);
+    }
     // near chain: candidates within distance bound[1]
     if (pos + kn <= end) {
       // prev[pos] is the nearest earlier position with the same key hash
-      uint32_t link = c.near_idx.prev[pos];
-      uint32_t steps = 0;
+      const uint64_t e0 = c.near_idx.prev[pos];
+      const uint64_t fp = e0 & 0xFFFFFFFF00000000ull;
+      uint32_t link = uint32_t(e0);
+      uint32_t steps = 0, walked = 0;
       while (link) {
         uint64_t src = seg_lo + link - 1;
         uint64_t d = pos - src;
         if (d >= bound[1]) break;
+        const uint64_t e = c.near_idx.prev[src];
+        if ((e & 0xFFFFFFFF00000000ull) != fp) {  // different key, same hash
+          if (maxc && ++walked >= 8 * maxc) break;
+          link = uint32_t(e);
+          continue;
+        }
         uint64_t L = match_len(x, src, pos, end);
         int cl = dclass(d, bound);
         if (L >= thr[cl] && (L > best_len || (L == best_len && src > best_src))) {
@@ -425,16 +451,24 @@ static void parse_block(const EncCtx& c, uint64_t b, std::vector<BTok>& toks, st
           if (pos + L == end) break;
         }
         if (maxc && ++steps >= maxc) break;
-        link = c.near_idx.prev[src];
+        link = uint32_t(e);
       }
     }
     // far chain: any distance
     if (pos + kf <= end && best_len < end - pos) {
-      uint32_t link = c.far_idx.prev[pos];
-      uint32_t steps = 0;
+      const uint64_t e0 = c.far_idx.prev[pos];
+      const uint64_t fp = e0 & 0xFFFFFFFF00000000ull;
+      uint32_t link = uint32_t(e0);
+      uint32_t steps = 0, walked = 0;
       while (link) {
         uint64_t src = seg_lo + link - 1;
         uint64_t d = pos - src;
+        const uint64_t e = c.far_idx.prev[src];
+        if ((e & 0xFFFFFFFF00000000ull) != fp) {
+          if (maxc && ++walked >= 8 * maxc) break;
+          link = uint32_t(e);
+          continue;
+        }
         uint64_t L = match_len(x, src, pos, end);
         int cl = dclass(d, bound);
         if (L >= thr[cl] && (L > best_len || (L == best_len && src > best_src))) {
@@ -443,7 +477,7 @@ static void parse_block(const EncCtx& c, uint64_t b, std::vector<BTok>& toks, st
           if (pos + L == end) break;
         }
         if (maxc && ++steps >= maxc) break;
-        link = c.far_idx.prev[src];
+        link = uint32_t(e);
       }
     }
     if (best_len) {
@@ -749,43 +783,42 @@ int lz_entropy_size(const uint8_t* arc, uint64_t arc_size, double* total, double
 
 namespace lz {
 
-// Levels by a sequential sweep in block order: each output byte remembers the
-// level of the token that wrote it (literals 0); a match takes the maximum
-// over its source bytes, +1 for bytes of another block.  Byte levels are kept
-// per run, not per byte: one entry per token piece.
-int compute_levels(const ArcView& v, uint32_t* levels, uint32_t* max_level) {
-  // run map: token start positions and levels of literal and match parts
-  std::vector<uint64_t> starts;  // start of each run (sorted)
-  std::vector<uint32_t> lv;      // level of the run
-  starts.reserve(2 * v.n_tok + 1);
-  lv.reserve(2 * v.n_tok + 1);
+// Levels by a sequential sweep in block order.  Each block keeps its runs
+// (literal runs at level 0, match pieces at their level) sorted by start, so a
+// source interval is resolved by a binary search in the source block's runs
+// only; a source interval that spans two blocks is split.
+int compute_levels(const ArcView& v, uint32_t* levels, uint32_t* max_level, uint8_t* has_match) {
+  struct Run {
+    uint32_t start;  // offset in block
+    uint32_t level;
+  };
+  std::vector<std::vector<Run>> runs(v.nb);
   uint32_t mx = 0;
   for (uint64_t b = 0; b < v.nb; ++b) {
+    std::vector<Run>& mine = runs[b];
     int rc = walk_block(v, b, [&](uint64_t t, const Tok& k) {
-      if (k.lit_len) {
-        starts.push_back(k.dst);
-        lv.push_back(0);
-      }
+      const uint64_t b0 = b << v.log2_bs;
+      if (k.lit_len) mine.push_back(Run{uint32_t(k.dst - b0), 0});
       uint32_t L = 0;
       if (k.mlen) {
-        uint64_t m0 = k.dst + k.lit_len;
-        uint64_t s = k.src, e = std::min(k.src + k.mlen, m0);
-        // runs overlapping [s, e)
-        size_t i = std::upper_bound(starts.begin(), starts.end(), s) - starts.begin() - 1;
-        for (; i < starts.size() && starts[i] < e; ++i) {
-          uint64_t run_start = starts[i];
-          uint64_t run_end = (i + 1 < starts.size()) ? starts[i + 1] : m0;
-          if (run_end <= s) continue;
-          // a run may straddle a block boundary only if its token was cut;
-          // runs never cross block ends, so the block of its start decides
-          uint32_t w = lv[i] + ((run_start >> v.log2_bs) != b ? 1u : 0u);
-          (void)run_end;
-          L = std::max(L, w);
+        const uint64_t m0 = k.dst + k.lit_len;
+        const uint64_t s = k.src, e = std::min(k.src + k.mlen, m0);  // own bytes excluded
+        for (uint64_t q = s; q < e;) {
+          const uint64_t sb = q >> v.log2_bs;
+          const uint64_t sb_end = std::min(e, (sb + 1) << v.log2_bs);
+          const std::vector<Run>& R = runs[sb];
+          const uint32_t lo = uint32_t(q - (sb << v.log2_bs)), hi = uint32_t(sb_end - (sb << v.log2_bs));
+          // last run starting at or before lo, then every run starting before hi
+          size_t i = std::upper_bound(R.begin(), R.end(), lo, [](uint32_t x, const Run& r) { return x < r.start; }) -
+                     R.begin();
+          i = i ? i - 1 : 0;
+          for (; i < R.size() && R[i].start < hi; ++i) L = std::max(L, R[i].level + (sb != b ? 1u : 0u));
+          q = sb_end;
         }
-        starts.push_back(m0);
-        lv.push_back(L);
+        mine.push_back(Run{uint32_t(m0 - b0), L});
       }
       if (levels) levels[t] = L;
+      if (has_match) has_match[t] = k.mlen ? 1 : 0;
       mx = std::max(mx, L);
     });
     if (rc) return fail(LZ_E_CORRUPT, "block %llu fails validation", (unsigned long long)b);

@@ -42,6 +42,8 @@ struct Tok {
   uint64_t lit_off;  // offset in the lit stream
   uint64_t mlen;
   uint64_t src;
+  uint64_t x16_off;  // extension cursors before this token
+  uint64_t x32_off;
 };
 
 // Walks block b's tokens, validating every container rule; calls f(tok_index,
@@ -53,7 +55,7 @@ int walk_block(const ArcView& v, uint64_t b, F&& f);
 int validate_archive(const ArcView& v, uint32_t n_threads);
 
 // Per-token levels (see lz_plan); returns max level.
-int compute_levels(const ArcView& v, uint32_t* levels, uint32_t* max_level);
+int compute_levels(const ArcView& v, uint32_t* levels, uint32_t* max_level, uint8_t* has_match = nullptr);
 
 unsigned hw_threads(uint32_t requested);
 
@@ -84,6 +86,7 @@ int walk_block(const ArcView& v, uint64_t b, F&& f) {
   const uint8_t* slo = v.base + v.off_slo;
   const uint8_t* shi = (v.flags & 1) ? v.base + v.off_shi : nullptr;
   for (uint64_t t = t0; t < t1; ++t) {
+    const uint64_t xc0 = xc, yc0 = yc;
     uint8_t c = cmd[t];
     uint64_t val[2] = {uint64_t(c >> 4), uint64_t(c & 15)};
     bool last = (t + 1 == t1);
@@ -114,7 +117,7 @@ int walk_block(const ArcView& v, uint64_t b, F&& f) {
     if (shi) src |= uint64_t(shi[t]) << 32;
     if (mlen > 0 && src >= mstart) return LZ_E_CORRUPT;
     if (mlen == 0 && src != 0) return LZ_E_CORRUPT;
-    f(t, Tok{pos, lit_len, lc, mlen, src});
+    f(t, Tok{pos, lit_len, lc, mlen, src, xc0, yc0});
     lc += lit_len;
     pos = mstart + mlen;
   }

@@ -47,7 +47,7 @@ class Info(ctypes.Structure):
 
 
 class DecodeCfg(ctypes.Structure):
-    _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("wg_size", _u32)]
+    _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("wg_size", _u32), ("unit_batch", _u32)]
 
 
 def lib():
@@ -100,7 +100,17 @@ def _take_archive(pa, size):
         lib().lz_free(pa)
 
 
+def default_threads():
+    """Encoder threads: OMP_NUM_THREADS when set, else up to 16."""
+    v = os.environ.get("OMP_NUM_THREADS")
+    if v and v.isdigit() and int(v) > 0:
+        return int(v)
+    return min(os.cpu_count() or 1, 16)
+
+
 def params(log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0):
+    if not n_threads:
+        n_threads = default_threads()
     p = Params()
     lib().lz_params_default(ctypes.byref(p))
     p.log2_bs = log2_bs
@@ -193,9 +203,9 @@ def fnv1a64(data, seed=0xcbf29ce484222325):
     return int(lib().lz_fnv1a64(a.ctypes.data, a.size, seed))
 
 
-def _cfg(G=32, unroll=2, schedule=0):
+def _cfg(G=64, unroll=2, schedule=1, unit_batch=0):
     c = DecodeCfg()
-    c.G, c.unroll, c.schedule, c.wg_size = G, unroll, schedule, 0
+    c.G, c.unroll, c.schedule, c.wg_size, c.unit_batch = G, unroll, schedule, 0, unit_batch
     return c
 
 
@@ -226,11 +236,11 @@ class DeviceArchive:
         self.levels = int(lib().lz_device_levels(h))
         self.device_bytes = nb.value
 
-    def decode(self, out=None, G=32, unroll=2, schedule=0, stream=None, check=True):
+    def decode(self, out=None, G=64, unroll=2, schedule=1, stream=None, check=True, unit_batch=0):
         import torch
         if out is None:
             out = torch.empty(max(self.n, 1), dtype=torch.uint8, device=self.buf.device)
-        c = _cfg(G, unroll, schedule)
+        c = _cfg(G, unroll, schedule, unit_batch)
         rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                     _stream(stream))
         if rc:
@@ -239,8 +249,8 @@ class DeviceArchive:
             self.check(stream)
         return out[:self.n]
 
-    def decode_async(self, out, G=32, unroll=2, schedule=0, stream=None):
-        c = _cfg(G, unroll, schedule)
+    def decode_async(self, out, G=64, unroll=2, schedule=1, stream=None, unit_batch=0):
+        c = _cfg(G, unroll, schedule, unit_batch)
         rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                     _stream(stream))
         if rc:
