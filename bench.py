@@ -25,6 +25,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def log(msg):
+    """Progress on stderr (the JSON result line goes to stdout)."""
+    print("[bench %7.1fs] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
+
+
+T_START = time.perf_counter()
+
+
 def header_counts(arc):
     h = np.frombuffer(arc[:128].tobytes(), dtype=np.uint64)
     return {"n_tok": int(h[4]), "n_x16": int(h[5]), "n_x32": int(h[6]), "n_lit": int(h[7])}
@@ -70,19 +78,24 @@ def run_fastq(args, torch, lz):
     import synth
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
+    log("generating %d B of FASTQ-like reads" % args.size)
     x = synth.fastq(args.size, seed=3)
     n = int(x.size)
-    log = {"gen_s": round(time.perf_counter() - t0, 2)}
+    gen = {"gen_s": round(time.perf_counter() - t0, 2)}
+    log("generated %d B" % n)
     res = {}
     for name, thr in (("base", lz.BASE_THR), ("tuned", lz.TUNED_THR)):
         t0 = time.perf_counter()
+        log("encoding %s %s" % (name, thr))
         arc = lz.encode(x, args.log2_bs, thr, lz.BOUNDS_CFG, max_chain=args.max_chain)
         enc_s = time.perf_counter() - t0
+        log("encoded %s: %d B archive in %.1fs" % (name, arc.size, enc_s))
         info = lz.archive_info(arc)
         ent, _ = lz.entropy_size(arc)
         t0 = time.perf_counter()
         da = lz.DeviceArchive(arc, device=dev)
         open_s = time.perf_counter() - t0
+        log("opened %s on the device in %.1fs (%d levels)" % (name, open_s, da.levels))
         out = torch.empty(n, dtype=torch.uint8, device=dev)
         mean_ms, med_ms, wall = time_decode(torch, da, out, args.G, args.unroll, args.schedule, args.warmup,
                                             args.steps)
@@ -91,6 +104,7 @@ def run_fastq(args, torch, lz):
         if not ok:
             raise SystemExit(f"{name}: GPU decode differs from the input")
         alg, tok_bytes = algorithmic_bytes(arc, info)
+        log("decoded %s: %.3f ms per decode, %.2f GB/s, bit-exact" % (name, mean_ms, n / mean_ms / 1e6))
         res[name] = {
             "arc": arc, "info": info, "mean_ms": mean_ms, "median_ms": med_ms, "wall_s": wall,
             "gbps": n / (mean_ms * 1e-3) / 1e9, "alg_bytes": alg, "tok_bytes": tok_bytes,
@@ -130,7 +144,7 @@ def run_fastq(args, torch, lz):
             "tuned_coverage": round(t["info"]["coverage"], 4), "base_coverage": round(b["info"]["coverage"], 4),
             "tuned_levels": t["levels"], "base_levels": b["levels"],
             "base_ms": round(b["mean_ms"], 4), "encode_s": [round(b["enc_s"], 2), round(t["enc_s"], 2)],
-            "bit_exact": True, **log,
+            "bit_exact": True, **gen,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -139,6 +153,7 @@ def run_fastq(args, torch, lz):
         },
     }
     if not args.no_cpu:
+        log("timing the CPU oracle decode")
         dt, out = cpu_oracle_time(t["arc"], n)
         assert np.array_equal(out, x)
         line["cpu_baseline"] = {"value": round(n / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",

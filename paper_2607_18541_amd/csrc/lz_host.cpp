@@ -18,6 +18,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <sys/mman.h>
+
 #include <algorithm>
 #include <atomic>
 #include <thread>
@@ -281,9 +283,37 @@ static int assemble(uint64_t n, uint32_t log2_bs, uint64_t min_match, const uint
 // Chain entry of position p: low 32 bits = previous position + 1 with the
 // same key hash (0 = none), high 32 bits = a fingerprint of p's key, so a walk
 // rejects hash collisions from the entry it already loaded.
+// Large arrays backed by 2 MiB pages where the kernel allows it: chain walks
+// touch entries at random across gigabytes, so small pages miss the TLB.
+template <class T>
+struct HugeArray {
+  T* p = nullptr;
+  size_t n = 0;
+  HugeArray() = default;
+  HugeArray(const HugeArray&) = delete;
+  HugeArray& operator=(const HugeArray&) = delete;
+  ~HugeArray() { release(); }
+  void release() {
+    if (p) munmap(p, bytes(n));
+    p = nullptr;
+    n = 0;
+  }
+  static size_t bytes(size_t k) { return ((k * sizeof(T)) + (2u << 20) - 1) & ~size_t((2u << 20) - 1); }
+  void assign_zero(size_t k) {
+    release();
+    void* q = mmap(nullptr, bytes(k), PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
+    if (q == MAP_FAILED) throw std::bad_alloc();
+    madvise(q, bytes(k), MADV_HUGEPAGE);
+    p = (T*)q;  // anonymous mappings start zeroed
+    n = k;
+  }
+  T& operator[](size_t i) { return p[i]; }
+  const T& operator[](size_t i) const { return p[i]; }
+};
+
 struct HashIndex {
-  uint32_t key = 4;             // bytes hashed
-  std::vector<uint64_t> prev;
+  uint32_t key = 4;  // bytes hashed
+  HugeArray<uint64_t> prev;
 };
 
 static inline uint64_t load_key(const uint8_t* p, uint32_t k) {
@@ -313,70 +343,73 @@ static inline uint64_t fingerprint(uint64_t v) {
   return (v & 0xFFFFFFFF00000000ull);
 }
 
-// Builds prev[] over positions [lo, hi) (sources and destinations stay in one
-// segment) for positions p with p + key <= hi, in parallel: each thread
-// chains its own range with a local head table, then ranges are stitched.
+// Builds the chain entries of positions [lo, hi) for p + key <= hi.  The head
+// table is split into S hash slices.  Pass 1 counts, per position range and
+// slice, the positions whose key hashes into the slice; pass 2 scatters the
+// positions into slice-major lists (each list stays in increasing position
+// order); pass 3 links every slice's positions in order with its own part of
+// the head table, so each chain is written by one thread, nearest-first links
+// come out in position order, and the table can be large without per-thread
+// copies.
 static void build_index(const uint8_t* x, uint64_t lo, uint64_t hi, uint32_t key, unsigned threads,
                         HashIndex& idx, int bits) {
-  uint64_t len = hi - lo;
   idx.key = key;
-  if (len < key + 8) {  // too short for 8-byte key loads: hash slowly
-    for (uint64_t p = lo; p + key <= hi; ++p) idx.prev[p] = 0;
-    std::vector<uint32_t> head(1u << bits, 0);
-    for (uint64_t p = lo; p + key <= hi; ++p) {
-      uint8_t tmp[16] = {0};
-      memcpy(tmp, x + p, key);
-      const uint64_t kv = load_key(tmp, key);
-      uint32_t h = hash_key(kv, bits);
-      idx.prev[p] = head[h] | fingerprint(kv);
-      head[h] = uint32_t(p - lo + 1);
-    }
-    return;
-  }
-  uint64_t last = hi - key;  // last hashable position (inclusive)
-  uint64_t cnt = last - lo + 1;
-  // keys read 8 or 16 bytes; positions too close to the end use a copy
+  if (hi - lo < key) return;
+  const uint64_t last = hi - key;  // last hashable position (inclusive)
+  const uint64_t cnt = last - lo + 1;
   auto key_at = [&](uint64_t p) -> uint64_t {
     if (p + 16 <= hi) return load_key(x + p, key);
     uint8_t tmp[16] = {0};
     memcpy(tmp, x + p, key);
     return load_key(tmp, key);
   };
-  unsigned T = (unsigned)std::min<uint64_t>(threads, std::max<uint64_t>(1, cnt / (1u << 20)));
-  if (T < 1) T = 1;
-  uint64_t step = (cnt + T - 1) / T;
-  std::vector<std::vector<uint32_t>> heads(T), firsts(T);
-  std::vector<std::thread> pool;
-  for (unsigned w = 0; w < T; ++w) {
-    pool.emplace_back([&, w] {
-      uint64_t a = lo + w * step, b = std::min<uint64_t>(lo + (w + 1) * step, last + 1);
-      auto& head = heads[w];
-      auto& first = firsts[w];
-      head.assign(size_t(1) << bits, 0);
-      first.assign(size_t(1) << bits, 0);
-      for (uint64_t p = a; p < b; ++p) {
-        const uint64_t kv = key_at(p);
-        uint32_t h = hash_key(kv, bits);
-        idx.prev[p] = head[h] | fingerprint(kv);
-        if (!head[h]) first[h] = uint32_t(p - lo + 1);
-        head[h] = uint32_t(p - lo + 1);
-      }
-    });
-  }
-  for (auto& t : pool) t.join();
-  // stitch: the first occurrence in range w links to the last one before it
-  std::vector<uint32_t> acc(size_t(1) << bits, 0);
-  for (unsigned w = 0; w < T; ++w) {
-    auto& first = firsts[w];
-    auto& head = heads[w];
-    for (size_t h = 0; h < acc.size(); ++h) {
-      if (first[h]) {
-        uint64_t& e = idx.prev[lo + first[h] - 1];
-        e = (e & 0xFFFFFFFF00000000ull) | acc[h];
-        acc[h] = head[h];
-      }
+  const unsigned T = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(threads, cnt >> 16));
+  const unsigned S = T;
+  const int sbits = bits;
+  auto slice_of = [&](uint32_t h) { return (unsigned)(((uint64_t)h * S) >> sbits); };
+  std::vector<uint64_t> count((size_t)T * S, 0), off((size_t)T * S, 0);
+  auto range = [&](unsigned r, uint64_t& a, uint64_t& b) {
+    a = lo + cnt * r / T;
+    b = lo + cnt * (r + 1) / T;
+  };
+  auto run = [&](auto&& body) {
+    std::vector<std::thread> pool;
+    for (unsigned w = 0; w < T; ++w) pool.emplace_back([&, w] { body(w); });
+    for (auto& t : pool) t.join();
+  };
+  run([&](unsigned r) {
+    uint64_t a, b;
+    range(r, a, b);
+    uint64_t* c = &count[(size_t)r * S];
+    for (uint64_t p = a; p < b; ++p) c[slice_of(hash_key(key_at(p), bits))]++;
+  });
+  uint64_t acc = 0;
+  for (unsigned sl = 0; sl < S; ++sl)
+    for (unsigned r = 0; r < T; ++r) {
+      off[(size_t)r * S + sl] = acc;
+      acc += count[(size_t)r * S + sl];
     }
-  }
+  HugeArray<uint32_t> list;
+  list.assign_zero(cnt);
+  run([&](unsigned r) {
+    uint64_t a, b;
+    range(r, a, b);
+    uint64_t* o = &off[(size_t)r * S];
+    for (uint64_t p = a; p < b; ++p) list[o[slice_of(hash_key(key_at(p), bits))]++] = uint32_t(p - lo);
+  });
+  HugeArray<uint32_t> head;
+  head.assign_zero(1ull << bits);
+  run([&](unsigned sl) {
+    const uint64_t b0 = (sl == 0) ? 0 : off[(size_t)(T - 1) * S + sl - 1];  // end of previous slice
+    const uint64_t b1 = off[(size_t)(T - 1) * S + sl];
+    for (uint64_t i = b0; i < b1; ++i) {
+      const uint64_t p = lo + list[i];
+      const uint64_t kv = key_at(p);
+      const uint32_t h = hash_key(kv, bits);
+      idx.prev[p] = head[h] | fingerprint(kv);
+      head[h] = uint32_t(p - lo + 1);
+    }
+  });
 }
 
 static inline uint64_t match_len(const uint8_t* x, uint64_t src, uint64_t pos, uint64_t end) {
@@ -415,6 +448,8 @@ static void parse_block(const EncCtx& c, uint64_t b, std::vector<BTok>& toks, st
   const uint32_t* thr = c.thr_block ? c.thr_block + 4 * b : c.p->thr;
   const uint64_t* bound = c.p->bound;
   uint32_t maxc = c.p->max_chain;
+  // with a chain limit the walk also stops at a match this long (exact mode never does)
+  const uint64_t nice = maxc ? 128 : UINT64_MAX;
   uint32_t kn = c.near_idx.key, kf = c.far_idx.key;
   uint64_t pos = start, run = 0;
   toks.clear();
@@ -448,14 +483,14 @@ static void parse_block(const EncCtx& c, uint64_t b, std::vector<BTok>& toks, st
         if (L >= thr[cl] && (L > best_len || (L == best_len && src > best_src))) {
           best_len = L;
           best_src = src;
-          if (pos + L == end) break;
+          if (pos + L == end || L >= nice) break;
         }
         if (maxc && ++steps >= maxc) break;
         link = uint32_t(e);
       }
     }
     // far chain: any distance
-    if (pos + kf <= end && best_len < end - pos) {
+    if (pos + kf <= end && best_len < end - pos && best_len < nice) {
       const uint64_t e0 = c.far_idx.prev[pos];
       const uint64_t fp = e0 & 0xFFFFFFFF00000000ull;
       uint32_t link = uint32_t(e0);
@@ -474,7 +509,7 @@ static void parse_block(const EncCtx& c, uint64_t b, std::vector<BTok>& toks, st
         if (L >= thr[cl] && (L > best_len || (L == best_len && src > best_src))) {
           best_len = L;
           best_src = src;
-          if (pos + L == end) break;
+          if (pos + L == end || L >= nice) break;
         }
         if (maxc && ++steps >= maxc) break;
         link = uint32_t(e);
@@ -528,8 +563,8 @@ static int encode_impl(const uint8_t* in, uint64_t n, const lz_params* p, const 
   std::vector<BlockEnc> blocks(nb);
   uint64_t seg = p->segment ? p->segment : std::max<uint64_t>(n, 1);
   int bits = 16;
-  while (bits < 24 && (1ull << bits) < std::min<uint64_t>(seg, n)) ++bits;
-  unsigned idx_threads = std::min(threads, 8u);
+  while (bits < 28 && (1ull << bits) < std::min<uint64_t>(seg, n)) ++bits;
+  unsigned idx_threads = threads;
   try {
     for (uint64_t s0 = 0; s0 < n; s0 += seg) {
       uint64_t s1 = std::min(n, s0 + seg);
@@ -541,8 +576,8 @@ static int encode_impl(const uint8_t* in, uint64_t n, const lz_params* p, const 
       c.p = p;
       c.thr_block = thr_block ? thr_block + 4 * (s0 / bs) : nullptr;
       c.seg = 0;
-      c.near_idx.prev.assign(s1 - s0 + 16, 0);
-      c.far_idx.prev.assign(s1 - s0 + 16, 0);
+      c.near_idx.prev.assign_zero(s1 - s0 + 16);
+      c.far_idx.prev.assign_zero(s1 - s0 + 16);
       build_index(c.x, 0, c.n, kn, idx_threads, c.near_idx, bits);
       build_index(c.x, 0, c.n, kf, idx_threads, c.far_idx, bits);
       uint64_t b0 = s0 / bs, b1 = (s1 + bs - 1) / bs;
