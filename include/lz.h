@@ -176,6 +176,35 @@ uint64_t lz_device_n(const lz_dev* h);
 uint32_t lz_device_levels(const lz_dev* h); /* number of levels (schedule 1) */
 void lz_device_close(lz_dev* h);
 
+/* ------------------------------------------------------------ range decode */
+
+/* Region seek on a device-resident archive (Abstract; Sec. 1 "Positioning":
+ * random access into compressed-resident data without whole-file decode).
+ * A plan covers `count` ranges [off[i], off[i]+len[i]): the host computes the
+ * token closure of each range (every token the range's bytes depend on through
+ * match sources), lays it out in output order in device scratch and orders
+ * its copies by dependency depth.  LZ_E_RANGE if a range leaves [0, n).  Plans
+ * are host objects; free with lz_range_plan_free after the stream that ran
+ * them has completed. */
+typedef struct lz_range_plan lz_range_plan;
+int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const uint64_t* len, lz_range_plan** plan);
+uint64_t lz_range_plan_scratch_bytes(const lz_range_plan* plan); /* device scratch lz_range_run needs */
+uint64_t lz_range_plan_levels(const lz_range_plan* plan);        /* match depths (launches) */
+uint64_t lz_range_plan_closure_bytes(const lz_range_plan* plan); /* decoded bytes incl. the ranges */
+void lz_range_plan_free(lz_range_plan* plan);
+
+/* Runs a plan on `stream`: range i is written to d_out[out_off[i], +len[i]),
+ * which must lie inside [d_out, d_out+out_cap); d_scratch holds at least
+ * lz_range_plan_scratch_bytes.  All ranges of the plan share each launch. */
+int lz_range_run(lz_dev* h, lz_range_plan* plan, uint8_t* d_out, uint64_t out_cap, const uint64_t* out_off,
+                 void* d_scratch, uint64_t scratch_cap, const lz_decode_cfg* cfg, void* stream);
+
+/* Single range: scratch bytes it needs, and a synchronous decode of
+ * [off, off+len) into d_out[0, len). */
+int lz_range_scratch_bytes(lz_dev* h, uint64_t off, uint64_t len, uint64_t* bytes);
+int lz_decode_range(lz_dev* h, uint64_t off, uint64_t len, uint8_t* d_out, void* d_scratch, uint64_t scratch_cap,
+                    void* stream);
+
 /* Pure-copy mode (Sec. 3.3, first control): executes pre-decoded tokens on the
  * device.  Token t (SoA, device arrays): copy lit_len[t] bytes from
  * d_lit[lit_off[t]..] to d_out[dst[t]..], then mlen[t] bytes from

@@ -44,7 +44,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -642,6 +644,15 @@ struct lz_dev {
     }
   };
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
+  // host copy of the archive and lazily parsed blocks (range planning)
+  std::vector<uint8_t> host_arc;
+  struct RTok {
+    uint64_t dst, lit_off, src;
+    uint32_t ll, ml;
+  };
+  std::vector<std::vector<RTok>> tok_cache;
+  std::vector<uint8_t> tok_cached;
+  std::mutex mu;
   ~lz_dev() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
   }
@@ -925,7 +936,15 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
   if (rc) return rc;
   lz_dev* h = new lz_dev();
   h->v = v;
-  h->v.base = nullptr;
+  try {
+    h->host_arc.assign(arc, arc + v.total);
+    h->tok_cache.resize(v.nb);
+    h->tok_cached.assign(v.nb, 0);
+  } catch (const std::bad_alloc&) {
+    delete h;
+    return lz::fail(LZ_E_NOMEM, "host archive copy failed");
+  }
+  h->v.base = h->host_arc.data();
   uint8_t* base = (uint8_t*)d_buf;
   h->d_arc = base + L.arc;
   h->d_done = (uint32_t*)(base + L.done);
@@ -1119,6 +1138,291 @@ int lz_purecopy_device(uint64_t ntok, const uint64_t* d_dst, const uint64_t* d_l
   hipLaunchKernelGGL(k, dim3((unsigned)grid_for(nunits, resident_groups(k, 256, G), G)), dim3(kWG), 0, s, A);
   HIPCHK(hipGetLastError());
   return 0;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ range decode
+//
+// Bytes [off, off+len) without a full decode (the region seek of Sec. 1 /
+// Sec. 6 on compressed-resident data).  Host: the token closure of the range
+// (tokens overlapping it, then, recursively, every token overlapping a source
+// interval of a needed token; a self-overlapping match needs its period only)
+// is laid out in output order in a scratch region, so any source interval of a
+// needed token is contiguous there.  Each needed token becomes a literal piece
+// (archive -> scratch) and a match piece (scratch -> scratch) whose depth is
+// one more than the deepest piece it reads.  Device: one pure-copy launch for
+// all literal pieces, one per match depth, and one gathering every range into
+// the caller's output arena.  Several ranges are merged depth by depth.
+
+struct lz_range_plan {
+  uint64_t count = 0;
+  std::vector<uint64_t> range_src;   // per range: scratch-data offset of byte off
+  std::vector<uint64_t> range_len;
+  uint64_t data_bytes = 0;           // scratch-data bytes
+  // pieces, level-major: level 0 = literal pieces, then match depths 1..D
+  std::vector<uint64_t> p_dst, p_lit_off, p_src;
+  std::vector<uint32_t> p_lit_len, p_mlen;
+  std::vector<uint64_t> lvl_piece;   // first piece of each level (D+2 entries)
+  uint64_t scratch_bytes = 0;        // total device scratch for lz_range_run
+  uint8_t* staging = nullptr;        // pinned copy of the piece arrays
+  uint64_t staging_bytes = 0;
+  ~lz_range_plan() {
+    if (staging) (void)hipHostFree(staging);
+  }
+};
+
+namespace {
+
+const std::vector<lz_dev::RTok>& block_tokens(lz_dev* h, uint64_t b) {
+  if (!h->tok_cached[b]) {
+    auto& o = h->tok_cache[b];
+    o.clear();
+    (void)lz::walk_block(h->v, b, [&](uint64_t, const lz::Tok& k) {
+      o.push_back(lz_dev::RTok{k.dst, k.lit_off, k.src, (uint32_t)k.lit_len, (uint32_t)k.mlen});
+    });
+    h->tok_cached[b] = 1;
+  }
+  return h->tok_cache[b];
+}
+
+struct NeedTok {
+  uint64_t dst, lit_off, src;
+  uint32_t ll, ml;
+  uint64_t scratch;  // scratch-data offset of dst
+  uint32_t level;    // match depth
+};
+
+// Token closure of [off, off+len): needed tokens sorted by dst.
+void closure(lz_dev* h, uint64_t off, uint64_t len, std::vector<NeedTok>& need) {
+  const uint32_t lb = h->v.log2_bs;
+  std::vector<std::pair<uint64_t, uint64_t>> work{{off, off + len}};
+  std::vector<std::vector<uint8_t>> seen(h->v.nb);
+  need.clear();
+  while (!work.empty()) {
+    auto [a, e] = work.back();
+    work.pop_back();
+    for (uint64_t b = a >> lb; a < e && b < h->v.nb; ++b) {
+      const auto& T = block_tokens(h, b);
+      auto& sb = seen[b];
+      if (sb.empty()) sb.assign(T.size(), 0);
+      // first token with dst + span > a
+      size_t i = std::upper_bound(T.begin(), T.end(), a, [](uint64_t x, const lz_dev::RTok& t) { return x < t.dst; }) -
+                 T.begin();
+      i = i ? i - 1 : 0;
+      const uint64_t bend = std::min(e, (b + 1) << lb);
+      for (; i < T.size() && T[i].dst < bend; ++i) {
+        const auto& t = T[i];
+        if (t.dst + t.ll + t.ml <= a || sb[i]) continue;
+        sb[i] = 1;
+        need.push_back(NeedTok{t.dst, t.lit_off, t.src, t.ll, t.ml, 0, 0});
+        if (t.ml) {
+          const uint64_t m0 = t.dst + t.ll;
+          work.push_back({t.src, std::min(t.src + t.ml, m0)});
+        }
+      }
+      a = (b + 1) << lb;
+    }
+  }
+  std::sort(need.begin(), need.end(), [](const NeedTok& x, const NeedTok& y) { return x.dst < y.dst; });
+}
+
+// Index of the needed token containing output position x (it exists).
+size_t find_need(const std::vector<NeedTok>& need, uint64_t x) {
+  size_t i = std::upper_bound(need.begin(), need.end(), x, [](uint64_t v, const NeedTok& t) { return v < t.dst; }) -
+             need.begin();
+  return i - 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const uint64_t* len, lz_range_plan** out) {
+  if (!h || !out || (count && (!off || !len))) return lz::fail(LZ_E_INVAL, "null argument");
+  *out = nullptr;
+  for (uint64_t r = 0; r < count; ++r)
+    if (off[r] > h->v.n || len[r] > h->v.n - off[r])
+      return lz::fail(LZ_E_RANGE, "range [%llu, +%llu) outside [0, %llu)", (unsigned long long)off[r],
+                      (unsigned long long)len[r], (unsigned long long)h->v.n);
+  std::lock_guard<std::mutex> lock(h->mu);
+  lz_range_plan* P = new lz_range_plan();
+  try {
+    P->count = count;
+    // per level: pieces, across ranges
+    std::vector<std::vector<std::array<uint64_t, 5>>> by_lvl(1);  // dst, lit_off, lit_len, src, mlen
+    std::vector<NeedTok> need;
+    uint64_t base = 0;
+    for (uint64_t r = 0; r < count; ++r) {
+      P->range_len.push_back(len[r]);
+      if (len[r] == 0) {
+        P->range_src.push_back(base);
+        continue;
+      }
+      closure(h, off[r], len[r], need);
+      uint64_t acc = 0;
+      for (auto& t : need) {
+        t.scratch = base + acc;
+        acc += (uint64_t)t.ll + t.ml;
+      }
+      // depths in output order: a match reads only earlier needed tokens
+      for (size_t k = 0; k < need.size(); ++k) {
+        NeedTok& t = need[k];
+        if (t.ll) by_lvl[0].push_back({t.scratch, t.lit_off, t.ll, 0, 0});
+        if (!t.ml) continue;
+        const uint64_t m0 = t.dst + t.ll;
+        const uint64_t se = std::min(t.src + t.ml, m0);
+        uint32_t d = 0;
+        for (size_t j = find_need(need, t.src); j < need.size() && need[j].dst < se; ++j) {
+          const NeedTok& u = need[j];
+          const uint64_t um0 = u.dst + u.ll;
+          if (um0 < se && um0 + u.ml > t.src && u.ml) d = std::max(d, u.level);  // overlaps u's match part
+        }
+        t.level = d + 1;
+        if (by_lvl.size() <= t.level) by_lvl.resize(t.level + 1);
+        const size_t j = find_need(need, t.src);
+        const uint64_t src_s = need[j].scratch + (t.src - need[j].dst);
+        by_lvl[t.level].push_back({t.scratch + t.ll, 0, 0, src_s, t.ml});
+      }
+      const size_t j = find_need(need, off[r]);
+      P->range_src.push_back(need[j].scratch + (off[r] - need[j].dst));
+      base += acc;
+    }
+    P->data_bytes = base;
+    P->lvl_piece.push_back(0);
+    for (auto& L : by_lvl) {
+      for (auto& q : L) {
+        P->p_dst.push_back(q[0]);
+        P->p_lit_off.push_back(q[1]);
+        P->p_lit_len.push_back((uint32_t)q[2]);
+        P->p_src.push_back(q[3]);
+        P->p_mlen.push_back((uint32_t)q[4]);
+      }
+      P->lvl_piece.push_back(P->p_dst.size());
+    }
+    // gather pieces: one per range, reading the scratch data as "literals"
+    for (uint64_t r = 0; r < count; ++r) {
+      P->p_dst.push_back(0);  // output offsets are given at run time
+      P->p_lit_off.push_back(P->range_src[r]);
+      P->p_lit_len.push_back((uint32_t)0);
+      P->p_src.push_back(0);
+      P->p_mlen.push_back(0);
+    }
+    P->lvl_piece.push_back(P->p_dst.size());
+  } catch (const std::bad_alloc&) {
+    delete P;
+    return lz::fail(LZ_E_NOMEM, "range plan allocation failed");
+  }
+  // staging layout: dst | lit_off | src (u64) | lit_len | mlen (u32) | unit starts (u64, one unit per piece)
+  const uint64_t np = P->p_dst.size();
+  auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  P->staging_bytes = a256(8 * np) * 3 + a256(4 * np) * 2 + a256(8 * (np + 1));
+  P->scratch_bytes = P->staging_bytes + a256(P->data_bytes + 16);
+  *out = P;
+  return 0;
+}
+
+uint64_t lz_range_plan_scratch_bytes(const lz_range_plan* P) { return P ? P->scratch_bytes : 0; }
+uint64_t lz_range_plan_levels(const lz_range_plan* P) { return P && P->lvl_piece.size() > 2 ? P->lvl_piece.size() - 3 : 0; }
+uint64_t lz_range_plan_closure_bytes(const lz_range_plan* P) { return P ? P->data_bytes : 0; }
+void lz_range_plan_free(lz_range_plan* P) { delete P; }
+
+int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, const uint64_t* out_off,
+                 void* d_scratch, uint64_t scratch_cap, const lz_decode_cfg* cfg, void* stream) {
+  if (!h || !P || (P->count && (!d_out || !out_off)) || !d_scratch) return lz::fail(LZ_E_INVAL, "null argument");
+  if (scratch_cap < P->scratch_bytes)
+    return lz::fail(LZ_E_NOMEM, "range scratch %llu < %llu bytes", (unsigned long long)scratch_cap,
+                    (unsigned long long)P->scratch_bytes);
+  for (uint64_t r = 0; r < P->count; ++r)
+    if (out_off[r] > out_cap || P->range_len[r] > out_cap - out_off[r])
+      return lz::fail(LZ_E_INVAL, "range %llu does not fit the output arena", (unsigned long long)r);
+  uint32_t G, U, sched;
+  int rc = resolve_cfg(cfg, G, U, sched);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t np = P->p_dst.size();
+  auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  // gather pieces take the caller's output offsets
+  for (uint64_t r = 0; r < P->count; ++r) {
+    P->p_dst[P->lvl_piece[P->lvl_piece.size() - 2] + r] = out_off[r];
+    P->p_lit_len[P->lvl_piece[P->lvl_piece.size() - 2] + r] = (uint32_t)P->range_len[r];
+  }
+  if (!P->staging && hipHostMalloc((void**)&P->staging, P->staging_bytes, 0) != hipSuccess) {
+    P->staging = nullptr;
+    return lz::fail(LZ_E_NOMEM, "pinned staging allocation failed");
+  }
+  uint8_t* st = P->staging;
+  uint64_t o = 0;
+  const uint64_t o_dst = o; memcpy(st + o, P->p_dst.data(), 8 * np); o += a256(8 * np);
+  const uint64_t o_loff = o; memcpy(st + o, P->p_lit_off.data(), 8 * np); o += a256(8 * np);
+  const uint64_t o_src = o; memcpy(st + o, P->p_src.data(), 8 * np); o += a256(8 * np);
+  const uint64_t o_llen = o; memcpy(st + o, P->p_lit_len.data(), 4 * np); o += a256(4 * np);
+  const uint64_t o_mlen = o; memcpy(st + o, P->p_mlen.data(), 4 * np); o += a256(4 * np);
+  const uint64_t o_units = o;
+  for (uint64_t i = 0; i <= np; ++i) ((uint64_t*)(st + o))[i] = i;  // one piece per unit
+  uint8_t* D = (uint8_t*)d_scratch;
+  HIPCHK(hipMemcpyAsync(D, st, P->staging_bytes, hipMemcpyHostToDevice, s));
+  uint8_t* data = D + P->staging_bytes;
+  KArgs A;
+  memset(&A, 0, sizeof(A));
+  A.p_dst = (const uint64_t*)(D + o_dst);
+  A.p_lit_off = (const uint64_t*)(D + o_loff);
+  A.p_src = (const uint64_t*)(D + o_src);
+  A.p_lit_len = (const uint32_t*)(D + o_llen);
+  A.p_mlen = (const uint32_t*)(D + o_mlen);
+  kfn_t k = pick_kernel<kModePure>(G, U);
+  const uint64_t res = resident_groups(k, h->cu_count, G);
+  const size_t L = P->lvl_piece.size() - 1;  // levels incl. literal and gather
+  for (size_t l = 0; l < L; ++l) {
+    const uint64_t p0 = P->lvl_piece[l], p1 = P->lvl_piece[l + 1];
+    if (p1 == p0) continue;
+    KArgs a = A;
+    a.p_unit = (const uint64_t*)(D + o_units) + p0;
+    a.nunits = p1 - p0;
+    const bool gather = (l + 1 == L);
+    if (l == 0) {  // literal pieces: archive literals -> scratch data
+      a.lit = h->d_arc + h->v.off_lit;
+      a.lit_lo = (uintptr_t)h->d_arc;
+      a.lit_hi = (uintptr_t)h->d_arc + h->v.total;
+      a.out = data;
+    } else if (gather) {  // scratch data -> caller's arena
+      a.lit = data;
+      a.lit_lo = (uintptr_t)data;
+      a.lit_hi = (uintptr_t)data + P->data_bytes + 16;
+      a.out = d_out;
+    } else {  // match pieces inside the scratch data
+      a.out = data;
+    }
+    a.msrc = data;
+    a.msrc_lo = (uintptr_t)data;
+    a.msrc_hi = (uintptr_t)data + P->data_bytes + 16;
+    hipLaunchKernelGGL(k, dim3((unsigned)grid_for(a.nunits, res, G)), dim3(kWG), 0, s, a);
+    HIPCHK(hipGetLastError());
+  }
+  return 0;
+}
+
+int lz_range_scratch_bytes(lz_dev* h, uint64_t off, uint64_t len, uint64_t* bytes) {
+  if (!bytes) return lz::fail(LZ_E_INVAL, "null output");
+  lz_range_plan* P = nullptr;
+  int rc = lz_range_plan_create(h, 1, &off, &len, &P);
+  if (rc) return rc;
+  *bytes = P->scratch_bytes;
+  delete P;
+  return 0;
+}
+
+int lz_decode_range(lz_dev* h, uint64_t off, uint64_t len, uint8_t* d_out, void* d_scratch, uint64_t scratch_cap,
+                    void* stream) {
+  lz_range_plan* P = nullptr;
+  int rc = lz_range_plan_create(h, 1, &off, &len, &P);
+  if (rc) return rc;
+  const uint64_t zero = 0;
+  rc = lz_range_run(h, P, d_out, len, &zero, d_scratch, scratch_cap, nullptr, stream);
+  // the plan's pinned staging is read by the copy engine: wait before freeing
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && rc == 0) rc = lz::fail(LZ_E_HIP, "stream sync failed");
+  delete P;
+  return rc;
 }
 
 }  // extern "C"

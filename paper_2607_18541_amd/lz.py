@@ -76,6 +76,14 @@ def lib():
             "lz_device_n": (_u64, [_vp]),
             "lz_device_levels": (_u32, [_vp]),
             "lz_device_close": (None, [_vp]),
+            "lz_range_plan_create": (ctypes.c_int, [_vp, _u64, _vp, _vp, ctypes.POINTER(_vp)]),
+            "lz_range_plan_scratch_bytes": (_u64, [_vp]),
+            "lz_range_plan_levels": (_u64, [_vp]),
+            "lz_range_plan_closure_bytes": (_u64, [_vp]),
+            "lz_range_plan_free": (None, [_vp]),
+            "lz_range_run": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
+            "lz_range_scratch_bytes": (ctypes.c_int, [_vp, _u64, _u64, _p64]),
+            "lz_decode_range": (ctypes.c_int, [_vp, _u64, _u64, _vp, _vp, _u64, _vp]),
             "lz_purecopy_device": (ctypes.c_int, [_u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp,
                                                   _u64, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
         }
@@ -261,6 +269,27 @@ class DeviceArchive:
         if rc:
             raise LzError(rc, "lz_device_check")
 
+    def range_plan(self, offs, lens):
+        """Host plan for ranges [offs[i], offs[i]+lens[i])."""
+        return RangePlan(self, offs, lens)
+
+    def decode_range(self, off, length, out=None, scratch=None, stream=None):
+        """Bytes [off, off+length) as a device tensor (synchronous)."""
+        import torch
+        sb = _u64()
+        rc = lib().lz_range_scratch_bytes(self.h, off, length, ctypes.byref(sb))
+        if rc:
+            raise LzError(rc, "lz_range_scratch_bytes")
+        if out is None:
+            out = torch.empty(max(length, 1), dtype=torch.uint8, device=self.buf.device)
+        if scratch is None or scratch.numel() < sb.value:
+            scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.buf.device)
+        rc = lib().lz_decode_range(self.h, off, length, ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(scratch.data_ptr()), scratch.numel(), _stream(stream))
+        if rc:
+            raise LzError(rc, "lz_decode_range")
+        return out[:length]
+
     def close(self):
         if getattr(self, "h", None):
             lib().lz_device_close(self.h)
@@ -298,3 +327,42 @@ def purecopy(dst, lit_off, lit_len, src, mlen, unit_start, lit, ref, out, G=32, 
                                   ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c), _stream(stream))
     if rc:
         raise LzError(rc, "lz_purecopy_device")
+
+
+class RangePlan:
+    """Merged plan of several ranges of one DeviceArchive (host object)."""
+
+    def __init__(self, da, offs, lens):
+        self.da = da
+        self.offs = np.ascontiguousarray(offs, dtype=np.uint64)
+        self.lens = np.ascontiguousarray(lens, dtype=np.uint64)
+        p = _vp()
+        rc = lib().lz_range_plan_create(da.h, self.offs.size, self.offs.ctypes.data, self.lens.ctypes.data,
+                                        ctypes.byref(p))
+        if rc:
+            raise LzError(rc, "lz_range_plan_create")
+        self.p = p
+        self.scratch_bytes = int(lib().lz_range_plan_scratch_bytes(p))
+        self.levels = int(lib().lz_range_plan_levels(p))
+        self.closure_bytes = int(lib().lz_range_plan_closure_bytes(p))
+
+    def run(self, out, out_offs, scratch, G=64, unroll=2, stream=None):
+        """Enqueues the plan; range i lands at out[out_offs[i]:+lens[i]]."""
+        oo = np.ascontiguousarray(out_offs, dtype=np.uint64)
+        c = _cfg(G, unroll, 0)
+        rc = lib().lz_range_run(self.da.h, self.p, ctypes.c_void_p(out.data_ptr()), out.numel(), oo.ctypes.data,
+                                ctypes.c_void_p(scratch.data_ptr()), scratch.numel(), ctypes.byref(c),
+                                _stream(stream))
+        if rc:
+            raise LzError(rc, "lz_range_run")
+
+    def free(self):
+        if getattr(self, "p", None):
+            lib().lz_range_plan_free(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,101 @@
+"""GPU range decode (region seek): every range equals the same bytes of the
+oracle's full decode, alone and merged into one multi-range plan."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2607_18541_amd import lz
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _ranges(n, bs, rng, k=40):
+    r = [(0, 1), (0, n), (n - 1, 1), (n - 7, 7), (bs - 3, 9), (2 * bs - 1, bs + 2), (n // 2, 0)]
+    for _ in range(k):
+        L = int(min(n, np.exp(rng.uniform(0, np.log(max(2, n // 4))))))
+        o = int(rng.integers(0, n - L + 1))
+        r.append((o, L))
+    return [(o, L) for o, L in r if 0 <= o and o + L <= n]
+
+
+def _check_archive(arc, expect, label, log2_bs):
+    dev = _dev()
+    da = lz.DeviceArchive(arc, device=dev)
+    n = da.n
+    rng = np.random.default_rng(len(expect))
+    rs = _ranges(n, 1 << log2_bs, rng)
+    exp_t = torch.from_numpy(np.ascontiguousarray(expect)).to(dev)
+    for o, L in rs:
+        print(f"[{label}] range {o} +{L}", flush=True)
+        got = da.decode_range(o, L)
+        torch.cuda.synchronize()
+        assert torch.equal(got, exp_t[o:o + L]), (label, o, L)
+    # all ranges merged into one plan, into one arena
+    offs = [o for o, L in rs]
+    lens = [L for o, L in rs]
+    plan = da.range_plan(offs, lens)
+    oo = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64) if lens else np.zeros(0, np.uint64)
+    out = torch.full((int(sum(lens)) + 8,), 0x5A, dtype=torch.uint8, device=dev)
+    scratch = torch.empty(plan.scratch_bytes, dtype=torch.uint8, device=dev)
+    plan.run(out, oo, scratch)
+    torch.cuda.synchronize()
+    for (o, L), q in zip(rs, oo):
+        assert torch.equal(out[int(q):int(q) + L], exp_t[o:o + L]), (label, "merged", o, L)
+    assert bool((out[int(sum(lens)):] == 0x5A).all().item())
+    plan.free()
+    da.close()
+
+
+@pytest.mark.parametrize("thr", [lz.BASE_THR, lz.TUNED_THR])
+def test_range_fastq(thr):
+    x = synth.fastq(6 << 20, seed=3)
+    arc = lz.encode(x, 16, thr)
+    _check_archive(arc, x, f"fastq{thr}", 16)
+
+
+def test_range_zipf_small_blocks():
+    x = synth.zipf_text(3 << 20, seed=2)
+    arc = lz.encode(x, 12, lz.BASE_THR)
+    _check_archive(arc, x, "zipf", 12)
+
+
+def test_range_generated_and_overlaps():
+    n = 2 << 20
+    ll, ml, sr, lit = synth.geo_tokens(n, 64, seed=4, lit_prefix=4096, min_back=1)
+    x = oracle.exec_tokens(n, ll, ml, sr, lit)
+    arc = lz.build_archive(n, 14, ll, ml, sr, lit)
+    _check_archive(arc, x, "geo-overlap", 14)
+    z = np.zeros(300_000, np.uint8)
+    z[::1000] = 7
+    _check_archive(lz.encode(z, 12, (4, 4, 4, 4)), z, "runs", 12)
+
+
+def test_range_errors():
+    dev = _dev()
+    x = synth.zipf_text(50_000, seed=1)
+    da = lz.DeviceArchive(lz.encode(x, 12), device=dev)
+    with pytest.raises(lz.LzError) as e:
+        da.decode_range(49_990, 11)
+    assert e.value.rc == lz.LZ_E_RANGE
+    with pytest.raises(lz.LzError):
+        da.range_plan([10, 60_000], [5, 1])
+    got = da.decode_range(49_990, 10)
+    assert bytes(got.cpu().numpy()) == bytes(x[49_990:])
+
+
+def test_range_closure_is_small_against_the_file():
+    """A 16 KiB seek decodes far less than the prefix before it."""
+    dev = _dev()
+    x = synth.fastq(8 << 20, seed=5)
+    da = lz.DeviceArchive(lz.encode(x, 16, lz.TUNED_THR), device=dev)
+    p = da.range_plan([6 << 20], [16 << 10])
+    assert p.closure_bytes < (1 << 20)
+    p.free()
