@@ -205,6 +205,40 @@ int lz_range_scratch_bytes(lz_dev* h, uint64_t off, uint64_t len, uint64_t* byte
 int lz_decode_range(lz_dev* h, uint64_t off, uint64_t len, uint8_t* d_out, void* d_scratch, uint64_t scratch_cap,
                     void* stream);
 
+/* ------------------------------------------------------------ batch decode */
+
+/* Many archives in one replayable launch sequence (one graph launch): work of
+ * all archives that share a configuration is merged into the same kernel
+ * launches (one parse launch, then one per dependency level, or one for
+ * schedule 0).  This is how small archives -- starved alone, Sec. 3.1/3.2 --
+ * fill the GPU.  Archive i decodes into d_out[i] (capacity out_cap[i]);
+ * cfgs[i] (NULL = defaults) selects its configuration.  d_scratch holds the
+ * merged work lists (lz_batch_scratch_bytes).  The batch records the handles'
+ * device buffers: an archive must not be decoded elsewhere while the batch
+ * runs. */
+typedef struct lz_batch lz_batch;
+int lz_batch_scratch_bytes(uint32_t count, lz_dev* const* handles, const lz_decode_cfg* cfgs, uint64_t* bytes);
+int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_out, const uint64_t* out_cap,
+                    const lz_decode_cfg* cfgs, void* d_scratch, uint64_t scratch_cap, void* stream, lz_batch** batch);
+int lz_batch_launch(lz_batch* batch, void* stream);
+uint64_t lz_batch_launches(const lz_batch* batch); /* kernel launches per replay */
+void lz_batch_destroy(lz_batch* batch);
+
+/* Autotuner: archives are bucketed by size (x4 buckets from 16 KiB); for each
+ * bucket every (G in {16,32,64}) x (unroll in {1,2,4}) x (schedule 1, 0) is
+ * timed with HIP events as a batch of that bucket alone (one warm-up, `reps`
+ * replays) and the fastest is written to chosen[i] for the bucket's archives.
+ * report (optional) receives one entry per non-empty bucket. */
+typedef struct lz_tune_report {
+  uint64_t min_bytes, max_bytes, bytes;
+  uint32_t archives;
+  lz_decode_cfg best;
+  float best_ms, default_ms; /* default: G 64, unroll 2, schedule 1 */
+} lz_tune_report;
+int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* const* d_out, const uint64_t* out_cap,
+                void* d_scratch, uint64_t scratch_cap, void* stream, uint32_t reps, lz_decode_cfg* chosen,
+                lz_tune_report* report, uint32_t report_cap, uint32_t* n_report);
+
 /* Pure-copy mode (Sec. 3.3, first control): executes pre-decoded tokens on the
  * device.  Token t (SoA, device arrays): copy lit_len[t] bytes from
  * d_lit[lit_off[t]..] to d_out[dst[t]..], then mlen[t] bytes from

@@ -67,9 +67,9 @@ constexpr uint64_t kSegTok = 256;  // tokens per parse segment
 constexpr uint64_t kIdleTicks = 500000000ull;  // 5 s of the 100 MHz clock without progress
 constexpr int kWG = 256;
 
-struct KArgs {
-  // archive streams (device)
-  const uint64_t* tab;
+// One archive and its output, as the kernels see it.
+struct ArcDesc {
+  const uint64_t* tab;  // block table
   const uint8_t* cmd;
   const uint16_t* x16;
   const uint32_t* x32;
@@ -78,23 +78,29 @@ struct KArgs {
   const uint8_t* lit;
   uintptr_t lit_lo, lit_hi;  // readable bounds for literal windows
   uint64_t n;
-  uint32_t log2_bs, nb, min_match;
-  // output and match-source bounds
+  uint32_t log2_bs, nb, min_match, pad;
   uint8_t* out;
   const uint8_t* msrc;  // base that match sources index (out, or ref in mode 2)
   uintptr_t msrc_lo, msrc_hi;
-  // parse segments: per segment {t_start, t_end, blk_t_end, pos, lit, x16, x32, blk}
-  const uint64_t* seg;
-  uint64_t nseg;
-  // plan and match table
   const uint32_t* slot;       // per token: match-table index, or kNone
-  u32x4* mtab;                // per match: {offset in block, length, src lo, src hi}
-  const uint32_t* unit_blk;   // per unit: block
-  const uint32_t* unit_lvl;   // per unit: level
-  const uint32_t* unit_next;  // per unit: the block's next level with a unit, or kNone
-  const uint32_t* unit_tok;   // per unit: first match-table index (n_units + 1 entries)
+  u32x4* mtab;                // per match: {dst lo, length, src lo, dst hi | src hi << 16}
   const uint32_t* first_lvl;  // per block: lowest level with a unit, or kNone
   uint32_t* done_lvl;         // per block, live during schedule 0
+};
+
+struct KArgs {
+  ArcDesc one;             // the archive of a single decode
+  const ArcDesc* arcs;     // batch: archive descriptors (null = single)
+  // parse segments: per segment {t_start, t_end, blk_t_end, pos, lit, x16, x32, archive << 32 | blk}
+  const uint64_t* seg;
+  uint64_t nseg;
+  // plan units
+  const uint32_t* unit_blk;      // per unit: block
+  const uint32_t* unit_arc;      // per unit: archive (batch only)
+  const uint32_t* unit_lvl;      // per unit: level
+  const uint32_t* unit_next;     // per unit: the block's next level with a unit, or kNone
+  const uint32_t* unit_tok;      // per unit: first match-table index
+  const uint32_t* unit_tok_end;  // per unit: end of its match-table range
   const uint32_t* lvl_start;  // first unit of each level (n_levels + 1 entries)
   uint32_t* tickets;          // per level: units taken so far (schedule 0)
   uint32_t* err;
@@ -292,10 +298,20 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
   const int gslot = threadIdx.x - gl;  // first LDS slot of this group
   const uint64_t ngroups = (uint64_t)gridDim.x * (kWG / G);
   const uint64_t gid = (uint64_t)blockIdx.x * (kWG / G) + threadIdx.x / G;
-  const uint64_t bs = 1ull << A.log2_bs;
-  const uintptr_t out_b = (uintptr_t)A.out;
-  const uint32_t out_cap32 = (uint32_t)min<uint64_t>(A.msrc_hi - A.msrc_lo, 0xFFFFFFFFull);
-  __amdgpu_buffer_rsrc_t out_r = __builtin_amdgcn_make_buffer_rsrc((void*)A.out, 0, (int)out_cap32, 0x00020000);
+  ArcDesc D = A.one;
+  uint64_t bs = 1ull << D.log2_bs;
+  uintptr_t out_b = (uintptr_t)D.out;
+  uint32_t out_cap32 = (uint32_t)min<uint64_t>(D.msrc_hi - D.msrc_lo, 0xFFFFFFFFull);
+  __amdgpu_buffer_rsrc_t out_r = __builtin_amdgcn_make_buffer_rsrc((void*)D.out, 0, (int)out_cap32, 0x00020000);
+  // switches the group to archive `aid` of a batch
+  auto use_arc = [&](uint32_t aid) {
+    if (!A.arcs) return;
+    D = A.arcs[aid];
+    bs = 1ull << D.log2_bs;
+    out_b = (uintptr_t)D.out;
+    out_cap32 = (uint32_t)min<uint64_t>(D.msrc_hi - D.msrc_lo, 0xFFFFFFFFull);
+    out_r = __builtin_amdgcn_make_buffer_rsrc((void*)D.out, 0, (int)out_cap32, 0x00020000);
+  };
 
   // work item state (replicated on the group's lanes)
   bool finished = false, have_item = false, started = false;
@@ -368,18 +384,20 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
           litc = e[4];
           xc = e[5];
           yc = e[6];
-          blk = e[7];
-          bend = min(A.n, (blk + 1) * bs);
-          if (gl == 0 && pos == blk * bs) A.done_lvl[blk] = A.first_lvl[blk];
+          use_arc((uint32_t)(e[7] >> 32));
+          blk = e[7] & 0xFFFFFFFFull;
+          bend = min(D.n, (blk + 1) * bs);
+          if (gl == 0 && pos == blk * bs) D.done_lvl[blk] = D.first_lvl[blk];
         } else if (MODE == kModePure) {
           t_next = A.p_unit[item];
           t_end = A.p_unit[item + 1];
         } else {
+          if (A.unit_arc) use_arc(A.unit_arc[ua]);
           const bool has_u = (uint64_t)gl < nu;
           u_blk = has_u ? A.unit_blk[ua + gl] : 0;
           u_next = has_u ? A.unit_next[ua + gl] : kNone;
           t_next = A.unit_tok[ua];
-          t_end = A.unit_tok[ua + nu];
+          t_end = A.unit_tok_end[ua + nu - 1];
         }
         started = (MODE != kModeFlow);
         l_len = m_len = m_done = 0;
@@ -398,7 +416,7 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
           // ---------------------------------------------- a unit waits for its own block's lower levels
           bool ok = true;
           if ((uint64_t)gl < nu)
-            ok = __hip_atomic_load(A.done_lvl + u_blk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= lvl;
+            ok = __hip_atomic_load(D.done_lvl + u_blk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= lvl;
           if (group_bits<G>(__ballot(!ok), gw) == 0) {
             started = true;
             progressed = true;
@@ -412,7 +430,7 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
             __builtin_amdgcn_s_waitcnt(0);
             compiler_barrier();
             if ((uint64_t)gl < nu)
-              __hip_atomic_store(A.done_lvl + u_blk, u_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              __hip_atomic_store(D.done_lvl + u_blk, u_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
           have_item = false;
           progressed = true;
@@ -428,25 +446,25 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
             m_src = valid ? A.p_src[t] : 0;
             m_dst = l_dst + l_len;
           } else if (MODE == kModeParse) {
-            const uint32_t c = valid ? A.cmd[t] : 0u;
+            const uint32_t c = valid ? D.cmd[t] : 0u;
             const bool last = (t + 1 == blk_t_end);
             const uint32_t Lc = c >> 4, Mc = c & 15u;
             const uint32_t need_l = (valid && Lc == 15u) ? 1u : 0u;
             const uint32_t need_m = (valid && !last && Mc == 15u) ? 1u : 0u;
             uint32_t tot16;
             const uint64_t i16 = xc + gscan32<G>(need_l + need_m, gl, tot16);
-            uint32_t e_l = need_l ? A.x16[i16] : 0u;
-            uint32_t e_m = need_m ? A.x16[i16 + need_l] : 0u;
+            uint32_t e_l = need_l ? D.x16[i16] : 0u;
+            uint32_t e_m = need_m ? D.x16[i16 + need_l] : 0u;
             const uint32_t w_l = (need_l && e_l == 0xFFFFu) ? 1u : 0u;
             const uint32_t w_m = (need_m && e_m == 0xFFFFu) ? 1u : 0u;
             uint32_t tot32;
             const uint64_t i32 = yc + gscan32<G>(w_l + w_m, gl, tot32);
-            if (w_l) e_l += A.x32[i32];
-            if (w_m) e_m += A.x32[i32 + w_l];
+            if (w_l) e_l += D.x32[i32];
+            if (w_m) e_m += D.x32[i32 + w_l];
             const uint32_t lit_len = (Lc == 15u) ? 15u + e_l : Lc;
-            uint32_t mlen = (valid && !last) ? A.min_match + ((Mc == 15u) ? 15u + e_m : Mc) : 0u;
-            uint64_t src = valid ? (uint64_t)A.slo[t] : 0;
-            if (A.shi && valid) src |= (uint64_t)A.shi[t] << 32;
+            uint32_t mlen = (valid && !last) ? D.min_match + ((Mc == 15u) ? 15u + e_m : Mc) : 0u;
+            uint64_t src = valid ? (uint64_t)D.slo[t] : 0;
+            if (D.shi && valid) src |= (uint64_t)D.shi[t] << 32;
             uint64_t lit_tot;
             const uint64_t loff = litc + gscan64<G>(lit_len, gl, lit_tot);
             uint64_t span_tot;
@@ -458,9 +476,9 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
             pos += span_tot;
             // record the match in plan order; only literal runs are copied here
             if (valid && mlen > 0) {
-              const uint32_t sl = A.slot[t];
+              const uint32_t sl = D.slot[t];
               const uint64_t md = tdst + lit_len;
-              A.mtab[sl] = u32x4{(uint32_t)md, mlen, (uint32_t)src,
+              D.mtab[sl] = u32x4{(uint32_t)md, mlen, (uint32_t)src,
                                  (uint32_t)((md >> 32) & 0xFFFFu) | (uint32_t)((src >> 32) << 16)};
             }
             l_dst = tdst;
@@ -469,7 +487,7 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
             m_len = 0;
           } else {
             // a unit's matches from the match table
-            u32x4 r = valid ? A.mtab[t] : u32x4{0u, 0u, 0u, 0u};
+            u32x4 r = valid ? D.mtab[t] : u32x4{0u, 0u, 0u, 0u};
             m_dst = (uint64_t)r.x | ((uint64_t)(r.w & 0xFFFFu) << 32);
             m_len = r.y;
             m_src = (uint64_t)r.z | ((uint64_t)(r.w >> 16) << 32);
@@ -492,7 +510,7 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
         // this batch (same-level matches of other blocks never feed it)
         bool hz = false;
         if (MODE != kModePure) {
-          const uint64_t own0 = (m_dst >> A.log2_bs) << A.log2_bs;
+          const uint64_t own0 = (m_dst >> D.log2_bs) << D.log2_bs;
           hz = piece > 0 && src_end > max(batch_start, own0);
         }
         const uint64_t hz_bits = group_bits<G>(__ballot(hz), gw);
@@ -503,13 +521,13 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
         // ------------------------------------------------ cross-block waits
         bool ready = true;
         if (MODE == kModeFlow) {
-          const uint64_t sb0 = m_src >> A.log2_bs;
-          const uint64_t sb1 = inc_m ? ((src_end - 1) >> A.log2_bs) : 0;
+          const uint64_t sb0 = m_src >> D.log2_bs;
+          const uint64_t sb1 = inc_m ? ((src_end - 1) >> D.log2_bs) : 0;
           if (inc_m) {
-            const uint64_t own = m_dst >> A.log2_bs;
+            const uint64_t own = m_dst >> D.log2_bs;
             for (uint64_t b = sb0; b <= sb1; ++b)
               if (b != own)
-                ready = ready && (__hip_atomic_load(A.done_lvl + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= lvl);
+                ready = ready && (__hip_atomic_load(D.done_lvl + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= lvl);
           }
           ready = group_bits<G>(__ballot(!ready), gw) == 0;
           compiler_barrier();  // output loads stay after the done_level loads
@@ -525,10 +543,10 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
           const uint32_t base = gscan32<G>(ca + cb, gl, C);
           Desc d;
           d.a_dst = a_dst;
-          d.a_src = (uintptr_t)A.lit + l_src;
+          d.a_src = (uintptr_t)D.lit + l_src;
           d.a_len = inc_l ? l_len : 0u;
           d.b_dst = b_dst;
-          d.b_src = (uintptr_t)A.msrc + m_src;
+          d.b_src = (uintptr_t)D.msrc + m_src;
           d.b_len = inc_m ? piece : 0u;
           d.base = base;
           d.ca = ca;
@@ -553,25 +571,25 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
                 }
                 const Desc& e = s_desc[gslot + a];
                 const uint32_t q = k - e.base;
-                uintptr_t D, S, lb, hb;
+                uintptr_t Dd, S, lb, hb;
                 uint32_t L, qq;
                 if (q < e.ca) {
-                  D = e.a_dst; S = e.a_src; L = e.a_len; qq = q;
-                  lb = A.lit_lo; hb = A.lit_hi;
+                  Dd = e.a_dst; S = e.a_src; L = e.a_len; qq = q;
+                  lb = D.lit_lo; hb = D.lit_hi;
                 } else {
-                  D = e.b_dst; S = e.b_src; L = e.b_len; qq = q - e.ca;
-                  lb = A.msrc_lo; hb = A.msrc_hi;
+                  Dd = e.b_dst; S = e.b_src; L = e.b_len; qq = q - e.ca;
+                  lb = D.msrc_lo; hb = D.msrc_hi;
                 }
-                const uintptr_t s0 = (D & ~(uintptr_t)15) + 16 * (uintptr_t)qq;
-                const intptr_t l0 = (intptr_t)D - (intptr_t)s0;
-                const intptr_t h0 = (intptr_t)(D + L) - (intptr_t)s0;
+                const uintptr_t s0 = (Dd & ~(uintptr_t)15) + 16 * (uintptr_t)qq;
+                const intptr_t l0 = (intptr_t)Dd - (intptr_t)s0;
+                const intptr_t h0 = (intptr_t)(Dd + L) - (intptr_t)s0;
                 lo[i] = l0 > 0 ? (int)l0 : 0;
                 hi[i] = h0 < 16 ? (int)h0 : 16;
                 slot[i] = s0;
                 if (kCoh && q >= e.ca)
-                  v[i] = coh_load_window(out_r, (int64_t)(S + (s0 - D) - out_b), out_cap32, lo[i], hi[i]);
+                  v[i] = coh_load_window(out_r, (int64_t)(S + (s0 - Dd) - out_b), out_cap32, lo[i], hi[i]);
                 else
-                  v[i] = load_window(S + (s0 - D), lb, hb, lo[i], hi[i]);
+                  v[i] = load_window(S + (s0 - Dd), lb, hb, lo[i], hi[i]);
               }
             }
 #pragma unroll
@@ -633,6 +651,9 @@ struct lz_dev {
   u32x4* d_mtab = nullptr;
   uint64_t n_units = 0, n_match = 0;
   std::vector<uint64_t> lvl_start;  // first unit of each level, n_levels + 1 entries
+  // host copies of the plan's work lists (batch decodes merge them)
+  std::vector<uint32_t> h_ublk, h_ulvl, h_unext, h_utok;
+  std::vector<uint64_t> h_seg;
   int cu_count = 0;
   // replayable launch sequences, one per (output, config)
   struct GraphKey {
@@ -829,31 +850,43 @@ int build_plan(const lz::ArcView& v, Plan& P) {
   return 0;
 }
 
+ArcDesc arc_desc(const lz_dev* h, uint8_t* out, uint64_t out_cap) {
+  ArcDesc d;
+  memset(&d, 0, sizeof(d));
+  const lz::ArcView& v = h->v;
+  d.tab = (const uint64_t*)(h->d_arc + v.off_tab);
+  d.cmd = h->d_arc + v.off_cmd;
+  d.x16 = (const uint16_t*)(h->d_arc + v.off_x16);
+  d.x32 = (const uint32_t*)(h->d_arc + v.off_x32);
+  d.slo = (const uint32_t*)(h->d_arc + v.off_slo);
+  d.shi = (v.flags & 1) ? h->d_arc + v.off_shi : nullptr;
+  d.lit = h->d_arc + v.off_lit;
+  d.lit_lo = (uintptr_t)h->d_arc;
+  d.lit_hi = (uintptr_t)h->d_arc + v.total;
+  d.n = v.n;
+  d.log2_bs = v.log2_bs;
+  d.nb = (uint32_t)v.nb;
+  d.min_match = (uint32_t)v.min_match;
+  d.out = out;
+  d.msrc = out;
+  d.msrc_lo = (uintptr_t)out;
+  d.msrc_hi = (uintptr_t)out + out_cap;
+  d.slot = h->d_slot;
+  d.mtab = h->d_mtab;
+  d.first_lvl = h->d_first;
+  d.done_lvl = h->d_done;
+  return d;
+}
+
 KArgs base_args(const lz_dev* h) {
   KArgs A;
   memset(&A, 0, sizeof(A));
-  const lz::ArcView& v = h->v;
-  A.tab = (const uint64_t*)(h->d_arc + v.off_tab);
-  A.cmd = h->d_arc + v.off_cmd;
-  A.x16 = (const uint16_t*)(h->d_arc + v.off_x16);
-  A.x32 = (const uint32_t*)(h->d_arc + v.off_x32);
-  A.slo = (const uint32_t*)(h->d_arc + v.off_slo);
-  A.shi = (v.flags & 1) ? h->d_arc + v.off_shi : nullptr;
-  A.lit = h->d_arc + v.off_lit;
-  A.lit_lo = (uintptr_t)h->d_arc;
-  A.lit_hi = (uintptr_t)h->d_arc + v.total;
-  A.n = v.n;
-  A.log2_bs = v.log2_bs;
-  A.nb = (uint32_t)v.nb;
-  A.min_match = (uint32_t)v.min_match;
-  A.slot = h->d_slot;
-  A.mtab = h->d_mtab;
+  A.one = arc_desc(h, nullptr, 0);
   A.unit_blk = h->d_ublk;
   A.unit_lvl = h->d_ulvl;
   A.unit_next = h->d_unext;
   A.unit_tok = h->d_utok;
-  A.first_lvl = h->d_first;
-  A.done_lvl = h->d_done;
+  A.unit_tok_end = h->d_utok + 1;
   A.lvl_start = h->d_lvls;
   A.tickets = h->d_tick;
   A.seg = h->d_seg;
@@ -963,6 +996,11 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
   h->n_units = P.ublk.size();
   h->n_match = P.n_match;
   h->lvl_start = P.lvl_start;
+  h->h_ublk = P.ublk;
+  h->h_ulvl = P.ulvl;
+  h->h_unext = P.unext;
+  h->h_utok = P.utok;
+  h->h_seg = P.seg;
   hipStream_t s = (hipStream_t)stream;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -1034,10 +1072,7 @@ int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decod
     }
   // build the launch sequence once: parse, then the match units
   KArgs A = base_args(h);
-  A.out = d_out;
-  A.msrc = d_out;
-  A.msrc_lo = (uintptr_t)d_out;
-  A.msrc_hi = (uintptr_t)d_out + out_cap;
+  A.one = arc_desc(h, d_out, out_cap);
   A.unit_batch = batch;
   struct Launch {
     kfn_t k;
@@ -1118,13 +1153,13 @@ int lz_purecopy_device(uint64_t ntok, const uint64_t* d_dst, const uint64_t* d_l
   if (nunits == 0) return 0;
   KArgs A;
   memset(&A, 0, sizeof(A));
-  A.lit = d_lit;
-  A.lit_lo = (uintptr_t)d_lit;
-  A.lit_hi = (uintptr_t)d_lit + lit_size;
-  A.out = d_out;
-  A.msrc = d_ref;
-  A.msrc_lo = (uintptr_t)d_ref;
-  A.msrc_hi = (uintptr_t)d_ref + ref_size;
+  A.one.lit = d_lit;
+  A.one.lit_lo = (uintptr_t)d_lit;
+  A.one.lit_hi = (uintptr_t)d_lit + lit_size;
+  A.one.out = d_out;
+  A.one.msrc = d_ref;
+  A.one.msrc_lo = (uintptr_t)d_ref;
+  A.one.msrc_hi = (uintptr_t)d_ref + ref_size;
   A.p_dst = d_dst;
   A.p_lit_off = d_lit_off;
   A.p_lit_len = d_lit_len;
@@ -1381,21 +1416,21 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
     a.nunits = p1 - p0;
     const bool gather = (l + 1 == L);
     if (l == 0) {  // literal pieces: archive literals -> scratch data
-      a.lit = h->d_arc + h->v.off_lit;
-      a.lit_lo = (uintptr_t)h->d_arc;
-      a.lit_hi = (uintptr_t)h->d_arc + h->v.total;
-      a.out = data;
+      a.one.lit = h->d_arc + h->v.off_lit;
+      a.one.lit_lo = (uintptr_t)h->d_arc;
+      a.one.lit_hi = (uintptr_t)h->d_arc + h->v.total;
+      a.one.out = data;
     } else if (gather) {  // scratch data -> caller's arena
-      a.lit = data;
-      a.lit_lo = (uintptr_t)data;
-      a.lit_hi = (uintptr_t)data + P->data_bytes + 16;
-      a.out = d_out;
+      a.one.lit = data;
+      a.one.lit_lo = (uintptr_t)data;
+      a.one.lit_hi = (uintptr_t)data + P->data_bytes + 16;
+      a.one.out = d_out;
     } else {  // match pieces inside the scratch data
-      a.out = data;
+      a.one.out = data;
     }
-    a.msrc = data;
-    a.msrc_lo = (uintptr_t)data;
-    a.msrc_hi = (uintptr_t)data + P->data_bytes + 16;
+    a.one.msrc = data;
+    a.one.msrc_lo = (uintptr_t)data;
+    a.one.msrc_hi = (uintptr_t)data + P->data_bytes + 16;
     hipLaunchKernelGGL(k, dim3((unsigned)grid_for(a.nunits, res, G)), dim3(kWG), 0, s, a);
     HIPCHK(hipGetLastError());
   }
@@ -1426,3 +1461,350 @@ int lz_decode_range(lz_dev* h, uint64_t off, uint64_t len, uint8_t* d_out, void*
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batch decode
+//
+// Thousands of archives in one replayable launch sequence: archives that share
+// a configuration form a group; a group is one parse launch over the parse
+// segments of all its archives and one launch per dependency level over the
+// level-p units of all its archives (or one launch for schedule 0).  Every
+// work item carries its archive index; the kernels read that archive's
+// streams, plan and output from a descriptor table.  All groups are recorded
+// in one graph.
+
+struct lz_batch {
+  hipGraphExec_t exec = nullptr;
+  uint64_t scratch_used = 0;
+  uint64_t launches = 0;
+  ~lz_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+
+namespace {
+
+struct BatchGroup {
+  lz_decode_cfg cfg;
+  std::vector<uint32_t> arcs;  // archive indices
+};
+
+uint64_t group_scratch(const std::vector<lz_dev*>& H, const BatchGroup& g, uint64_t* nseg_out, uint64_t* nu_out,
+                       uint64_t* nl_out) {
+  uint64_t nseg = 0, nu = 0, nl = 0;
+  for (uint32_t i : g.arcs) {
+    nseg += H[i]->h_seg.size() / 8;
+    nu += H[i]->h_ublk.size();
+    nl = std::max<uint64_t>(nl, H[i]->lvl_start.size() ? H[i]->lvl_start.size() - 1 : 0);
+  }
+  auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  if (nseg_out) *nseg_out = nseg;
+  if (nu_out) *nu_out = nu;
+  if (nl_out) *nl_out = nl;
+  return a256(sizeof(ArcDesc) * g.arcs.size()) + a256(64 * nseg) + 6 * a256(4 * (nu + 1)) + a256(4 * (nl + 1)) +
+         a256(4 * (nl + 1)) + 256;
+}
+
+std::vector<BatchGroup> make_groups(uint32_t count, const lz_decode_cfg* cfgs) {
+  std::vector<BatchGroup> groups;
+  for (uint32_t i = 0; i < count; ++i) {
+    lz_decode_cfg c{64, 2, 1, 0, 1};
+    if (cfgs) c = cfgs[i];
+    if (!c.G) c.G = 64;
+    if (!c.unroll) c.unroll = 2;
+    size_t k = 0;
+    for (; k < groups.size(); ++k)
+      if (groups[k].cfg.G == c.G && groups[k].cfg.unroll == c.unroll && groups[k].cfg.schedule == c.schedule) break;
+    if (k == groups.size()) groups.push_back(BatchGroup{c, {}});
+    groups[k].arcs.push_back(i);
+  }
+  return groups;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lz_batch_scratch_bytes(uint32_t count, lz_dev* const* handles, const lz_decode_cfg* cfgs, uint64_t* bytes) {
+  if (!bytes || (count && !handles)) return lz::fail(LZ_E_INVAL, "null argument");
+  std::vector<lz_dev*> H(handles, handles + count);
+  uint64_t tot = 0;
+  for (auto& g : make_groups(count, cfgs)) tot += group_scratch(H, g, nullptr, nullptr, nullptr);
+  *bytes = tot + 256;
+  return 0;
+}
+
+int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_out, const uint64_t* out_cap,
+                    const lz_decode_cfg* cfgs, void* d_scratch, uint64_t scratch_cap, void* stream, lz_batch** out) {
+  if (!out || (count && (!handles || !d_out || !out_cap)) || !d_scratch) return lz::fail(LZ_E_INVAL, "null argument");
+  *out = nullptr;
+  std::vector<lz_dev*> H(handles, handles + count);
+  for (uint32_t i = 0; i < count; ++i) {
+    if (!H[i]) return lz::fail(LZ_E_INVAL, "null handle %u", i);
+    if (out_cap[i] < H[i]->v.n) return lz::fail(LZ_E_INVAL, "output %u too small", i);
+    if (H[i]->v.n && !d_out[i]) return lz::fail(LZ_E_INVAL, "null output %u", i);
+  }
+  auto groups = make_groups(count, cfgs);
+  uint64_t need = 256;
+  for (auto& g : groups) {
+    uint32_t G, U, sched;
+    int rc = resolve_cfg(&g.cfg, G, U, sched);
+    if (rc) return rc;
+    if (sched == 0)
+      for (uint32_t i : g.arcs)
+        if (out_cap[i] > 0xFFFFFFFFull) return lz::fail(LZ_E_INVAL, "schedule 0 outputs must be below 4 GiB");
+    need += group_scratch(H, g, nullptr, nullptr, nullptr);
+  }
+  if (scratch_cap < need)
+    return lz::fail(LZ_E_NOMEM, "batch scratch %llu < %llu bytes", (unsigned long long)scratch_cap,
+                    (unsigned long long)need);
+  auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  hipStream_t s = (hipStream_t)stream;
+  // host images of every group's tables, uploaded in one copy
+  std::vector<uint8_t> img(need, 0);
+  uint8_t* D0 = (uint8_t*)d_scratch;
+  struct Launch {
+    kfn_t k;
+    uint64_t grid;
+    KArgs a;
+  };
+  std::vector<Launch> seq;
+  uint64_t off = 0;
+  int cu = 0;
+  for (lz_dev* h : H) cu = std::max(cu, h->cu_count);
+  for (auto& g : groups) {
+    uint32_t G, U, sched;
+    (void)resolve_cfg(&g.cfg, G, U, sched);
+    uint64_t nseg, nu, nl;
+    group_scratch(H, g, &nseg, &nu, &nl);
+    const uint64_t o_desc = off;
+    const uint64_t o_seg = o_desc + a256(sizeof(ArcDesc) * g.arcs.size());
+    const uint64_t o_ublk = o_seg + a256(64 * nseg);
+    const uint64_t o_uarc = o_ublk + a256(4 * (nu + 1));
+    const uint64_t o_ulvl = o_uarc + a256(4 * (nu + 1));
+    const uint64_t o_unext = o_ulvl + a256(4 * (nu + 1));
+    const uint64_t o_utok = o_unext + a256(4 * (nu + 1));
+    const uint64_t o_utend = o_utok + a256(4 * (nu + 1));
+    const uint64_t o_lvls = o_utend + a256(4 * (nu + 1));
+    const uint64_t o_tick = o_lvls + a256(4 * (nl + 1));
+    const uint64_t o_err = o_tick + a256(4 * (nl + 1));
+    off = o_err + 256;
+    ArcDesc* desc = (ArcDesc*)(img.data() + o_desc);
+    uint64_t* seg = (uint64_t*)(img.data() + o_seg);
+    uint32_t *ublk = (uint32_t*)(img.data() + o_ublk), *uarc = (uint32_t*)(img.data() + o_uarc);
+    uint32_t *ulvl = (uint32_t*)(img.data() + o_ulvl), *unext = (uint32_t*)(img.data() + o_unext);
+    uint32_t *utok = (uint32_t*)(img.data() + o_utok), *utend = (uint32_t*)(img.data() + o_utend);
+    uint32_t* lvls = (uint32_t*)(img.data() + o_lvls);
+    uint64_t si = 0;
+    for (uint32_t j = 0; j < g.arcs.size(); ++j) {
+      lz_dev* h = H[g.arcs[j]];
+      desc[j] = arc_desc(h, d_out[g.arcs[j]], out_cap[g.arcs[j]]);
+      for (size_t r = 0; r + 8 <= h->h_seg.size(); r += 8) {
+        for (int w = 0; w < 7; ++w) seg[8 * si + w] = h->h_seg[r + w];
+        seg[8 * si + 7] = ((uint64_t)j << 32) | (h->h_seg[r + 7] & 0xFFFFFFFFull);
+        ++si;
+      }
+    }
+    // units of all archives, level-major
+    uint64_t ui = 0;
+    for (uint64_t p = 0; p < nl; ++p) {
+      lvls[p] = (uint32_t)ui;
+      for (uint32_t j = 0; j < g.arcs.size(); ++j) {
+        lz_dev* h = H[g.arcs[j]];
+        if (p + 1 >= h->lvl_start.size()) continue;
+        for (uint64_t u = h->lvl_start[p]; u < h->lvl_start[p + 1]; ++u, ++ui) {
+          ublk[ui] = h->h_ublk[u];
+          uarc[ui] = j;
+          ulvl[ui] = h->h_ulvl[u];
+          unext[ui] = h->h_unext[u];
+          utok[ui] = h->h_utok[u];
+          utend[ui] = h->h_utok[u + 1];
+        }
+      }
+    }
+    lvls[nl] = (uint32_t)ui;
+    KArgs A;
+    memset(&A, 0, sizeof(A));
+    A.arcs = (const ArcDesc*)(D0 + o_desc);
+    A.one = desc[0];
+    A.seg = (const uint64_t*)(D0 + o_seg);
+    A.nseg = nseg;
+    A.unit_blk = (const uint32_t*)(D0 + o_ublk);
+    A.unit_arc = (const uint32_t*)(D0 + o_uarc);
+    A.unit_lvl = (const uint32_t*)(D0 + o_ulvl);
+    A.unit_next = (const uint32_t*)(D0 + o_unext);
+    A.unit_tok = (const uint32_t*)(D0 + o_utok);
+    A.unit_tok_end = (const uint32_t*)(D0 + o_utend);
+    A.lvl_start = (const uint32_t*)(D0 + o_lvls);
+    A.tickets = (uint32_t*)(D0 + o_tick);
+    A.err = (uint32_t*)(D0 + o_err);
+    A.n_levels = (uint32_t)nl;
+    A.unit_batch = 1;
+    if (nseg) {
+      kfn_t kp = pick_kernel<kModeParse>(G, U);
+      seq.push_back({kp, grid_for(nseg, resident_groups(kp, cu, G), G), A});
+    }
+    if (nu) {
+      if (sched == 0) {
+        kfn_t k = pick_kernel<kModeFlow>(G, U);
+        KArgs a = A;
+        a.unit_lo = 0;
+        a.unit_hi = nu;
+        seq.push_back({k, grid_for(nu, resident_groups(k, cu, G), G), a});
+      } else {
+        kfn_t k = pick_kernel<kModeLevels>(G, U);
+        const uint64_t res = resident_groups(k, cu, G);
+        for (uint64_t p = 0; p < nl; ++p) {
+          KArgs a = A;
+          a.unit_lo = lvls[p];
+          a.unit_hi = lvls[p + 1];
+          if (a.unit_hi == a.unit_lo) continue;
+          seq.push_back({k, grid_for(a.unit_hi - a.unit_lo, res, G), a});
+        }
+      }
+    }
+  }
+  // upload the tables (pinned staging), then record the launches
+  uint8_t* hp = nullptr;
+  if (hipHostMalloc((void**)&hp, off ? off : 1, 0) != hipSuccess) return lz::fail(LZ_E_NOMEM, "pinned staging failed");
+  memcpy(hp, img.data(), off);
+  hipError_t e1 = hipMemcpyAsync(D0, hp, off, hipMemcpyHostToDevice, s);
+  hipError_t e2 = hipStreamSynchronize(s);
+  (void)hipHostFree(hp);
+  if (e1 != hipSuccess || e2 != hipSuccess) return lz::fail(LZ_E_HIP, "batch table upload failed");
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipGraphCreate(&graph, 0));
+  hipGraphNode_t prev = nullptr;
+  for (Launch& L : seq) {
+    hipKernelNodeParams kp2;
+    memset(&kp2, 0, sizeof(kp2));
+    void* args[] = {&L.a};
+    kp2.func = (void*)L.k;
+    kp2.gridDim = dim3((unsigned)L.grid);
+    kp2.blockDim = dim3(kWG);
+    kp2.kernelParams = args;
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp2);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return lz::fail(LZ_E_HIP, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+    }
+    prev = node;
+  }
+  lz_batch* B = new lz_batch();
+  hipError_t e = hipGraphInstantiate(&B->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    delete B;
+    return lz::fail(LZ_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  B->scratch_used = off;
+  B->launches = seq.size();
+  *out = B;
+  return 0;
+}
+
+int lz_batch_launch(lz_batch* b, void* stream) {
+  if (!b || !b->exec) return lz::fail(LZ_E_INVAL, "null batch");
+  HIPCHK(hipGraphLaunch(b->exec, (hipStream_t)stream));
+  return 0;
+}
+
+uint64_t lz_batch_launches(const lz_batch* b) { return b ? b->launches : 0; }
+void lz_batch_destroy(lz_batch* b) { delete b; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ autotuner
+//
+// Archives are bucketed by size (factor-4 buckets from 4 KiB).  For every
+// bucket each candidate (G, unroll, schedule) is built as a batch of that
+// bucket's archives alone and timed with HIP events over `reps` graph
+// launches after one warm-up; the fastest candidate becomes the configuration
+// of every archive in the bucket.
+
+extern "C" int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* const* d_out, const uint64_t* out_cap,
+                           void* d_scratch, uint64_t scratch_cap, void* stream, uint32_t reps, lz_decode_cfg* chosen,
+                           lz_tune_report* report, uint32_t report_cap, uint32_t* n_report) {
+  if ((count && (!handles || !d_out || !out_cap || !chosen)) || !d_scratch) return lz::fail(LZ_E_INVAL, "null argument");
+  if (reps == 0) reps = 3;
+  hipStream_t s = (hipStream_t)stream;
+  auto bucket_of = [&](uint64_t n) {
+    int b = 0;
+    uint64_t lim = 16384;
+    while (n >= lim && b < 15) {
+      lim <<= 2;
+      ++b;
+    }
+    return b;
+  };
+  std::vector<std::vector<uint32_t>> buckets(16);
+  for (uint32_t i = 0; i < count; ++i) buckets[bucket_of(handles[i]->v.n)].push_back(i);
+  static const uint32_t Gs[3] = {16, 32, 64}, Us[3] = {1, 2, 4}, Ss[2] = {1, 0};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  uint32_t nrep = 0;
+  int rc = 0;
+  for (int b = 0; b < 16 && rc == 0; ++b) {
+    auto& idx = buckets[b];
+    if (idx.empty()) continue;
+    std::vector<lz_dev*> H;
+    std::vector<uint8_t*> O;
+    std::vector<uint64_t> C;
+    uint64_t bytes = 0;
+    for (uint32_t i : idx) {
+      H.push_back(handles[i]);
+      O.push_back(d_out[i]);
+      C.push_back(out_cap[i]);
+      bytes += handles[i]->v.n;
+    }
+    lz_decode_cfg best{64, 2, 1, 0, 1};
+    float best_ms = 1e30f, default_ms = -1.f;
+    for (uint32_t S : Ss)
+      for (uint32_t G : Gs)
+        for (uint32_t U : Us) {
+          lz_decode_cfg c{G, U, S, 0, 1};
+          bool too_big = false;
+          if (S == 0)
+            for (uint64_t cap : C) too_big = too_big || cap > 0xFFFFFFFFull;
+          if (too_big) continue;
+          std::vector<lz_decode_cfg> cf(idx.size(), c);
+          lz_batch* B = nullptr;
+          rc = lz_batch_create((uint32_t)idx.size(), H.data(), O.data(), C.data(), cf.data(), d_scratch, scratch_cap,
+                               stream, &B);
+          if (rc) break;
+          float ms = 0;
+          rc = lz_batch_launch(B, stream);
+          if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = lz::fail(LZ_E_HIP, "event record failed");
+          for (uint32_t r = 0; r < reps && !rc; ++r) rc = lz_batch_launch(B, stream);
+          if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                      hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = lz::fail(LZ_E_HIP, "event timing failed");
+          lz_batch_destroy(B);
+          if (rc) break;
+          ms /= (float)reps;
+          if (G == 64 && U == 2 && S == 1) default_ms = ms;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+          }
+        }
+    if (rc) break;
+    for (uint32_t i : idx) chosen[i] = best;
+    if (report && nrep < report_cap) {
+      lz_tune_report& R = report[nrep];
+      R.min_bytes = (b == 0) ? 0 : (16384ull << (2 * (b - 1)));
+      R.max_bytes = 16384ull << (2 * b);
+      R.archives = (uint32_t)idx.size();
+      R.bytes = bytes;
+      R.best = best;
+      R.best_ms = best_ms;
+      R.default_ms = default_ms;
+    }
+    ++nrep;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (n_report) *n_report = nrep;
+  return rc;
+}

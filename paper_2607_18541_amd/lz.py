@@ -50,6 +50,11 @@ class DecodeCfg(ctypes.Structure):
     _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("wg_size", _u32), ("unit_batch", _u32)]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("min_bytes", _u64), ("max_bytes", _u64), ("bytes", _u64), ("archives", _u32),
+                ("best", DecodeCfg), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float)]
+
+
 def lib():
     global _LIB
     if _LIB is None:
@@ -84,6 +89,13 @@ def lib():
             "lz_range_run": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
             "lz_range_scratch_bytes": (ctypes.c_int, [_vp, _u64, _u64, _p64]),
             "lz_decode_range": (ctypes.c_int, [_vp, _u64, _u64, _vp, _vp, _u64, _vp]),
+            "lz_batch_scratch_bytes": (ctypes.c_int, [_u32, _vp, _vp, _p64]),
+            "lz_batch_create": (ctypes.c_int, [_u32, _vp, _vp, _vp, _vp, _vp, _u64, _vp, ctypes.POINTER(_vp)]),
+            "lz_batch_launch": (ctypes.c_int, [_vp, _vp]),
+            "lz_batch_launches": (_u64, [_vp]),
+            "lz_batch_destroy": (None, [_vp]),
+            "lz_autotune": (ctypes.c_int, [_u32, _vp, _vp, _vp, _vp, _u64, _vp, _u32, _vp, _vp, _u32,
+                                           ctypes.POINTER(_u32)]),
             "lz_purecopy_device": (ctypes.c_int, [_u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp,
                                                   _u64, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
         }
@@ -366,3 +378,91 @@ class RangePlan:
             self.free()
         except Exception:
             pass
+
+
+def _ptr_array(vals):
+    arr = (ctypes.c_void_p * max(len(vals), 1))()
+    for i, v in enumerate(vals):
+        arr[i] = v
+    return arr
+
+
+def _cfg_array(cfgs):
+    arr = (DecodeCfg * max(len(cfgs), 1))()
+    for i, c in enumerate(cfgs):
+        if isinstance(c, DecodeCfg):
+            arr[i] = c
+        else:
+            G, U, S = c
+            arr[i] = _cfg(G, U, S)
+    return arr
+
+
+class Batch:
+    """One replayable launch sequence decoding many DeviceArchives; archive i
+    into outs[i] (torch tensors).  cfgs: None, or per archive a DecodeCfg or a
+    (G, unroll, schedule) tuple."""
+
+    def __init__(self, archives, outs, cfgs=None, stream=None):
+        import torch
+        self.archives = archives
+        self.outs = outs
+        hs = _ptr_array([a.h.value for a in archives])
+        cf = None if cfgs is None else _cfg_array(cfgs)
+        sb = _u64()
+        rc = lib().lz_batch_scratch_bytes(len(archives), hs, cf, ctypes.byref(sb))
+        if rc:
+            raise LzError(rc, "lz_batch_scratch_bytes")
+        dev = archives[0].buf.device if archives else torch.device("cuda")
+        self.scratch = torch.empty(max(sb.value, 256), dtype=torch.uint8, device=dev)
+        op = _ptr_array([o.data_ptr() for o in outs])
+        caps = np.array([o.numel() for o in outs], dtype=np.uint64)
+        b = _vp()
+        rc = lib().lz_batch_create(len(archives), hs, op, caps.ctypes.data, cf, ctypes.c_void_p(self.scratch.data_ptr()),
+                                   self.scratch.numel(), _stream(stream), ctypes.byref(b))
+        if rc:
+            raise LzError(rc, "lz_batch_create")
+        self.b = b
+        self.launches = int(lib().lz_batch_launches(b))
+
+    def launch(self, stream=None):
+        rc = lib().lz_batch_launch(self.b, _stream(stream))
+        if rc:
+            raise LzError(rc, "lz_batch_launch")
+
+    def destroy(self):
+        if getattr(self, "b", None):
+            lib().lz_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def autotune(archives, outs, reps=3, stream=None):
+    """Per-archive configuration chosen per size bucket; returns (cfgs, report)."""
+    import torch
+    n = len(archives)
+    hs = _ptr_array([a.h.value for a in archives])
+    sb = _u64()
+    rc = lib().lz_batch_scratch_bytes(n, hs, None, ctypes.byref(sb))
+    if rc:
+        raise LzError(rc, "lz_batch_scratch_bytes")
+    scratch = torch.empty(max(sb.value, 256), dtype=torch.uint8, device=archives[0].buf.device)
+    op = _ptr_array([o.data_ptr() for o in outs])
+    caps = np.array([o.numel() for o in outs], dtype=np.uint64)
+    chosen = (DecodeCfg * max(n, 1))()
+    rep = (TuneReport * 16)()
+    nrep = _u32()
+    rc = lib().lz_autotune(n, hs, op, caps.ctypes.data, ctypes.c_void_p(scratch.data_ptr()), scratch.numel(),
+                           _stream(stream), reps, chosen, rep, 16, ctypes.byref(nrep))
+    if rc:
+        raise LzError(rc, "lz_autotune")
+    cfgs = [(chosen[i].G, chosen[i].unroll, chosen[i].schedule) for i in range(n)]
+    report = [{"min_bytes": rep[i].min_bytes, "max_bytes": rep[i].max_bytes, "archives": rep[i].archives,
+               "bytes": rep[i].bytes, "best": (rep[i].best.G, rep[i].best.unroll, rep[i].best.schedule),
+               "best_ms": rep[i].best_ms, "default_ms": rep[i].default_ms} for i in range(nrep.value)]
+    return cfgs, report

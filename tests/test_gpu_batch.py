@@ -1,0 +1,86 @@
+"""Batched decode of many uneven archives in one graph launch: every archive's
+bytes equal its solo decode and the oracle; the autotuner's choices decode
+bit-exactly too."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2607_18541_amd import lz
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _mixed_archives(k, seed):
+    sizes = synth.loguniform(k, 4096, 2 << 20, seed)
+    arcs, inputs = [], []
+    for i, n in enumerate(sizes):
+        n = int(n)
+        if i % 3 == 0:
+            x = synth.zipf_text(n, seed=seed * 1000 + i)
+        elif i % 3 == 1:
+            x = synth.fastq(n, seed=seed * 1000 + i)
+        else:
+            ll, ml, sr, lit = synth.geo_tokens(n, 64, seed=seed * 1000 + i, lit_prefix=min(4096, n), min_back=1)
+            x = oracle.exec_tokens(n, ll, ml, sr, lit)
+        thr = (lz.BASE_THR, lz.TUNED_THR)[i % 2]
+        lb = (12, 14, 16)[i % 3]
+        if i % 3 == 2:
+            arc = lz.build_archive(x.size, lb, ll, ml, sr, lit)
+        else:
+            arc = lz.encode(x, lb, thr)
+        arcs.append(arc)
+        inputs.append(x)
+    return arcs, inputs
+
+
+@pytest.mark.parametrize("mix", ["default", "mixed", "flow"])
+def test_batch_equals_solo(mix):
+    dev = _dev()
+    arcs, inputs = _mixed_archives(60, 7)
+    das = [lz.DeviceArchive(a, device=dev) for a in arcs]
+    outs = [torch.full((max(d.n, 1) + 16,), 0xEE, dtype=torch.uint8, device=dev) for d in das]
+    if mix == "default":
+        cfgs = None
+    elif mix == "mixed":
+        cfgs = [((16, 32, 64)[i % 3], (1, 2, 4)[i % 3], i % 2) for i in range(len(das))]
+    else:
+        cfgs = [(32, 2, 0)] * len(das)
+    print(f"[batch {mix}] {len(das)} archives", flush=True)
+    b = lz.Batch(das, outs, cfgs)
+    for rep in range(2):
+        b.launch()
+        torch.cuda.synchronize()
+        for i, (d, x) in enumerate(zip(das, inputs)):
+            got = outs[i][:d.n].cpu().numpy()
+            assert np.array_equal(got, x), (mix, rep, i, d.n)
+            assert bool((outs[i][d.n:] == 0xEE).all().item())
+    # equal to the solo decode of the same archive
+    for i in (0, 1, 2, len(das) - 1):
+        solo = das[i].decode()
+        assert torch.equal(solo, outs[i][:das[i].n])
+    b.destroy()
+
+
+def test_autotune_choices_decode_exactly():
+    dev = _dev()
+    arcs, inputs = _mixed_archives(24, 11)
+    das = [lz.DeviceArchive(a, device=dev) for a in arcs]
+    outs = [torch.empty(max(d.n, 1), dtype=torch.uint8, device=dev) for d in das]
+    cfgs, report = lz.autotune(das, outs, reps=1)
+    assert len(report) >= 2 and sum(r["archives"] for r in report) == len(das)
+    for r in report:
+        assert r["best_ms"] <= r["default_ms"] * 1.0001
+    b = lz.Batch(das, outs, cfgs)
+    b.launch()
+    torch.cuda.synchronize()
+    for i, (d, x) in enumerate(zip(das, inputs)):
+        assert np.array_equal(outs[i][:d.n].cpu().numpy(), x), i
+    b.destroy()
