@@ -239,6 +239,28 @@ int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* const* d_out, c
                 void* d_scratch, uint64_t scratch_cap, void* stream, uint32_t reps, lz_decode_cfg* chosen,
                 lz_tune_report* report, uint32_t report_cap, uint32_t* n_report);
 
+/* ------------------------------------------------------------ serving */
+
+/* Continuous batching of region-seek requests on one device-resident archive
+ * (Sec. 1 "Positioning": compressed residency with sub-millisecond seek).
+ * Requests queue in arrival order.  lz_serve_tick retires finished groups
+ * (frees their scratch), admits waiting requests in order while one of
+ * `slots` is free and the arena has room for the output and the scratch of
+ * the group, and launches all requests admitted in that tick as one merged
+ * range plan, alternating two streams so new groups overlap running ones.
+ * Outputs live in the arena until lz_serve_release.  Single-threaded use. */
+typedef struct lz_server lz_server;
+int lz_serve_create(lz_dev* h, void* d_arena, uint64_t arena_bytes, uint32_t slots, const lz_decode_cfg* cfg,
+                    lz_server** server);
+int lz_serve_submit(lz_server* server, uint64_t off, uint64_t len, uint64_t* id);
+int lz_serve_tick(lz_server* server, uint64_t* n_done, uint64_t* n_admitted);
+int lz_serve_status(lz_server* server, uint64_t id, int* state /* 0 waiting, 1 running, 2 done, 3 released */,
+                    uint8_t** d_ptr);
+int lz_serve_release(lz_server* server, uint64_t id);
+void lz_serve_stats(const lz_server* server, uint64_t* waiting, uint64_t* running_groups, uint64_t* arena_used,
+                    uint64_t* arena_high_water);
+int lz_serve_destroy(lz_server* server);
+
 /* Pure-copy mode (Sec. 3.3, first control): executes pre-decoded tokens on the
  * device.  Token t (SoA, device arrays): copy lit_len[t] bytes from
  * d_lit[lit_off[t]..] to d_out[dst[t]..], then mlen[t] bytes from

@@ -46,6 +46,7 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -1808,3 +1809,235 @@ extern "C" int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* cons
   if (n_report) *n_report = nrep;
   return rc;
 }
+
+// ------------------------------------------------------------------ serving
+//
+// Continuous batching of range requests against one device-resident archive.
+// Requests wait in a FIFO; a tick first retires every launched group whose
+// completion event has fired (their requests become done, their scratch is
+// freed), then admits waiting requests in arrival order while a request slot
+// is free and the device arena has room for its output plus its share of
+// scratch, and launches everything admitted in this tick as one merged range
+// plan on the next of two streams, so a new group runs while earlier ones are
+// still on the device.  Outputs stay in the arena until released.
+
+struct lz_server {
+  lz_dev* h = nullptr;
+  uint8_t* arena = nullptr;
+  uint64_t arena_bytes = 0;
+  uint32_t slots = 0;
+  lz_decode_cfg cfg{64, 2, 1, 0, 1};
+  hipStream_t streams[2] = {nullptr, nullptr};
+  uint32_t next_stream = 0;
+  struct Req {
+    uint64_t id, off, len;
+    uint64_t out_at = 0;          // arena offset of the output
+    int state = 0;                // 0 waiting, 1 running, 2 done
+  };
+  std::vector<Req> reqs;          // indexed by id
+  std::vector<uint64_t> fifo;     // waiting ids, arrival order
+  size_t fifo_head = 0;
+  uint32_t active = 0;            // admitted, not yet released
+  struct Group {
+    hipEvent_t ev;
+    lz_range_plan* plan;
+    uint64_t scratch_at, scratch_len;
+    std::vector<uint64_t> ids;
+  };
+  std::vector<Group> running;
+  // first-fit allocator over the arena: free extents by offset
+  std::map<uint64_t, uint64_t> free_ext;
+  uint64_t used = 0, high_water = 0;
+  static uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+  bool alloc(uint64_t len, uint64_t* at) {
+    len = a256(std::max<uint64_t>(len, 1));
+    for (auto it = free_ext.begin(); it != free_ext.end(); ++it)
+      if (it->second >= len) {
+        *at = it->first;
+        const uint64_t rest = it->second - len, nxt = it->first + len;
+        free_ext.erase(it);
+        if (rest) free_ext[nxt] = rest;
+        used += len;
+        high_water = std::max(high_water, used);
+        return true;
+      }
+    return false;
+  }
+  void release(uint64_t at, uint64_t len) {
+    len = a256(std::max<uint64_t>(len, 1));
+    used -= len;
+    auto it = free_ext.emplace(at, len).first;
+    auto nx = std::next(it);
+    if (nx != free_ext.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_ext.erase(nx);
+    }
+    if (it != free_ext.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_ext.erase(it);
+      }
+    }
+  }
+};
+
+extern "C" {
+
+int lz_serve_create(lz_dev* h, void* d_arena, uint64_t arena_bytes, uint32_t slots, const lz_decode_cfg* cfg,
+                    lz_server** out) {
+  if (!h || !d_arena || !out || slots == 0) return lz::fail(LZ_E_INVAL, "bad argument");
+  lz_server* S = new lz_server();
+  S->h = h;
+  S->arena = (uint8_t*)d_arena;
+  S->arena_bytes = arena_bytes & ~uint64_t(255);
+  S->slots = slots;
+  if (cfg) S->cfg = *cfg;
+  S->free_ext[0] = S->arena_bytes;
+  for (auto& st : S->streams)
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      delete S;
+      return lz::fail(LZ_E_HIP, "stream creation failed");
+    }
+  *out = S;
+  return 0;
+}
+
+int lz_serve_submit(lz_server* S, uint64_t off, uint64_t len, uint64_t* id) {
+  if (!S || !id) return lz::fail(LZ_E_INVAL, "null argument");
+  if (off > S->h->v.n || len > S->h->v.n - off) return lz::fail(LZ_E_RANGE, "range outside the archive");
+  if (lz_server::a256(std::max<uint64_t>(len, 1)) > S->arena_bytes)
+    return lz::fail(LZ_E_NOMEM, "request of %llu bytes exceeds the arena", (unsigned long long)len);
+  lz_server::Req r;
+  r.id = S->reqs.size();
+  r.off = off;
+  r.len = len;
+  S->reqs.push_back(r);
+  S->fifo.push_back(r.id);
+  *id = r.id;
+  return 0;
+}
+
+// One scheduling step; *n_done receives how many requests finished in it.
+int lz_serve_tick(lz_server* S, uint64_t* n_done, uint64_t* n_admitted) {
+  if (!S) return lz::fail(LZ_E_INVAL, "null server");
+  uint64_t done = 0, admitted = 0;
+  // 1. retire finished groups
+  for (size_t g = 0; g < S->running.size();) {
+    hipError_t q = hipEventQuery(S->running[g].ev);
+    if (q == hipErrorNotReady) {
+      ++g;
+      continue;
+    }
+    if (q != hipSuccess) return lz::fail(LZ_E_HIP, "group failed: %s", hipGetErrorString(q));
+    auto& G = S->running[g];
+    for (uint64_t id : G.ids) S->reqs[id].state = 2;
+    done += G.ids.size();
+    S->release(G.scratch_at, G.scratch_len);
+    (void)hipEventDestroy(G.ev);
+    lz_range_plan_free(G.plan);
+    S->running.erase(S->running.begin() + g);
+  }
+  // 2. admit in arrival order
+  std::vector<uint64_t> ids, offs, lens;
+  std::vector<uint64_t> out_at;
+  while (S->fifo_head < S->fifo.size() && S->active < S->slots) {
+    auto& r = S->reqs[S->fifo[S->fifo_head]];
+    uint64_t at;
+    if (!S->alloc(r.len, &at)) break;  // head waits for memory: FIFO order
+    r.out_at = at;
+    ids.push_back(r.id);
+    offs.push_back(r.off);
+    lens.push_back(r.len);
+    ++S->fifo_head;
+    ++S->active;
+  }
+  while (!ids.empty()) {
+    // 3. one merged plan for everything admitted now; shrink if scratch does not fit
+    lz_range_plan* P = nullptr;
+    int rc = lz_range_plan_create(S->h, ids.size(), offs.data(), lens.data(), &P);
+    if (rc) return rc;
+    uint64_t sat;
+    if (!S->alloc(P->scratch_bytes, &sat)) {
+      const uint64_t need = lz_server::a256(std::max<uint64_t>(lens.back(), 1)) + lz_server::a256(P->scratch_bytes);
+      lz_range_plan_free(P);
+      if (ids.size() == 1 && S->running.empty() && need > S->arena_bytes)
+        return lz::fail(LZ_E_NOMEM, "request %llu needs %llu bytes, more than the arena", (unsigned long long)ids[0],
+                        (unsigned long long)need);
+      // give back the newest admission; it waits at the head of the queue
+      auto& r = S->reqs[ids.back()];
+      S->release(r.out_at, r.len);
+      --S->active;
+      --S->fifo_head;
+      ids.pop_back();
+      offs.pop_back();
+      lens.pop_back();
+      continue;
+    }
+    std::vector<uint64_t> oo;
+    for (uint64_t id : ids) oo.push_back(S->reqs[id].out_at);
+    hipStream_t st = S->streams[S->next_stream];
+    S->next_stream ^= 1;
+    rc = lz_range_run(S->h, P, S->arena, S->arena_bytes, oo.data(), S->arena + sat, P->scratch_bytes, &S->cfg, st);
+    if (rc) {
+      S->release(sat, P->scratch_bytes);
+      lz_range_plan_free(P);
+      return rc;
+    }
+    lz_server::Group G;
+    if (hipEventCreateWithFlags(&G.ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(G.ev, st) != hipSuccess)
+      return lz::fail(LZ_E_HIP, "event failed");
+    G.plan = P;
+    G.scratch_at = sat;
+    G.scratch_len = P->scratch_bytes;
+    G.ids = ids;
+    for (uint64_t id : ids) S->reqs[id].state = 1;
+    S->running.push_back(std::move(G));
+    admitted += ids.size();
+    break;
+  }
+  if (n_done) *n_done = done;
+  if (n_admitted) *n_admitted = admitted;
+  return 0;
+}
+
+// State of a request: 0 waiting, 1 running, 2 done; *d_ptr its output when done.
+int lz_serve_status(lz_server* S, uint64_t id, int* state, uint8_t** d_ptr) {
+  if (!S || id >= S->reqs.size() || !state) return lz::fail(LZ_E_INVAL, "bad request id");
+  *state = S->reqs[id].state;
+  if (d_ptr) *d_ptr = S->arena + S->reqs[id].out_at;
+  return 0;
+}
+
+// Frees a done request's output.
+int lz_serve_release(lz_server* S, uint64_t id) {
+  if (!S || id >= S->reqs.size() || S->reqs[id].state != 2) return lz::fail(LZ_E_INVAL, "request not done");
+  S->release(S->reqs[id].out_at, S->reqs[id].len);
+  S->reqs[id].state = 3;
+  --S->active;
+  return 0;
+}
+
+void lz_serve_stats(const lz_server* S, uint64_t* waiting, uint64_t* running_groups, uint64_t* arena_used,
+                    uint64_t* arena_high_water) {
+  if (!S) return;
+  if (waiting) *waiting = S->fifo.size() - S->fifo_head;
+  if (running_groups) *running_groups = S->running.size();
+  if (arena_used) *arena_used = S->used;
+  if (arena_high_water) *arena_high_water = S->high_water;
+}
+
+int lz_serve_destroy(lz_server* S) {
+  if (!S) return 0;
+  for (auto& G : S->running) {
+    (void)hipEventSynchronize(G.ev);
+    (void)hipEventDestroy(G.ev);
+    lz_range_plan_free(G.plan);
+  }
+  for (auto& st : S->streams)
+    if (st) (void)hipStreamDestroy(st);
+  delete S;
+  return 0;
+}
+
+}  // extern "C"

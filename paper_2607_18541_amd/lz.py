@@ -96,6 +96,13 @@ def lib():
             "lz_batch_destroy": (None, [_vp]),
             "lz_autotune": (ctypes.c_int, [_u32, _vp, _vp, _vp, _vp, _u64, _vp, _u32, _vp, _vp, _u32,
                                            ctypes.POINTER(_u32)]),
+            "lz_serve_create": (ctypes.c_int, [_vp, _vp, _u64, _u32, ctypes.POINTER(DecodeCfg), ctypes.POINTER(_vp)]),
+            "lz_serve_submit": (ctypes.c_int, [_vp, _u64, _u64, _p64]),
+            "lz_serve_tick": (ctypes.c_int, [_vp, _p64, _p64]),
+            "lz_serve_status": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_vp)]),
+            "lz_serve_release": (ctypes.c_int, [_vp, _u64]),
+            "lz_serve_stats": (None, [_vp, _p64, _p64, _p64, _p64]),
+            "lz_serve_destroy": (ctypes.c_int, [_vp]),
             "lz_purecopy_device": (ctypes.c_int, [_u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp,
                                                   _u64, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
         }
@@ -466,3 +473,69 @@ def autotune(archives, outs, reps=3, stream=None):
                "bytes": rep[i].bytes, "best": (rep[i].best.G, rep[i].best.unroll, rep[i].best.schedule),
                "best_ms": rep[i].best_ms, "default_ms": rep[i].default_ms} for i in range(nrep.value)]
     return cfgs, report
+
+
+class Server:
+    """Continuous-batching range server over one DeviceArchive; the arena
+    (outputs + scratch) is a torch device buffer of `arena_bytes`."""
+
+    def __init__(self, da, arena_bytes, slots=64, G=64, unroll=2):
+        import torch
+        self.da = da
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=da.buf.device)
+        c = _cfg(G, unroll, 1)
+        p = _vp()
+        rc = lib().lz_serve_create(da.h, ctypes.c_void_p(self.arena.data_ptr()), arena_bytes, slots, ctypes.byref(c),
+                                   ctypes.byref(p))
+        if rc:
+            raise LzError(rc, "lz_serve_create")
+        self.s = p
+
+    def submit(self, off, length):
+        i = _u64()
+        rc = lib().lz_serve_submit(self.s, off, length, ctypes.byref(i))
+        if rc:
+            raise LzError(rc, "lz_serve_submit")
+        return i.value
+
+    def tick(self):
+        d, a = _u64(), _u64()
+        rc = lib().lz_serve_tick(self.s, ctypes.byref(d), ctypes.byref(a))
+        if rc:
+            raise LzError(rc, "lz_serve_tick")
+        return d.value, a.value
+
+    def status(self, rid):
+        st = ctypes.c_int()
+        ptr = _vp()
+        rc = lib().lz_serve_status(self.s, rid, ctypes.byref(st), ctypes.byref(ptr))
+        if rc:
+            raise LzError(rc, "lz_serve_status")
+        return st.value, (ptr.value or 0) - self.arena.data_ptr()
+
+    def result(self, rid, length):
+        """View of a done request's bytes inside the arena."""
+        st, off = self.status(rid)
+        assert st == 2, st
+        return self.arena[off:off + length]
+
+    def release(self, rid):
+        rc = lib().lz_serve_release(self.s, rid)
+        if rc:
+            raise LzError(rc, "lz_serve_release")
+
+    def stats(self):
+        w, r, u, hw = _u64(), _u64(), _u64(), _u64()
+        lib().lz_serve_stats(self.s, ctypes.byref(w), ctypes.byref(r), ctypes.byref(u), ctypes.byref(hw))
+        return {"waiting": w.value, "running_groups": r.value, "arena_used": u.value, "arena_high_water": hw.value}
+
+    def destroy(self):
+        if getattr(self, "s", None):
+            lib().lz_serve_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

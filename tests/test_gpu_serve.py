@@ -1,0 +1,77 @@
+"""Serving loop: requests admitted by slots and memory while others run; every
+result is byte-identical to the same range alone (tolerance 0: lossless)."""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2607_18541_amd import lz
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.mark.parametrize("arena_mib,slots", [(256, 64), (40, 3)])
+def test_serve_mix_equals_alone(arena_mib, slots):
+    dev = _dev()
+    x = synth.fastq(24 << 20, seed=5)
+    da = lz.DeviceArchive(lz.encode(x, 16, lz.TUNED_THR), device=dev)
+    n = da.n
+    k = 80
+    lens = synth.loguniform(k, 16 << 10, 2 << 20, 17)
+    offs = (synth.uniform(k, 18) * (n - lens)).astype(np.uint64)
+    srv = lz.Server(da, arena_mib << 20, slots=slots)
+    pending = {}
+    submitted = 0
+    done_order = []
+    t_end = time.time() + 120
+    # arrivals interleaved with ticks: new requests join while earlier groups run
+    while (submitted < k or pending) and time.time() < t_end:
+        for _ in range(5):
+            if submitted < k:
+                rid = srv.submit(int(offs[submitted]), int(lens[submitted]))
+                pending[rid] = submitted
+                submitted += 1
+        srv.tick()
+        for rid in list(pending):
+            st, _ = srv.status(rid)
+            if st == 2:
+                i = pending.pop(rid)
+                got = srv.result(rid, int(lens[i])).clone()
+                done_order.append(i)
+                alone = da.decode_range(int(offs[i]), int(lens[i]))
+                assert torch.equal(got, alone), i
+                assert bytes(got.cpu().numpy()) == bytes(x[int(offs[i]):int(offs[i]) + int(lens[i])])
+                srv.release(rid)
+        st = srv.stats()
+        assert st["arena_used"] <= arena_mib << 20
+    assert not pending and len(done_order) == k
+    assert srv.stats()["arena_high_water"] <= arena_mib << 20
+    srv.destroy()
+
+
+def test_serve_rejects_oversized_and_out_of_range():
+    dev = _dev()
+    x = synth.zipf_text(4 << 20, seed=3)
+    da = lz.DeviceArchive(lz.encode(x, 14), device=dev)
+    srv = lz.Server(da, 1 << 20, slots=2)
+    with pytest.raises(lz.LzError):
+        srv.submit(da.n - 10, 11)
+    with pytest.raises(lz.LzError) as e:
+        srv.submit(0, 2 << 20)  # can never fit a 1 MiB arena
+    assert e.value.rc == lz.LZ_E_NOMEM
+    rid = srv.submit(100, 1000)
+    for _ in range(1000):
+        srv.tick()
+        if srv.status(rid)[0] == 2:
+            break
+    assert bytes(srv.result(rid, 1000).cpu().numpy()) == bytes(x[100:1100])
+    srv.release(rid)
+    srv.destroy()
