@@ -261,6 +261,36 @@ void lz_serve_stats(const lz_server* server, uint64_t* waiting, uint64_t* runnin
                     uint64_t* arena_high_water);
 int lz_serve_destroy(lz_server* server);
 
+/* ------------------------------------------------------ learned thresholds */
+
+/* Per-block features of the threshold selector: feats[64*b + 16*c + k] = the
+ * fraction of block b's bytes produced by matches of distance class c (bounds
+ * as given) in length bin k (bins as in lz_info.hist).  Computed from an
+ * archive -- the selector uses a cheap parse at thresholds 4/4/4/4. */
+int lz_block_features(const uint8_t* arc, uint64_t arc_size, const uint64_t* bounds, float* feats);
+
+/* Per block (arrays of n_blocks, each may be NULL): entropy-bound bytes of the
+ * block's streams with the block as one tile, token, match and match-byte
+ * counts. */
+int lz_block_stats(const uint8_t* arc, uint64_t arc_size, double* ent, uint64_t* ntok, uint64_t* nmatch,
+                   uint64_t* match_bytes);
+
+/* The selector network on the GPU (fp32, device pointers, async on stream):
+ * 64 -> 128 -> 128 -> 16, ReLU, softmax over 16 candidate threshold tuples.
+ * Parameters: W1 64x128, b1, W2 128x128, b2, W3 128x16, b3 (row-major, flat,
+ * lz_mlp_param_count() floats).  Activations are row-major [batch x width]. */
+uint64_t lz_mlp_param_count(void);
+int lz_mlp_forward(const float* d_params, uint32_t batch, const float* d_x, float* d_h1, float* d_h2, float* d_logits,
+                   void* stream);
+/* Mean softmax cross-entropy gradient for int32 labels; d_work holds
+ * batch x 272 floats; d_loss (may be NULL) is incremented by the mean loss. */
+int lz_mlp_backward(const float* d_params, uint32_t batch, const float* d_x, const float* d_h1, const float* d_h2,
+                    const float* d_logits, const int32_t* d_labels, float* d_grads, float* d_work, float* d_loss,
+                    void* stream);
+/* One bias-corrected Adam step (Kingma and Ba); step counts from 1. */
+int lz_mlp_adam(float* d_params, const float* d_grads, float* d_m, float* d_v, uint64_t n, float lr, float beta1,
+                float beta2, float eps, uint32_t step, void* stream);
+
 /* Pure-copy mode (Sec. 3.3, first control): executes pre-decoded tokens on the
  * device.  Token t (SoA, device arrays): copy lit_len[t] bytes from
  * d_lit[lit_off[t]..] to d_out[dst[t]..], then mlen[t] bytes from

@@ -871,3 +871,80 @@ extern "C" int lz_plan(const uint8_t* arc, uint64_t arc_size, uint32_t* levels, 
   if (rc) return rc;
   return compute_levels(v, levels, max_level);
 }
+
+// ------------------------------------------------------------------ per-block statistics
+
+namespace lz {
+static int len_bin16(uint64_t L) {
+  static const uint64_t edges[16] = {0, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64, 128, 256, 1024, 4096, 16384};
+  int b = 0;
+  while (b < 15 && L >= edges[b + 1]) ++b;
+  return b;
+}
+}  // namespace lz
+
+extern "C" {
+
+// feats[64*b + 16*c + k] = fraction of block b's bytes produced by matches of
+// distance class c (bounds as given) and length bin k.
+int lz_block_features(const uint8_t* arc, uint64_t arc_size, const uint64_t* bounds, float* feats) {
+  if (!feats || !bounds) return fail(LZ_E_INVAL, "null argument");
+  ArcView v;
+  int rc = view_archive(arc, arc_size, &v);
+  if (rc) return rc;
+  std::atomic<int> bad{0};
+  parallel_for(v.nb, hw_threads(0), [&](uint64_t b, unsigned) {
+    double acc[64] = {0};
+    int r = walk_block(v, b, [&](uint64_t, const Tok& t) {
+      if (!t.mlen) return;
+      const uint64_t d = t.dst + t.lit_len - t.src;
+      acc[16 * dclass(d, bounds) + len_bin16(t.mlen)] += double(t.mlen);
+    });
+    if (r) bad.store(r);
+    const double len = double(std::min(v.bs, v.n - b * v.bs));
+    for (int k = 0; k < 64; ++k) feats[64 * b + k] = float(acc[k] / len);
+  });
+  if (bad.load()) return fail(LZ_E_CORRUPT, "archive fails validation");
+  return 0;
+}
+
+// Per block: entropy-bound bytes of its streams (each stream of the block one
+// tile, same charge as lz_entropy_size), token count, match count, match bytes.
+int lz_block_stats(const uint8_t* arc, uint64_t arc_size, double* ent, uint64_t* ntok, uint64_t* nmatch,
+                   uint64_t* match_bytes) {
+  ArcView v;
+  int rc = view_archive(arc, arc_size, &v);
+  if (rc) return rc;
+  std::atomic<int> bad{0};
+  const uint64_t* T = v.tab();
+  parallel_for(v.nb, hw_threads(0), [&](uint64_t b, unsigned) {
+    uint64_t nm = 0, mb = 0;
+    int r = walk_block(v, b, [&](uint64_t, const Tok& t) {
+      if (t.mlen) {
+        ++nm;
+        mb += t.mlen;
+      }
+    });
+    if (r) bad.store(r);
+    const uint64_t t0 = T[4 * b], t1 = T[4 * b + 4];
+    const uint64_t l0 = T[4 * b + 1], l1 = T[4 * b + 5];
+    const uint64_t x0 = T[4 * b + 2], x1 = T[4 * b + 6];
+    const uint64_t y0 = T[4 * b + 3], y1 = T[4 * b + 7];
+    if (ent) {
+      double e = tile_entropy_bytes(v.base + v.off_cmd + t0, t1 - t0, 1);
+      e += tile_entropy_bytes(v.base + v.off_x16 + 2 * x0, 2 * (x1 - x0), 1);
+      e += tile_entropy_bytes(v.base + v.off_x32 + 4 * y0, 4 * (y1 - y0), 1);
+      for (int k = 0; k < 4; ++k) e += tile_entropy_bytes(v.base + v.off_slo + 4 * t0 + k, t1 - t0, 4);
+      if (v.flags & 1) e += tile_entropy_bytes(v.base + v.off_shi + t0, t1 - t0, 1);
+      e += tile_entropy_bytes(v.base + v.off_lit + l0, l1 - l0, 1);
+      ent[b] = e;
+    }
+    if (ntok) ntok[b] = t1 - t0;
+    if (nmatch) nmatch[b] = nm;
+    if (match_bytes) match_bytes[b] = mb;
+  });
+  if (bad.load()) return fail(LZ_E_CORRUPT, "archive fails validation");
+  return 0;
+}
+
+}  // extern "C"

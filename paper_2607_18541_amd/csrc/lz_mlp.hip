@@ -1,0 +1,167 @@
+// lz_mlp.hip -- gfx950 kernels of the per-block threshold selector.
+//
+// A 64 -> 128 -> 128 -> 16 perceptron (ReLU, softmax over 16 threshold
+// tuples) scores encoder settings per LZ block from its match-length /
+// distance-class histogram (the quantities Sec. 3.3 and Sec. 4.3 tie to
+// throughput and to offset cost).  Shapes are tiny (batch 256, width 128), so
+// the kernels are latency-bound: one fp32 GEMM kernel with 16x16 LDS tiles
+// and fused bias / ReLU / ReLU-gradient epilogues, a softmax cross-entropy
+// kernel, a column-sum kernel for bias gradients and an Adam kernel.  Matrix
+// cores would not shorten a chain of dependent launches at these sizes.
+//
+// Parameter vector (fp32, row-major): W1 64x128, b1 128, W2 128x128, b2 128,
+// W3 128x16, b3 16 = 26,896 values.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lz_internal.h"
+
+namespace {
+
+constexpr int IN = 64, H = 128, OUT = 16;
+constexpr uint64_t OW1 = 0, OB1 = OW1 + IN * H, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3 = OB2 + H, OB3 = OW3 + H * OUT,
+                   NP = OB3 + OUT;
+constexpr int T = 16;
+
+// C[M,N] (ldc) = op(A)[M,K] * op(B)[K,N] (+ bias[N]); epilogue: 0 none,
+// 1 ReLU, 2 multiply by (R[M,N] > 0) (ReLU gradient; R has ldc).
+// op(A) = A (lda, row-major) or A^T when TA; likewise B.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(T * T) void k_gemm(int M, int N, int K, const float* __restrict__ A, int lda,
+                                                 const float* __restrict__ B, int ldb, float* __restrict__ C, int ldc,
+                                                 const float* __restrict__ bias, int epi, const float* __restrict__ R) {
+  __shared__ float sa[T][T + 1], sb[T][T + 1];
+  const int tx = threadIdx.x % T, ty = threadIdx.x / T;
+  const int row = blockIdx.y * T + ty, col = blockIdx.x * T + tx;
+  float acc = 0.f;
+  for (int k0 = 0; k0 < K; k0 += T) {
+    const int ka = k0 + tx, kb = k0 + ty;
+    float a = 0.f, b = 0.f;
+    if (row < M && ka < K) a = TA ? A[(size_t)ka * lda + row] : A[(size_t)row * lda + ka];
+    if (kb < K && col < N) b = TB ? B[(size_t)col * ldb + kb] : B[(size_t)kb * ldb + col];
+    sa[ty][tx] = a;
+    sb[ty][tx] = b;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < T; ++k) acc = fmaf(sa[ty][k], sb[k][tx], acc);
+    __syncthreads();
+  }
+  if (row < M && col < N) {
+    if (bias) acc += bias[col];
+    if (epi == 1) acc = fmaxf(acc, 0.f);
+    if (epi == 2) acc = (R[(size_t)row * ldc + col] > 0.f) ? acc : 0.f;
+    C[(size_t)row * ldc + col] = acc;
+  }
+}
+
+// dlogits = (softmax(logits) - onehot(label)) / B; loss[0] += mean CE.
+__global__ void k_softmax_ce(int Bn, const float* __restrict__ logits, const int32_t* __restrict__ labels,
+                             float* __restrict__ dlogits, float* __restrict__ loss) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= Bn) return;
+  const float* z = logits + (size_t)r * OUT;
+  float mx = z[0];
+  for (int j = 1; j < OUT; ++j) mx = fmaxf(mx, z[j]);
+  float s = 0.f;
+  for (int j = 0; j < OUT; ++j) s += expf(z[j] - mx);
+  const int y = labels[r];
+  for (int j = 0; j < OUT; ++j) {
+    const float p = expf(z[j] - mx) / s;
+    dlogits[(size_t)r * OUT + j] = (p - (j == y ? 1.f : 0.f)) / (float)Bn;
+  }
+  if (loss) atomicAdd(loss, (logf(s) - (z[y] - mx)) / (float)Bn);
+}
+
+// out[j] = sum_r X[r, j] (bias gradients)
+__global__ void k_colsum(int Bn, int N, const float* __restrict__ X, float* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  float s = 0.f;
+  for (int r = 0; r < Bn; ++r) s += X[(size_t)r * N + j];
+  out[j] = s;
+}
+
+__global__ void k_adam(uint64_t n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+template <bool TA, bool TB>
+void gemm(hipStream_t s, int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, int ldc,
+          const float* bias, int epi, const float* R) {
+  dim3 grid((N + T - 1) / T, (M + T - 1) / T);
+  hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(T * T), 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias, epi, R);
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t lz_mlp_param_count(void) { return NP; }
+
+// Forward pass for `batch` rows of x [batch x 64]: h1, h2 [batch x 128] and
+// logits [batch x 16] (device buffers, row-major).
+int lz_mlp_forward(const float* d_params, uint32_t batch, const float* d_x, float* d_h1, float* d_h2, float* d_logits,
+                   void* stream) {
+  if (!d_params || !d_x || !d_h1 || !d_h2 || !d_logits) return lz::fail(LZ_E_INVAL, "null argument");
+  if (batch == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  const float* P = d_params;
+  gemm<false, false>(s, batch, H, IN, d_x, IN, P + OW1, H, d_h1, H, P + OB1, 1, nullptr);
+  gemm<false, false>(s, batch, H, H, d_h1, H, P + OW2, H, d_h2, H, P + OB2, 1, nullptr);
+  gemm<false, false>(s, batch, OUT, H, d_h2, H, P + OW3, OUT, d_logits, OUT, P + OB3, 0, nullptr);
+  if (hipGetLastError() != hipSuccess) return lz::fail(LZ_E_HIP, "forward launch failed");
+  return 0;
+}
+
+// Gradient of the mean softmax cross-entropy (labels int32 in [0,16)) into
+// d_grads [26,896]; d_work needs batch x (16 + 128 + 128) floats; d_loss (may
+// be null) receives += the mean loss.  Uses the activations of lz_mlp_forward.
+int lz_mlp_backward(const float* d_params, uint32_t batch, const float* d_x, const float* d_h1, const float* d_h2,
+                    const float* d_logits, const int32_t* d_labels, float* d_grads, float* d_work, float* d_loss,
+                    void* stream) {
+  if (!d_params || !d_x || !d_h1 || !d_h2 || !d_logits || !d_labels || !d_grads || !d_work)
+    return lz::fail(LZ_E_INVAL, "null argument");
+  if (batch == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  const float* P = d_params;
+  float* d3 = d_work;                        // batch x 16
+  float* dh2 = d3 + (size_t)batch * OUT;     // batch x 128
+  float* dh1 = dh2 + (size_t)batch * H;      // batch x 128
+  hipLaunchKernelGGL(k_softmax_ce, dim3((batch + 255) / 256), dim3(256), 0, s, (int)batch, d_logits, d_labels, d3,
+                     d_loss);
+  // layer 3
+  gemm<true, false>(s, H, OUT, batch, d_h2, H, d3, OUT, d_grads + OW3, OUT, nullptr, 0, nullptr);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, s, (int)batch, OUT, d3, d_grads + OB3);
+  gemm<false, true>(s, batch, H, OUT, d3, OUT, P + OW3, OUT, dh2, H, nullptr, 2, d_h2);
+  // layer 2
+  gemm<true, false>(s, H, H, batch, d_h1, H, dh2, H, d_grads + OW2, H, nullptr, 0, nullptr);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, s, (int)batch, H, dh2, d_grads + OB2);
+  gemm<false, true>(s, batch, H, H, dh2, H, P + OW2, H, dh1, H, nullptr, 2, d_h1);
+  // layer 1
+  gemm<true, false>(s, IN, H, batch, d_x, IN, dh1, H, d_grads + OW1, H, nullptr, 0, nullptr);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, s, (int)batch, H, dh1, d_grads + OB1);
+  if (hipGetLastError() != hipSuccess) return lz::fail(LZ_E_HIP, "backward launch failed");
+  return 0;
+}
+
+// One Adam step (Kingma & Ba), bias-corrected; `step` counts from 1.
+int lz_mlp_adam(float* d_params, const float* d_grads, float* d_m, float* d_v, uint64_t n, float lr, float beta1,
+                float beta2, float eps, uint32_t step, void* stream) {
+  if (!d_params || !d_grads || !d_m || !d_v || step == 0) return lz::fail(LZ_E_INVAL, "bad argument");
+  const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, n, d_params,
+                     d_grads, d_m, d_v, lr, beta1, beta2, eps, c1, c2);
+  if (hipGetLastError() != hipSuccess) return lz::fail(LZ_E_HIP, "adam launch failed");
+  return 0;
+}
+
+}  // extern "C"

@@ -103,6 +103,13 @@ def lib():
             "lz_serve_release": (ctypes.c_int, [_vp, _u64]),
             "lz_serve_stats": (None, [_vp, _p64, _p64, _p64, _p64]),
             "lz_serve_destroy": (ctypes.c_int, [_vp]),
+            "lz_block_features": (ctypes.c_int, [_vp, _u64, _vp, _vp]),
+            "lz_block_stats": (ctypes.c_int, [_vp, _u64, _vp, _vp, _vp, _vp]),
+            "lz_mlp_param_count": (_u64, []),
+            "lz_mlp_forward": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _vp, _vp]),
+            "lz_mlp_backward": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "lz_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                           ctypes.c_float, _u32, _vp]),
             "lz_purecopy_device": (ctypes.c_int, [_u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp,
                                                   _u64, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
         }
@@ -539,3 +546,50 @@ class Server:
             self.destroy()
         except Exception:
             pass
+
+
+def block_features(arc, bounds=BOUNDS_CFG):
+    a = _u8(arc)
+    nb = archive_info(a)["n_blocks"]
+    f = np.zeros((max(nb, 1), 64), dtype=np.float32)
+    b = np.asarray(bounds, dtype=np.uint64)
+    rc = lib().lz_block_features(a.ctypes.data, a.size, b.ctypes.data, f.ctypes.data)
+    if rc:
+        raise LzError(rc, "lz_block_features")
+    return f[:nb]
+
+
+def block_stats(arc):
+    """Per block: entropy-bound bytes, tokens, matches, match bytes."""
+    a = _u8(arc)
+    nb = archive_info(a)["n_blocks"]
+    ent = np.zeros(max(nb, 1), dtype=np.float64)
+    nt, nm, mb = (np.zeros(max(nb, 1), dtype=np.uint64) for _ in range(3))
+    rc = lib().lz_block_stats(a.ctypes.data, a.size, ent.ctypes.data, nt.ctypes.data, nm.ctypes.data, mb.ctypes.data)
+    if rc:
+        raise LzError(rc, "lz_block_stats")
+    return ent[:nb], nt[:nb], nm[:nb], mb[:nb]
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mlp_forward(params, x, h1, h2, logits, stream=None):
+    rc = lib().lz_mlp_forward(_p(params), x.shape[0], _p(x), _p(h1), _p(h2), _p(logits), _stream(stream))
+    if rc:
+        raise LzError(rc, "lz_mlp_forward")
+
+
+def mlp_backward(params, x, h1, h2, logits, labels, grads, work, loss=None, stream=None):
+    rc = lib().lz_mlp_backward(_p(params), x.shape[0], _p(x), _p(h1), _p(h2), _p(logits), _p(labels), _p(grads),
+                               _p(work), None if loss is None else _p(loss), _stream(stream))
+    if rc:
+        raise LzError(rc, "lz_mlp_backward")
+
+
+def mlp_adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    rc = lib().lz_mlp_adam(_p(params), _p(grads), _p(m), _p(v), params.numel(), lr, beta1, beta2, eps, step,
+                           _stream(stream))
+    if rc:
+        raise LzError(rc, "lz_mlp_adam")

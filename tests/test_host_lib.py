@@ -171,3 +171,23 @@ def test_params_rejected():
         lz.encode(x, 12, bounds=(100, 50, 200))
     with pytest.raises(lz.LzError):
         lz.encode(x, 12, segment=1000)
+
+
+def test_block_features_equal_oracle():
+    from oracle import mlp_ref
+    for x in (synth.zipf_text(700_000, seed=3), synth.fastq(600_000, seed=4)):
+        arc = lz.encode(x, 16, (4, 4, 4, 4), max_chain=16)
+        F = lz.block_features(arc, lz.BOUNDS_CFG)
+        R = mlp_ref.block_features(oracle.tokens(arc), x.size, 16, lz.BOUNDS_CFG)
+        assert np.allclose(F, R, rtol=1e-6, atol=1e-7)
+
+
+def test_block_stats_single_block_equal_oracle_entropy():
+    for x in (synth.zipf_text(60_000, seed=5), synth.fastq(50_000, seed=6)):
+        arc = lz.encode(x, 16, lz.BASE_THR)
+        ent, nt, nm, mb = lz.block_stats(arc)
+        tot, parts = oracle.entropy_size(arc)
+        assert ent.size == 1
+        assert ent[0] == pytest.approx(parts[0] + parts[1] + parts[2] + parts[3] + parts[4] + parts[6], abs=1e-6)
+        T = oracle.tokens(arc)
+        assert nt[0] == T["dst"].size and nm[0] == int((T["mlen"] > 0).sum()) and mb[0] == int(T["mlen"].sum())
