@@ -553,9 +553,11 @@ static int encode_impl(const uint8_t* in, uint64_t n, const lz_params* p, const 
   // key lengths: near serves classes 0-1, far serves classes 2-3; per-block
   // tuples take the minimum over all blocks so every chain stays exhaustive
   uint32_t tmin[4] = {p->thr[0], p->thr[1], p->thr[2], p->thr[3]};
-  if (thr_block)
+  if (thr_block && nb) {
+    for (int k = 0; k < 4; ++k) tmin[k] = UINT32_MAX;
     for (uint64_t b = 0; b < nb; ++b)
       for (int k = 0; k < 4; ++k) tmin[k] = std::min(tmin[k], thr_block[4 * b + k]);
+  }
   for (int k = 0; k < 4; ++k)
     if (tmin[k] < 1) return fail(LZ_E_INVAL, "thresholds must be >= 1");
   uint32_t kn = std::min<uint32_t>(std::min(tmin[0], tmin[1]), 8);

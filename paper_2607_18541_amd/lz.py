@@ -174,7 +174,7 @@ def encode_blockwise(x, thr_per_block, tuple_id=None, log2_bs=16, bounds=BOUNDS_
     x = _u8(x)
     tb = np.ascontiguousarray(thr_per_block, dtype=np.uint32).reshape(-1)
     tid = None if tuple_id is None else np.ascontiguousarray(tuple_id, dtype=np.uint8)
-    p = params(log2_bs, (1, 1, 1, 1), bounds, max_chain, n_threads)
+    p = params(log2_bs, TUNED_THR, bounds, max_chain, n_threads)  # header thresholds: informational
     pa = _vp()
     sz = _u64()
     rc = lib().lz_encode_blockwise(x.ctypes.data, x.size, ctypes.byref(p), tb.ctypes.data,

@@ -58,7 +58,7 @@ def test_forward_backward_adam_match_reference(B):
 def test_learned_selector_end_to_end():
     _dev()
     from paper_2607_18541_amd import learn
-    res, sel = learn.run(n_files=24, blocks_per_file=12, log2_bs=14, epochs=40, seed=3)
+    res, sel = learn.run(n_files=40, blocks_per_file=12, log2_bs=14, epochs=40, seed=3)
     print("learned selector:", {k: res[k] for k in ("loss_first", "loss_last", "val_accuracy", "test_mean_J",
                                                     "fixed_J", "test_gain")}, flush=True)
     assert res["loss_last"] < res["loss_first"]

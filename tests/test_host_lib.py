@@ -191,3 +191,17 @@ def test_block_stats_single_block_equal_oracle_entropy():
         assert ent[0] == pytest.approx(parts[0] + parts[1] + parts[2] + parts[3] + parts[4] + parts[6], abs=1e-6)
         T = oracle.tokens(arc)
         assert nt[0] == T["dst"].size and nm[0] == int((T["mlen"] > 0).sum()) and mb[0] == int(T["mlen"].sum())
+
+
+def test_blockwise_encoder_uniform_equals_plain():
+    """Per-block thresholds that are all equal give the plain parse (same
+    tokens; only the per-block info bytes are added)."""
+    x = synth.fastq(300_000, seed=8)
+    nb = (x.size + (1 << 14) - 1) >> 14
+    for thr in (lz.BASE_THR, lz.TUNED_THR):
+        a = lz.encode_blockwise(x, np.array([thr] * nb, np.uint32), np.full(nb, 1, np.uint8), log2_bs=14)
+        b = lz.encode(x, 14, thr)
+        ta, tb = oracle.tokens(a), oracle.tokens(b)
+        for k in ta:
+            assert np.array_equal(ta[k], tb[k])
+        assert np.array_equal(oracle.decode(a), x)
