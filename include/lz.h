@@ -124,10 +124,12 @@ int lz_archive_info(const uint8_t* arc, uint64_t arc_size, lz_info* out);
  * header+table, src_hi plane. */
 int lz_entropy_size(const uint8_t* arc, uint64_t arc_size, double* total, double* parts);
 
-/* Dependency levels (schedule of a block-parallel decode; not in the paper):
- * literals are level 0; a match's level is the maximum over its source bytes
- * of the writing token's level, plus one if that token is in another block.
- * levels (may be NULL) receives n_tok values; *max_level the maximum. */
+/* Dependency depth of every match (the schedule of the parallel decode; the
+ * paper does not fix one): literal bytes have depth 0 and a match has depth
+ * 1 + the largest depth among the tokens that write its source bytes, its own
+ * output excluded (a self-overlapping match reads its period).  Matches of one
+ * depth never read each other's output.  levels (may be NULL) receives n_tok
+ * values (0 for a token without a match); *max_level the largest depth. */
 int lz_plan(const uint8_t* arc, uint64_t arc_size, uint32_t* levels, uint32_t* max_level);
 
 /* FNV-1a 64 (Sec. 2 integrity hash), seed = offset basis 0xcbf29ce484222325. */
@@ -141,22 +143,22 @@ typedef struct lz_dev lz_dev; /* opaque handle of a device-resident archive */
 
 /* Decode configuration.  A decode is a parse launch (one group of G lanes per
  * 256-token segment of a block: token headers, literal runs, match table)
- * followed by the matches grouped into (level, block) units by the plan of
- * lz_plan.  G lanes cooperate on a unit (Sec. 2, G in {8,16,32,64}); unroll =
- * 16-byte chunks per lane per step (1, 2, 4).  schedule 0 = all units in one
- * launch, a unit starting once the blocks it reads have finished their lower
- * levels (per-block flags); schedule 1 = one launch per dependency level.
- * NULL config = G 64, unroll 2, schedule 1, unit_batch 1. */
+ * followed by the matches in order of their depth (lz_plan), cut into windows
+ * of G matches; the G lanes of a group cooperate on a window (Sec. 2, G in
+ * {8,16,32,64}); unroll = 16-byte chunks per lane per step (1, 2, 4).
+ * schedule 0 = every depth in one launch, a window starting once all windows
+ * of the depth below have finished (per-depth counters); schedule 1 = one
+ * launch per depth.  NULL config = G 64, unroll 2, schedule 1. */
 typedef struct lz_decode_cfg {
   uint32_t G;
   uint32_t unroll;
   uint32_t schedule;
-  uint32_t wg_size;    /* threads per workgroup: 0 or 256 */
-  uint32_t unit_batch; /* (level, block) units per work item, 1..G; 0 = 1 */
+  uint32_t wg_size; /* threads per workgroup: 0 or 256 */
 } lz_decode_cfg;
 
-/* Device bytes lz_device_open needs for this archive: the archive itself,
- * per-block flags, and (for schedule 1) the level plan. */
+/* Device bytes lz_device_open needs for this archive: the archive itself, the
+ * depth plan (a match-table slot per token, level starts, counters), the parse
+ * segments and the match table (16 bytes per token). */
 int lz_device_bytes(const uint8_t* arc, uint64_t arc_size, uint64_t* bytes);
 
 /* Validates the archive on the host, copies it into the caller's device buffer
@@ -173,7 +175,7 @@ int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decod
 int lz_device_check(lz_dev* h, void* stream);
 
 uint64_t lz_device_n(const lz_dev* h);
-uint32_t lz_device_levels(const lz_dev* h); /* number of levels (schedule 1) */
+uint32_t lz_device_levels(const lz_dev* h); /* number of match depths (launches of schedule 1) */
 void lz_device_close(lz_dev* h);
 
 /* ------------------------------------------------------------ range decode */

@@ -179,7 +179,8 @@ def tokens(arc):
 
 
 def levels(arc):
-    """Dependency level of each token's match; returns (levels u32[T], max)."""
+    """Dependency depth of each token's match (0 for a token without one);
+    returns (depths u32[T], max)."""
     a = _u8(arc)
     T = info(a)["n_tok"]
     lv = np.zeros(max(T, 1), dtype=np.uint32)

@@ -21,10 +21,10 @@
  *  - Decode: execute tokens in order, copying literals, then copying each
  *    match byte by byte from its absolute source (which realises overlap).
  *  - Integrity: FNV-1a 64 over the output (Sec. 2: FNV on GPU paths).
- *  - Dependency levels of a parallel block decode (not in the paper; the
- *    reading used here: literal bytes are level 0, a match takes the maximum
- *    over its source bytes of the writer's level, plus one when that writer
- *    sits in a different block; bytes of the match itself are excluded).
+ *  - Dependency depth of each match for a parallel decode (the paper fixes
+ *    no schedule; the reading used here: literal bytes have depth 0, a match
+ *    has depth one more than the deepest token that wrote any of its source
+ *    bytes, the bytes of the match itself excluded).
  *  - Entropy-bound size: order-0 entropy of each stream over 64 KiB tiles
  *    (Sec. 2: tile-ANS over 64 KB tiles), plus a symbol-table charge.
  *
@@ -569,32 +569,32 @@ int or_tokens(const uint8_t* arc, uint64_t size, uint64_t* blk, uint64_t* dst, u
 /* ------------------------------------------------------------- levels */
 
 typedef struct {
-  const view_t* v;
-  uint32_t* byte_level;  /* level of the token that wrote each output byte */
-  uint64_t* byte_block;  /* unused placeholder to keep the walk signature */
-  uint32_t* tok_level;
-  uint32_t max_level;
+  uint32_t* byte_depth; /* depth of the token part that wrote each output byte */
+  uint32_t* tok_depth;
+  uint32_t max_depth;
 } lvl_ctx;
 
 static void lvl_visit(void* ctx, uint64_t block, uint64_t t, uint64_t dst, uint64_t lit_len,
                       uint64_t lit_off, uint64_t mlen, uint64_t src) {
   (void)lit_off;
+  (void)block;
   lvl_ctx* c = (lvl_ctx*)ctx;
   uint64_t m0 = dst + lit_len;
-  for (uint64_t i = 0; i < lit_len; ++i) c->byte_level[dst + i] = 0;
-  uint32_t lv = 0;
-  uint64_t src_end = src + mlen < m0 ? src + mlen : m0; /* own bytes excluded */
-  for (uint64_t q = src; q < src_end && mlen > 0; ++q) {
-    uint32_t w = c->byte_level[q];
-    if (q / c->v->bs != block) w += 1;
-    if (w > lv) lv = w;
+  for (uint64_t i = 0; i < lit_len; ++i) c->byte_depth[dst + i] = 0;
+  uint32_t dep = 0;
+  if (mlen > 0) {
+    uint32_t deepest = 0;
+    uint64_t src_end = src + mlen < m0 ? src + mlen : m0; /* own bytes excluded */
+    for (uint64_t q = src; q < src_end; ++q)
+      if (c->byte_depth[q] > deepest) deepest = c->byte_depth[q];
+    dep = deepest + 1;
   }
-  for (uint64_t i = 0; i < mlen; ++i) c->byte_level[m0 + i] = lv;
-  c->tok_level[t] = lv;
-  if (lv > c->max_level) c->max_level = lv;
+  for (uint64_t i = 0; i < mlen; ++i) c->byte_depth[m0 + i] = dep;
+  c->tok_depth[t] = dep;
+  if (dep > c->max_depth) c->max_depth = dep;
 }
 
-/* Level of every token's match (0 for tokens without a match). */
+/* Depth of every token's match (0 for tokens without a match). */
 int or_levels(const uint8_t* arc, uint64_t size, uint32_t* tok_level, uint32_t* max_level) {
   view_t v;
   int rc = open_view(arc, size, &v);
@@ -602,15 +602,13 @@ int or_levels(const uint8_t* arc, uint64_t size, uint32_t* tok_level, uint32_t* 
   rc = walk(&v, 0, 0);
   if (rc) return rc;
   lvl_ctx c;
-  c.v = &v;
-  c.byte_level = (uint32_t*)malloc(sizeof(uint32_t) * (v.n + 1));
-  c.byte_block = 0;
-  c.tok_level = tok_level;
-  c.max_level = 0;
-  if (!c.byte_level) return OR_E_NOMEM;
+  c.byte_depth = (uint32_t*)malloc(sizeof(uint32_t) * (v.n + 1));
+  c.tok_depth = tok_level;
+  c.max_depth = 0;
+  if (!c.byte_depth) return OR_E_NOMEM;
   rc = walk(&v, lvl_visit, &c);
-  free(c.byte_level);
-  *max_level = c.max_level;
+  free(c.byte_depth);
+  *max_level = c.max_depth;
   return rc;
 }
 

@@ -56,10 +56,22 @@
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
+// Output, literal and source bytes are addressed as integers; these casts put
+// the accesses in the global address space (global_load/global_store, not flat
+// instructions, which also count against the LDS wait counter).
+#define LZ_G __attribute__((address_space(1)))
+typedef unsigned int u32x4_a1 __attribute__((ext_vector_type(4), aligned(1)));
+template <typename T>
+__device__ __forceinline__ LZ_G T* gptr(uintptr_t a) { return (LZ_G T*)a; }
+template <typename T>
+__device__ __forceinline__ T gld(const T* p, uint64_t i) { return *(const LZ_G T*)(p + i); }
+template <typename T>
+__device__ __forceinline__ void gst(T* p, uint64_t i, T v) { *(LZ_G T*)(p + i) = v; }
+
 namespace {
 
-constexpr int kModeFlow = 0;    // all units, one launch, done_level waits
-constexpr int kModeLevels = 1;  // the units of one level, no waits
+constexpr int kModeFlow = 0;    // every level in one launch, per-level completion counters
+constexpr int kModeLevels = 1;  // the windows of one level, no waits
 constexpr int kModePure = 2;    // pre-decoded tokens, sources in a reference buffer
 constexpr int kModeParse = 3;   // parse blocks, copy literals, fill the match table
 constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -83,38 +95,32 @@ struct ArcDesc {
   uint8_t* out;
   const uint8_t* msrc;  // base that match sources index (out, or ref in mode 2)
   uintptr_t msrc_lo, msrc_hi;
-  const uint32_t* slot;       // per token: match-table index, or kNone
-  u32x4* mtab;                // per match: {dst lo, length, src lo, dst hi | src hi << 16}
-  const uint32_t* first_lvl;  // per block: lowest level with a unit, or kNone
-  uint32_t* done_lvl;         // per block, live during schedule 0
+  const uint32_t* slot;  // per token: match-table index, or kNone
+  u32x4* mtab;           // per match: {dst lo, length, src lo, dst hi | src hi << 16}
 };
 
 struct KArgs {
-  ArcDesc one;             // the archive of a single decode
-  const ArcDesc* arcs;     // batch: archive descriptors (null = single)
+  ArcDesc one;          // the archive of a single decode
+  const ArcDesc* arcs;  // batch: archive descriptors (null = single)
   // parse segments: per segment {t_start, t_end, blk_t_end, pos, lit, x16, x32, archive << 32 | blk}
   const uint64_t* seg;
   uint64_t nseg;
-  // plan units
-  const uint32_t* unit_blk;      // per unit: block
-  const uint32_t* unit_arc;      // per unit: archive (batch only)
-  const uint32_t* unit_lvl;      // per unit: level
-  const uint32_t* unit_next;     // per unit: the block's next level with a unit, or kNone
-  const uint32_t* unit_tok;      // per unit: first match-table index
-  const uint32_t* unit_tok_end;  // per unit: end of its match-table range
-  const uint32_t* lvl_start;  // first unit of each level (n_levels + 1 entries)
-  uint32_t* tickets;          // per level: units taken so far (schedule 0)
+  // Match windows.  Single archive: implicit windows of G consecutive
+  // match-table slots.  Batch: explicit windows {slot | count << 32 | archive << 40}.
+  const uint64_t* items;
+  const uint32_t* lvl_start;  // per level: first slot (implicit) or first window (explicit); n_levels + 1
+  uint32_t* tickets;          // per level: windows taken (schedule 0)
+  uint32_t* wdone;            // per level: windows finished (schedule 0)
   uint32_t* err;
   uint32_t n_levels;
-  uint32_t unit_batch;        // units per work item (<= G)
-  uint64_t unit_lo, unit_hi;  // units this launch covers (schedule 1)
+  uint64_t lo, hi;  // schedule 1 and mode 2: slot or token range (implicit) / window range (explicit)
   // mode 2 (pre-decoded tokens)
   const uint64_t* p_dst;
   const uint64_t* p_lit_off;
   const uint32_t* p_lit_len;
   const uint64_t* p_src;
   const uint32_t* p_mlen;
-  const uint64_t* p_unit;
+  const uint64_t* p_unit;  // token ranges of the work items; null = windows of G tokens over [lo, hi)
   uint64_t nunits;
 };
 
@@ -150,73 +156,71 @@ __device__ __forceinline__ uint32_t gscan32(uint32_t v, int gl, uint32_t& total)
 // bits of this lane's group in a wave-wide ballot
 template <int G>
 __device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int gw) {
-  if (G == 64) return ballot;
-  return (ballot >> (gw * G)) & ((1ull << G) - 1);
+  if constexpr (G == 64) return ballot;
+  else return (ballot >> (gw * G)) & ((1ull << G) - 1);
 }
 
 __device__ __forceinline__ uint32_t nchunks(uintptr_t d, uint32_t len) {
   return len ? (uint32_t)(((d + len + 15) >> 4) - (d >> 4)) : 0u;
 }
 
-// 16 source bytes of a window; out-of-range windows fall back to the needed bytes
-__device__ __forceinline__ u32x4 load_window(uintptr_t w, uintptr_t lo_b, uintptr_t hi_b, int lo, int hi) {
-  u32x4 v;
-  if (w >= lo_b && w + 16 <= hi_b) {
-    __builtin_memcpy(&v, (const void*)w, 16);
-  } else {
-    uint32_t d[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int i = 0; i < 16; ++i)
-      if (i >= lo && i < hi) d[i >> 2] |= uint32_t(*(const uint8_t*)(w + i)) << (8 * (i & 3));
-    v = u32x4{d[0], d[1], d[2], d[3]};
-  }
-  return v;
-}
-
 __device__ __forceinline__ uint32_t dword_at(const u32x4& v, int i) {  // i = dword index 0..3
   return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
+// Read target of the lanes whose window is read byte by byte: every lane
+// issues its 16-byte load unconditionally, so the loads of a step stay in
+// flight together.
+__device__ __align__(16) uint8_t g_pad16[16];
+
+// Bytes [lo, hi) of the 16-byte window at w, one byte at a time (windows that
+// reach outside the readable range; the other bytes are zero).
+__device__ __forceinline__ u32x4 load_bytes(uintptr_t w, int lo, int hi) {
+  uint32_t d[4] = {0u, 0u, 0u, 0u};
+  for (int i = lo; i < hi; ++i) d[i >> 2] |= uint32_t(*gptr<const uint8_t>(w + i)) << (8 * (i & 3));
+  return u32x4{d[0], d[1], d[2], d[3]};
 }
 
 // Writes bytes [lo, hi) of a 16-byte aligned chunk at a with naturally aligned
 // stores only (no read-modify-write of bytes outside the range).
 __device__ __forceinline__ void store_chunk(uintptr_t a, const u32x4& v, int lo, int hi) {
   if (lo == 0 && hi == 16) {
-    *(u32x4*)a = v;
+    *gptr<u32x4>(a) = v;
     return;
   }
   int i = lo;
   if ((i & 1) && i < hi) {
-    *(uint8_t*)(a + i) = (uint8_t)(dword_at(v, i >> 2) >> (8 * (i & 3)));
+    *gptr<uint8_t>(a + i) = (uint8_t)(dword_at(v, i >> 2) >> (8 * (i & 3)));
     i += 1;
   }
   if ((i & 2) && i + 2 <= hi) {
-    *(uint16_t*)(a + i) = (uint16_t)(dword_at(v, i >> 2) >> (8 * (i & 3)));
+    *gptr<uint16_t>(a + i) = (uint16_t)(dword_at(v, i >> 2) >> (8 * (i & 3)));
     i += 2;
   }
   if ((i & 4) && i + 4 <= hi) {
-    *(uint32_t*)(a + i) = dword_at(v, i >> 2);
+    *gptr<uint32_t>(a + i) = dword_at(v, i >> 2);
     i += 4;
   }
   if ((i & 8) && i + 8 <= hi) {
     uint64_t q = (uint64_t)dword_at(v, i >> 2) | ((uint64_t)dword_at(v, (i >> 2) + 1) << 32);
-    *(uint64_t*)(a + i) = q;
+    *gptr<uint64_t>(a + i) = q;
     i += 8;
   }
   if (i + 8 <= hi) {
     uint64_t q = (uint64_t)dword_at(v, i >> 2) | ((uint64_t)dword_at(v, (i >> 2) + 1) << 32);
-    *(uint64_t*)(a + i) = q;
+    *gptr<uint64_t>(a + i) = q;
     i += 8;
   }
   if (i + 4 <= hi) {
-    *(uint32_t*)(a + i) = dword_at(v, i >> 2);
+    *gptr<uint32_t>(a + i) = dword_at(v, i >> 2);
     i += 4;
   }
   if (i + 2 <= hi) {
-    *(uint16_t*)(a + i) = (uint16_t)(dword_at(v, i >> 2) >> (8 * (i & 3)));
+    *gptr<uint16_t>(a + i) = (uint16_t)(dword_at(v, i >> 2) >> (8 * (i & 3)));
     i += 2;
   }
   if (i + 1 <= hi) {
-    *(uint8_t*)(a + i) = (uint8_t)(dword_at(v, i >> 2) >> (8 * (i & 3)));
+    *gptr<uint8_t>(a + i) = (uint8_t)(dword_at(v, i >> 2) >> (8 * (i & 3)));
   }
 }
 
@@ -228,20 +232,11 @@ __device__ __forceinline__ void store_chunk(uintptr_t a, const u32x4& v, int lo,
 // (outputs below 4 GiB); the buffer's size also bounds every access.
 constexpr int kSC1 = 16;  // cache-policy bit of buffer intrinsics: sc1
 
-__device__ __forceinline__ u32x4 coh_load_window(__amdgpu_buffer_rsrc_t r, int64_t w, uint32_t cap, int lo, int hi) {
-  u32x4 v;
-  if (w >= 0 && w + 16 <= (int64_t)cap) {
-    v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(uint32_t)w, 0, kSC1);
-  } else {
-    uint32_t d[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int i = 0; i < 16; ++i)
-      if (i >= lo && i < hi)
-        d[i >> 2] |= uint32_t(__builtin_amdgcn_raw_buffer_load_b8(r, (int)(uint32_t)(w + i), 0, kSC1))
-                     << (8 * (i & 3));
-    v = u32x4{d[0], d[1], d[2], d[3]};
-  }
-  return v;
+__device__ __forceinline__ u32x4 coh_load_bytes(__amdgpu_buffer_rsrc_t r, uint32_t w, int lo, int hi) {
+  uint32_t d[4] = {0u, 0u, 0u, 0u};
+  for (int i = lo; i < hi; ++i)
+    d[i >> 2] |= uint32_t(__builtin_amdgcn_raw_buffer_load_b8(r, (int)(w + i), 0, kSC1)) << (8 * (i & 3));
+  return u32x4{d[0], d[1], d[2], d[3]};
 }
 
 __device__ __forceinline__ void coh_store_chunk(__amdgpu_buffer_rsrc_t r, uint32_t a, const u32x4& v, int lo, int hi) {
@@ -284,7 +279,7 @@ __device__ __forceinline__ void coh_store_chunk(__amdgpu_buffer_rsrc_t r, uint32
 
 __device__ __forceinline__ void compiler_barrier() { asm volatile("" ::: "memory"); }
 
-__device__ __forceinline__ void lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+__device__ __forceinline__ void mem_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
 template <int G, int U, int MODE>
 __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
@@ -313,18 +308,21 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
     out_cap32 = (uint32_t)min<uint64_t>(D.msrc_hi - D.msrc_lo, 0xFFFFFFFFull);
     out_r = __builtin_amdgcn_make_buffer_rsrc((void*)D.out, 0, (int)out_cap32, 0x00020000);
   };
+  // windows of a level (schedule 0)
+  auto level_windows = [&](uint32_t p) -> uint32_t {
+    const uint32_t n = A.lvl_start[p + 1] - A.lvl_start[p];
+    return A.items ? n : (n + G - 1) / G;
+  };
 
   // work item state (replicated on the group's lanes)
-  bool finished = false, have_item = false, started = false;
-  uint64_t item = 0, iter = 0;
-  uint64_t blk = 0;
-  uint32_t lvl = 0, cur_lvl = 0;
-  uint64_t ua = 0, nu = 0;                 // units [ua, ua + nu) of the item
-  uint64_t u_blk = 0;                      // lane j < nu: block of unit ua + j
-  uint32_t u_next = kNone;                 // lane j < nu: that block's next level
+  bool finished = false, have_item = false, started = true;
+  uint64_t iter = 0;
+  uint32_t lvl = 0, cur_lvl = 0, ready = 0;  // schedule 0: levels <= ready may start
   if (MODE == kModeParse) {
-    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < A.n_levels; i += (uint64_t)gridDim.x * kWG)
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < A.n_levels; i += (uint64_t)gridDim.x * kWG) {
       A.tickets[i] = 0u;
+      A.wdone[i] = 0u;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) *A.err = 0u;
   }
   uint64_t t_next = 0, t_end = 0, blk_t_end = 0, pos = 0, bend = 0, litc = 0, xc = 0, yc = 0;
@@ -334,50 +332,76 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
   bool l_pend = false;
   uint32_t idle = 0;
   uint64_t t_last = 0;
+  // a window: explicit record, or the w-th run of G slots from `base`
+  auto set_window = [&](uint64_t k, uint64_t base, uint64_t end) {
+    if (A.items) {
+      const uint64_t e = A.items[k];
+      use_arc((uint32_t)(e >> 40));
+      t_next = e & 0xFFFFFFFFull;
+      t_end = t_next + ((e >> 32) & 0xFFull);
+    } else {
+      t_next = base + k * G;
+      t_end = min(t_next + G, end);
+    }
+  };
 
   for (;;) {
     // ---------------------------------------------------- take a work item
     if (!finished && !have_item) {
       if (MODE == kModeFlow) {
-        // units are taken level by level, so every unit waited on was taken earlier
+        // windows are taken level by level, so every window waited on was taken earlier
         for (;;) {
           if (cur_lvl >= A.n_levels) {
             finished = true;
             break;
           }
-          const uint64_t l1 = A.lvl_start[cur_lvl + 1];
-          uint64_t u = 0;
-          if (gl == 0) u = A.lvl_start[cur_lvl] + atomicAdd(A.tickets + cur_lvl, A.unit_batch);
-          u = __shfl(u, 0, G);
-          if (u < l1) {
-            ua = u;
-            nu = min(l1 - u, (uint64_t)A.unit_batch);
+          uint32_t w = 0;
+          if (gl == 0) w = atomicAdd(A.tickets + cur_lvl, 1u);
+          w = __shfl(w, 0, G);
+          if (w < level_windows(cur_lvl)) {
             lvl = cur_lvl;
+            if (A.items) set_window(A.lvl_start[lvl] + w, 0, 0);
+            else set_window(w, A.lvl_start[lvl], A.lvl_start[lvl + 1]);
             have_item = true;
+            started = lvl <= ready;
             break;
           }
           ++cur_lvl;
         }
       } else if (MODE == kModeLevels) {
-        const uint64_t u = A.unit_lo + (gid + iter * ngroups) * A.unit_batch;
+        const uint64_t k = gid + iter * ngroups;
         ++iter;
-        if (u >= A.unit_hi) {
+        const uint64_t cnt = A.items ? A.hi - A.lo : (A.hi - A.lo + G - 1) / G;
+        if (k >= cnt) {
           finished = true;
         } else {
-          ua = u;
-          nu = min(A.unit_hi - u, (uint64_t)A.unit_batch);
+          if (A.items) set_window(A.lo + k, 0, 0);
+          else set_window(k, A.lo, A.hi);
+          have_item = true;
+        }
+      } else if (MODE == kModePure) {
+        const uint64_t k = gid + iter * ngroups;
+        ++iter;
+        const uint64_t cnt = A.p_unit ? A.nunits : (A.hi - A.lo + G - 1) / G;
+        if (k >= cnt) {
+          finished = true;
+        } else {
+          if (A.p_unit) {
+            t_next = A.p_unit[k];
+            t_end = A.p_unit[k + 1];
+          } else {
+            t_next = A.lo + k * G;
+            t_end = min(t_next + G, A.hi);
+          }
           have_item = true;
         }
       } else {
-        const uint64_t count = (MODE == kModeParse) ? A.nseg : A.nunits;
         const uint64_t k = gid + iter * ngroups;
         ++iter;
-        if (k >= count) finished = true;
-        else { item = k; have_item = true; }
-      }
-      if (have_item) {
-        if (MODE == kModeParse) {
-          const uint64_t* e = A.seg + 8 * item;
+        if (k >= A.nseg) {
+          finished = true;
+        } else {
+          const uint64_t* e = A.seg + 8 * k;
           t_next = e[0];
           t_end = e[1];
           blk_t_end = e[2];
@@ -386,21 +410,12 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
           xc = e[5];
           yc = e[6];
           use_arc((uint32_t)(e[7] >> 32));
-          blk = e[7] & 0xFFFFFFFFull;
+          const uint64_t blk = e[7] & 0xFFFFFFFFull;
           bend = min(D.n, (blk + 1) * bs);
-          if (gl == 0 && pos == blk * bs) D.done_lvl[blk] = D.first_lvl[blk];
-        } else if (MODE == kModePure) {
-          t_next = A.p_unit[item];
-          t_end = A.p_unit[item + 1];
-        } else {
-          if (A.unit_arc) use_arc(A.unit_arc[ua]);
-          const bool has_u = (uint64_t)gl < nu;
-          u_blk = has_u ? A.unit_blk[ua + gl] : 0;
-          u_next = has_u ? A.unit_next[ua + gl] : kNone;
-          t_next = A.unit_tok[ua];
-          t_end = A.unit_tok_end[ua + nu - 1];
+          have_item = true;
         }
-        started = (MODE != kModeFlow);
+      }
+      if (have_item) {
         l_len = m_len = m_done = 0;
         l_pend = false;
       }
@@ -414,14 +429,15 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
       const uint64_t pend_bits = group_bits<G>(__ballot(lane_pend), gw);
       if (pend_bits == 0) {
         if (!started) {
-          // ---------------------------------------------- a unit waits for its own block's lower levels
-          bool ok = true;
-          if ((uint64_t)gl < nu)
-            ok = __hip_atomic_load(D.done_lvl + u_blk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= lvl;
-          if (group_bits<G>(__ballot(!ok), gw) == 0) {
+          // ---------------------------------------------- the level below must be complete
+          uint32_t c = 0;
+          if (gl == 0) c = __hip_atomic_load(A.wdone + (lvl - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          c = __shfl(c, 0, G);
+          if (c >= level_windows(lvl - 1)) {
             started = true;
+            ready = lvl;
             progressed = true;
-            compiler_barrier();
+            compiler_barrier();  // output loads stay after the counter load
           }
         } else if (t_next >= t_end) {
           // ---------------------------------------------- item complete
@@ -430,8 +446,7 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
             compiler_barrier();
             __builtin_amdgcn_s_waitcnt(0);
             compiler_barrier();
-            if ((uint64_t)gl < nu)
-              __hip_atomic_store(D.done_lvl + u_blk, u_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (gl == 0) __hip_atomic_fetch_add(A.wdone + lvl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
           have_item = false;
           progressed = true;
@@ -439,33 +454,48 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
           // ---------------------------------------------- next G tokens
           const uint64_t t = t_next + gl;
           const bool valid = t < t_end;
+          // every lane loads (lanes past the end reread the last token), so the
+          // loads of a step are issued together and waited for once
+          const uint64_t tc = valid ? t : t_end - 1;
           if (MODE == kModePure) {
-            l_dst = valid ? A.p_dst[t] : 0;
-            l_len = valid ? A.p_lit_len[t] : 0u;
-            l_src = valid ? A.p_lit_off[t] : 0;
-            m_len = valid ? A.p_mlen[t] : 0u;
-            m_src = valid ? A.p_src[t] : 0;
+            const uint64_t dst = A.p_dst[tc], loff = A.p_lit_off[tc], src = A.p_src[tc];
+            const uint32_t ll = A.p_lit_len[tc], ml = A.p_mlen[tc];
+            l_dst = valid ? dst : 0;
+            l_len = valid ? ll : 0u;
+            l_src = valid ? loff : 0;
+            m_len = valid ? ml : 0u;
+            m_src = valid ? src : 0;
             m_dst = l_dst + l_len;
           } else if (MODE == kModeParse) {
-            const uint32_t c = valid ? D.cmd[t] : 0u;
+            const uint32_t c_raw = gld(D.cmd, tc);
+            const uint32_t s_lo = gld(D.slo, tc);
+            const uint32_t s_hi = gld(D.shi ? D.shi : D.cmd, tc);  // without a high plane: ignored
+            const uint32_t sl = gld(D.slot, tc);
+            const uint64_t src = (uint64_t)s_lo | (D.shi ? (uint64_t)s_hi << 32 : 0ull);
+            const uint32_t c = valid ? c_raw : 0u;
             const bool last = (t + 1 == blk_t_end);
             const uint32_t Lc = c >> 4, Mc = c & 15u;
             const uint32_t need_l = (valid && Lc == 15u) ? 1u : 0u;
             const uint32_t need_m = (valid && !last && Mc == 15u) ? 1u : 0u;
-            uint32_t tot16;
-            const uint64_t i16 = xc + gscan32<G>(need_l + need_m, gl, tot16);
-            uint32_t e_l = need_l ? D.x16[i16] : 0u;
-            uint32_t e_m = need_m ? D.x16[i16 + need_l] : 0u;
-            const uint32_t w_l = (need_l && e_l == 0xFFFFu) ? 1u : 0u;
-            const uint32_t w_m = (need_m && e_m == 0xFFFFu) ? 1u : 0u;
-            uint32_t tot32;
-            const uint64_t i32 = yc + gscan32<G>(w_l + w_m, gl, tot32);
-            if (w_l) e_l += D.x32[i32];
-            if (w_m) e_m += D.x32[i32 + w_l];
+            uint32_t e_l = 0u, e_m = 0u, tot16 = 0u, tot32 = 0u;
+            if (group_bits<G>(__ballot(need_l + need_m != 0u), gw) != 0) {
+              // length extensions: positions from a group prefix count; a lane
+              // that needs none reads at the cursor, inside the archive
+              const uint64_t i16 = xc + gscan32<G>(need_l + need_m, gl, tot16);
+              const uint32_t x_a = gld(D.x16, i16), x_b = gld(D.x16, i16 + need_l);
+              e_l = need_l ? x_a : 0u;
+              e_m = need_m ? x_b : 0u;
+              const uint32_t w_l = (need_l && e_l == 0xFFFFu) ? 1u : 0u;
+              const uint32_t w_m = (need_m && e_m == 0xFFFFu) ? 1u : 0u;
+              if (group_bits<G>(__ballot(w_l + w_m != 0u), gw) != 0) {
+                const uint64_t i32 = yc + gscan32<G>(w_l + w_m, gl, tot32);
+                const uint32_t y_a = gld(D.x32, i32), y_b = gld(D.x32, i32 + w_l);
+                if (w_l) e_l += y_a;
+                if (w_m) e_m += y_b;
+              }
+            }
             const uint32_t lit_len = (Lc == 15u) ? 15u + e_l : Lc;
             uint32_t mlen = (valid && !last) ? D.min_match + ((Mc == 15u) ? 15u + e_m : Mc) : 0u;
-            uint64_t src = valid ? (uint64_t)D.slo[t] : 0;
-            if (D.shi && valid) src |= (uint64_t)D.shi[t] << 32;
             uint64_t lit_tot;
             const uint64_t loff = litc + gscan64<G>(lit_len, gl, lit_tot);
             uint64_t span_tot;
@@ -477,18 +507,18 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
             pos += span_tot;
             // record the match in plan order; only literal runs are copied here
             if (valid && mlen > 0) {
-              const uint32_t sl = D.slot[t];
               const uint64_t md = tdst + lit_len;
-              D.mtab[sl] = u32x4{(uint32_t)md, mlen, (uint32_t)src,
-                                 (uint32_t)((md >> 32) & 0xFFFFu) | (uint32_t)((src >> 32) << 16)};
+              gst(D.mtab, sl, u32x4{(uint32_t)md, mlen, (uint32_t)src,
+                                    (uint32_t)((md >> 32) & 0xFFFFu) | (uint32_t)((src >> 32) << 16)});
             }
             l_dst = tdst;
             l_len = lit_len;
             l_src = loff;
             m_len = 0;
           } else {
-            // a unit's matches from the match table
-            u32x4 r = valid ? D.mtab[t] : u32x4{0u, 0u, 0u, 0u};
+            // a window's matches from the match table
+            const u32x4 rr = gld((const u32x4*)D.mtab, tc);
+            const u32x4 r = valid ? rr : u32x4{0u, 0u, 0u, 0u};
             m_dst = (uint64_t)r.x | ((uint64_t)(r.w & 0xFFFFu) << 32);
             m_len = r.y;
             m_src = (uint64_t)r.z | ((uint64_t)(r.w >> 16) << 32);
@@ -501,113 +531,103 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
           progressed = true;
         }
       } else {
-        // ------------------------------------------------ form a batch
-        const int first = __builtin_ctzll(pend_bits);
-        const uint64_t my_next = l_pend ? l_dst : (m_dst + m_done);
-        const uint64_t batch_start = __shfl(my_next, first, G);
-        const uint32_t piece = m_rem ? min(m_rem, (uint32_t)(m_dst - m_src) + m_done) : 0u;
-        const uint64_t src_end = m_src + piece;
-        // a match can only collide with bytes of its own block written in
-        // this batch (same-level matches of other blocks never feed it)
-        bool hz = false;
-        if (MODE != kModePure) {
-          const uint64_t own0 = (m_dst >> D.log2_bs) << D.log2_bs;
-          hz = piece > 0 && src_end > max(batch_start, own0);
-        }
-        const uint64_t hz_bits = group_bits<G>(__ballot(hz), gw);
-        const int h = hz_bits ? __builtin_ctzll(hz_bits) : G;
-        const bool inc_l = l_pend && gl <= h;
-        const bool inc_m = piece > 0 && gl < h;
-
-        // ------------------------------------------------ cross-block waits
-        bool ready = true;
-        if (MODE == kModeFlow) {
-          const uint64_t sb0 = m_src >> D.log2_bs;
-          const uint64_t sb1 = inc_m ? ((src_end - 1) >> D.log2_bs) : 0;
-          if (inc_m) {
-            const uint64_t own = m_dst >> D.log2_bs;
-            for (uint64_t b = sb0; b <= sb1; ++b)
-              if (b != own)
-                ready = ready && (__hip_atomic_load(D.done_lvl + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= lvl);
-          }
-          ready = group_bits<G>(__ballot(!ready), gw) == 0;
-          compiler_barrier();  // output loads stay after the done_level loads
-        }
-
-        if (ready) {
-          // ---------------------------------------------- chunk the batch
-          const uintptr_t a_dst = out_b + l_dst;
-          const uintptr_t b_dst = out_b + m_dst + m_done;
-          const uint32_t ca = inc_l ? nchunks(a_dst, l_len) : 0u;
-          const uint32_t cb = inc_m ? nchunks(b_dst, piece) : 0u;
-          uint32_t C;
-          const uint32_t base = gscan32<G>(ca + cb, gl, C);
-          Desc d;
-          d.a_dst = a_dst;
-          d.a_src = (uintptr_t)D.lit + l_src;
-          d.a_len = inc_l ? l_len : 0u;
-          d.b_dst = b_dst;
-          d.b_src = (uintptr_t)D.msrc + m_src;
-          d.b_len = inc_m ? piece : 0u;
-          d.base = base;
-          d.ca = ca;
-          s_desc[threadIdx.x] = d;
-          s_base[threadIdx.x] = base;
-          lds_order();
-          for (uint32_t r = 0; r < C; r += G * U) {
-            u32x4 v[U];
-            uintptr_t slot[U];
-            int lo[U], hi[U];
+        // ------------------------------------------------ one pass over every pending segment
+        // Matches of one level never read each other's output, so every lane
+        // copies at once; a self-overlapping match (period d < length) writes
+        // pieces d, 2d, 4d, ... each read from the already final prefix.
+        const uint32_t piece = m_rem ? (uint32_t)min<uint64_t>(m_rem, (m_dst - m_src) + m_done) : 0u;
+        const bool inc_l = l_pend;
+        const bool inc_m = piece > 0;
+        const uintptr_t a_dst = out_b + l_dst;
+        const uintptr_t b_dst = out_b + m_dst + m_done;
+        const uint32_t ca = inc_l ? nchunks(a_dst, l_len) : 0u;
+        const uint32_t cb = inc_m ? nchunks(b_dst, piece) : 0u;
+        uint32_t C;
+        const uint32_t base = gscan32<G>(ca + cb, gl, C);
+        Desc d;
+        d.a_dst = a_dst;
+        d.a_src = (uintptr_t)D.lit + l_src;
+        d.a_len = inc_l ? l_len : 0u;
+        d.b_dst = b_dst;
+        d.b_src = (uintptr_t)D.msrc + m_src;
+        d.b_len = inc_m ? piece : 0u;
+        d.base = base;
+        d.ca = ca;
+        // a group lives in one wave, whose LDS accesses complete in order
+        s_desc[threadIdx.x] = d;
+        s_base[threadIdx.x] = base;
+        compiler_barrier();
+        for (uint32_t r = 0; r < C; r += G * U) {
+          // owner of chunk k: the last lane whose first chunk is <= k
+          uint32_t own[U];
 #pragma unroll
-            for (int i = 0; i < U; ++i) {
-              const uint32_t k = r + i * G + gl;
-              lo[i] = 0;
-              hi[i] = 0;
-              slot[i] = 0;
-              if (k < C) {
-                int a = 0, b = G;
-                while (b - a > 1) {
-                  const int mid = (a + b) >> 1;
-                  if (s_base[gslot + mid] <= k) a = mid; else b = mid;
-                }
-                const Desc& e = s_desc[gslot + a];
-                const uint32_t q = k - e.base;
-                uintptr_t Dd, S, lb, hb;
-                uint32_t L, qq;
-                if (q < e.ca) {
-                  Dd = e.a_dst; S = e.a_src; L = e.a_len; qq = q;
-                  lb = D.lit_lo; hb = D.lit_hi;
-                } else {
-                  Dd = e.b_dst; S = e.b_src; L = e.b_len; qq = q - e.ca;
-                  lb = D.msrc_lo; hb = D.msrc_hi;
-                }
-                const uintptr_t s0 = (Dd & ~(uintptr_t)15) + 16 * (uintptr_t)qq;
-                const intptr_t l0 = (intptr_t)Dd - (intptr_t)s0;
-                const intptr_t h0 = (intptr_t)(Dd + L) - (intptr_t)s0;
-                lo[i] = l0 > 0 ? (int)l0 : 0;
-                hi[i] = h0 < 16 ? (int)h0 : 16;
-                slot[i] = s0;
-                if (kCoh && q >= e.ca)
-                  v[i] = coh_load_window(out_r, (int64_t)(S + (s0 - Dd) - out_b), out_cap32, lo[i], hi[i]);
-                else
-                  v[i] = load_window(S + (s0 - Dd), lb, hb, lo[i], hi[i]);
-              }
-            }
+          for (int i = 0; i < U; ++i) own[i] = 0;
+#pragma unroll
+          for (int step = G / 2; step >= 1; step >>= 1) {
 #pragma unroll
             for (int i = 0; i < U; ++i)
-              if (hi[i] > lo[i]) {
-                if (kCoh)
-                  coh_store_chunk(out_r, (uint32_t)(slot[i] - out_b), v[i], lo[i], hi[i]);
-                else
-                  store_chunk(slot[i], v[i], lo[i], hi[i]);
-              }
+              if (s_base[gslot + own[i] + step] <= r + i * G + gl) own[i] += step;
           }
-          lds_order();
-          // ---------------------------------------------- retire segments
-          if (inc_l) l_pend = false;
-          if (inc_m) m_done += piece;
-          progressed = true;
+          u32x4 v[U];
+          uintptr_t cdst[U], win[U];
+          int lo[U], hi[U];
+          bool fast[U], from_out[U];
+#pragma unroll
+          for (int i = 0; i < U; ++i) {
+            const uint32_t k = r + i * G + gl;
+            const Desc& e = s_desc[gslot + own[i]];
+            const uint32_t q = k - e.base;
+            const bool m = q >= e.ca;
+            const uintptr_t Dd = m ? e.b_dst : e.a_dst;
+            const uintptr_t S = m ? e.b_src : e.a_src;
+            const uint32_t L = m ? e.b_len : e.a_len;
+            const uint32_t qq = m ? q - e.ca : q;
+            const uintptr_t s0 = (Dd & ~(uintptr_t)15) + 16 * (uintptr_t)qq;
+            const intptr_t l0 = (intptr_t)Dd - (intptr_t)s0;
+            const intptr_t h0 = (intptr_t)(Dd + L) - (intptr_t)s0;
+            const bool valid = k < C;
+            lo[i] = l0 > 0 ? (int)l0 : 0;
+            hi[i] = valid ? (h0 < 16 ? (int)h0 : 16) : 0;
+            cdst[i] = s0;
+            win[i] = S + (s0 - Dd);
+            from_out[i] = m;
+            const uintptr_t lb = m ? D.msrc_lo : D.lit_lo, hb = m ? D.msrc_hi : D.lit_hi;
+            fast[i] = valid && win[i] >= lb && win[i] + 16 <= hb;
+          }
+          // all loads in flight before the first store (a buffer load out of
+          // range returns zeros)
+#pragma unroll
+          for (int i = 0; i < U; ++i) {
+            if (kCoh && from_out[i])
+              v[i] = __builtin_amdgcn_raw_buffer_load_b128(out_r, fast[i] ? (int)(uint32_t)(win[i] - out_b) : 0, 0,
+                                                           kSC1);
+            else
+              v[i] = *gptr<const u32x4_a1>(fast[i] ? win[i] : (uintptr_t)g_pad16);
+          }
+#pragma unroll
+          for (int i = 0; i < U; ++i)
+            if (!fast[i] && hi[i] > lo[i]) {
+              if (kCoh && from_out[i])
+                v[i] = coh_load_bytes(out_r, (uint32_t)(win[i] - out_b), lo[i], hi[i]);
+              else
+                v[i] = load_bytes(win[i], lo[i], hi[i]);
+            }
+#pragma unroll
+          for (int i = 0; i < U; ++i)
+            if (hi[i] > lo[i]) {
+              if (kCoh)
+                coh_store_chunk(out_r, (uint32_t)(cdst[i] - out_b), v[i], lo[i], hi[i]);
+              else
+                store_chunk(cdst[i], v[i], lo[i], hi[i]);
+            }
         }
+        compiler_barrier();
+        // ---------------------------------------------- retire segments
+        if (inc_l) l_pend = false;
+        if (inc_m) m_done += piece;
+        // a further piece reads what this pass wrote
+        if (group_bits<G>(__ballot(m_len > m_done), gw) != 0) mem_order();
+        progressed = true;
       }
     }
     // -------------------------------------------------------- idle guard
@@ -637,32 +657,25 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
 struct lz_dev {
   lz::ArcView v;  // host view of the header (base pointer not kept)
   uint8_t* d_arc = nullptr;
-  uint32_t* d_done = nullptr;
-  uint32_t* d_ctrl = nullptr;  // [0] ticket, [1] err
+  uint32_t* d_ctrl = nullptr;  // [1] error flag
   uint32_t* d_slot = nullptr;
-  uint32_t* d_ublk = nullptr;
-  uint32_t* d_ulvl = nullptr;
-  uint32_t* d_unext = nullptr;
-  uint32_t* d_utok = nullptr;
-  uint32_t* d_first = nullptr;
   uint32_t* d_lvls = nullptr;
   uint32_t* d_tick = nullptr;
+  uint32_t* d_wdone = nullptr;
   uint64_t* d_seg = nullptr;
   uint64_t n_seg = 0;
   u32x4* d_mtab = nullptr;
-  uint64_t n_units = 0, n_match = 0;
-  std::vector<uint64_t> lvl_start;  // first unit of each level, n_levels + 1 entries
-  // host copies of the plan's work lists (batch decodes merge them)
-  std::vector<uint32_t> h_ublk, h_ulvl, h_unext, h_utok;
-  std::vector<uint64_t> h_seg;
+  uint64_t n_match = 0;
+  std::vector<uint64_t> lvl_start;  // first match-table slot of each level, n_levels + 1 entries
+  std::vector<uint64_t> h_seg;      // host copy of the parse segments (batch decodes merge them)
   int cu_count = 0;
   // replayable launch sequences, one per (output, config)
   struct GraphKey {
     uint8_t* out;
     uint64_t cap;
-    uint32_t G, U, sched, batch;
+    uint32_t G, U, sched;
     bool operator==(const GraphKey& o) const {
-      return out == o.out && cap == o.cap && G == o.G && U == o.U && sched == o.sched && batch == o.batch;
+      return out == o.out && cap == o.cap && G == o.G && U == o.U && sched == o.sched;
     }
   };
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
@@ -683,26 +696,21 @@ struct lz_dev {
 namespace {
 
 struct DevLayout {
-  uint64_t arc, done, ctrl, slot, ublk, ulvl, unext, utok, first, lvls, tick, seg, mtab, total;
+  uint64_t arc, ctrl, slot, lvls, tick, wdone, seg, mtab, total;
 };
 
-// Device layout for an archive; unit and match counts are bounded by n_tok.
+// Device layout for an archive; level and match counts are bounded by n_tok.
 DevLayout layout(const lz::ArcView& v) {
   auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
   const uint64_t T = v.n_tok;
   DevLayout L;
   L.arc = 0;
-  L.done = a256(v.total);
-  L.ctrl = a256(L.done + 4 * (v.nb + 1));
+  L.ctrl = a256(v.total);
   L.slot = a256(L.ctrl + 256);
-  L.ublk = a256(L.slot + 4 * (T + 1));
-  L.ulvl = a256(L.ublk + 4 * (T + 1));
-  L.unext = a256(L.ulvl + 4 * (T + 1));
-  L.utok = a256(L.unext + 4 * (T + 1));
-  L.first = a256(L.utok + 4 * (T + 2));
-  L.lvls = a256(L.first + 4 * (v.nb + 1));
+  L.lvls = a256(L.slot + 4 * (T + 1));
   L.tick = a256(L.lvls + 4 * (T + 2));
-  L.seg = a256(L.tick + 4 * (T + 2));
+  L.wdone = a256(L.tick + 4 * (T + 2));
+  L.seg = a256(L.wdone + 4 * (T + 2));
   L.mtab = a256(L.seg + 64 * (T / kSegTok + v.nb + 2));
   L.total = a256(L.mtab + 16 * (T + 1));
   return L;
@@ -714,9 +722,10 @@ DevLayout layout(const lz::ArcView& v) {
     if (e_ != hipSuccess) return lz::fail(LZ_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
   } while (0)
 
-// Host plan: levels -> units ordered by (level, block) -> match-table slots.
+// Host plan: dependency depth of every match -> match-table slots ordered by
+// (depth, token); parse segments with their stream cursors.
 struct Plan {
-  std::vector<uint32_t> slot, ublk, ulvl, unext, utok, first, lvls32;
+  std::vector<uint32_t> slot, lvls32;
   std::vector<uint64_t> seg;  // parse segments, 8 words each
   std::vector<uint64_t> lvl_start;
   uint64_t n_match = 0;
@@ -724,92 +733,29 @@ struct Plan {
 
 int build_plan(const lz::ArcView& v, Plan& P) {
   const uint64_t T = v.n_tok;
-  std::vector<uint32_t> lv(T + 1, 0);
+  std::vector<uint32_t> depth(T + 1, 0);
   std::vector<uint8_t> hasm(T + 1, 0);
   uint32_t mx = 0;
-  int rc = lz::compute_levels(v, lv.data(), &mx, hasm.data());
+  int rc = lz::compute_levels(v, depth.data(), &mx, hasm.data());
   if (rc) return rc;
   const uint64_t* tab = v.tab();
-  // per block: its match tokens sorted by (level, index); its units in level order
-  std::vector<uint64_t> mstart(v.nb + 1, 0);
-  for (uint64_t b = 0; b < v.nb; ++b) {
-    uint64_t c = 0;
-    for (uint64_t t = tab[4 * b]; t < tab[4 * b + 4]; ++t) c += hasm[t];
-    mstart[b + 1] = mstart[b] + c;
-  }
-  const uint64_t M = mstart[v.nb];
+  // counting sort of the matches by depth (1..mx), token order inside a depth
+  const uint64_t NL = mx;
+  std::vector<uint64_t> cnt(NL + 2, 0);
+  uint64_t M = 0;
+  for (uint64_t t = 0; t < T; ++t)
+    if (hasm[t]) {
+      cnt[depth[t]]++;
+      ++M;
+    }
   P.n_match = M;
   if (M > 0xFFFFFFF0ull) return lz::fail(LZ_E_INVAL, "too many matches for 32-bit plan indices");
-  std::vector<uint64_t> order(M);  // (level << 32 | local rank) sorted per block -> token index
-  std::vector<uint32_t> ord_lvl(M);
-  std::vector<uint64_t> ustart(v.nb + 1, 0);  // per block count of units, then prefix
-  {
-    std::vector<uint64_t> nunits(v.nb, 0);
-    std::vector<std::thread> pool;
-    unsigned W = std::min<unsigned>(lz::hw_threads(0), 16);
-    std::atomic<uint64_t> next{0};
-    for (unsigned w = 0; w < W; ++w)
-      pool.emplace_back([&] {
-        std::vector<std::pair<uint32_t, uint64_t>> tmp;
-        for (;;) {
-          uint64_t b = next.fetch_add(1);
-          if (b >= v.nb) break;
-          tmp.clear();
-          for (uint64_t t = tab[4 * b]; t < tab[4 * b + 4]; ++t)
-            if (hasm[t]) tmp.emplace_back(lv[t], t);
-          std::stable_sort(tmp.begin(), tmp.end(),
-                           [](const std::pair<uint32_t, uint64_t>& x, const std::pair<uint32_t, uint64_t>& y) {
-                             return x.first < y.first;
-                           });
-          uint64_t u = 0;
-          for (size_t i = 0; i < tmp.size(); ++i) {
-            order[mstart[b] + i] = tmp[i].second;
-            ord_lvl[mstart[b] + i] = tmp[i].first;
-            if (i == 0 || tmp[i].first != tmp[i - 1].first) ++u;
-          }
-          nunits[b] = u;
-        }
-      });
-    for (auto& t : pool) t.join();
-    for (uint64_t b = 0; b < v.nb; ++b) ustart[b + 1] = ustart[b] + nunits[b];
-  }
-  const uint64_t NU = ustart[v.nb];
-  const uint64_t NL = M ? (uint64_t)mx + 1 : 0;
-  // count units per level, then place each block's units in (level, block) order
-  std::vector<uint64_t> per_lvl(NL + 1, 0);
-  std::vector<uint32_t> bu_lvl(NU), bu_cnt(NU);  // block-major unit list
-  for (uint64_t b = 0; b < v.nb; ++b) {
-    uint64_t u = ustart[b];
-    for (uint64_t i = mstart[b]; i < mstart[b + 1]; ++i) {
-      if (i == mstart[b] || ord_lvl[i] != ord_lvl[i - 1]) {
-        bu_lvl[u] = ord_lvl[i];
-        bu_cnt[u] = 0;
-        ++u;
-      }
-      bu_cnt[u - 1]++;
-    }
-  }
-  for (uint64_t u = 0; u < NU; ++u) per_lvl[bu_lvl[u] + 1]++;
   P.lvl_start.assign(NL + 1, 0);
-  for (uint64_t p = 0; p < NL; ++p) P.lvl_start[p + 1] = P.lvl_start[p] + per_lvl[p + 1];
+  for (uint64_t p = 0; p < NL; ++p) P.lvl_start[p + 1] = P.lvl_start[p] + cnt[p + 1];
   std::vector<uint64_t> cursor(P.lvl_start.begin(), P.lvl_start.end());
-  std::vector<uint32_t> uid_of(NU);  // block-major unit -> global unit id
-  P.ublk.assign(NU, 0);
-  P.ulvl.assign(NU, 0);
-  P.unext.assign(NU, kNone);
-  std::vector<uint32_t> ucnt(NU);
-  P.first.assign(v.nb + 1, kNone);
-  for (uint64_t b = 0; b < v.nb; ++b) {
-    for (uint64_t u = ustart[b]; u < ustart[b + 1]; ++u) {
-      uint64_t g = cursor[bu_lvl[u]]++;
-      uid_of[u] = (uint32_t)g;
-      P.ublk[g] = (uint32_t)b;
-      P.ulvl[g] = bu_lvl[u];
-      ucnt[g] = bu_cnt[u];
-      if (u + 1 < ustart[b + 1]) P.unext[g] = bu_lvl[u + 1];
-    }
-    if (ustart[b + 1] > ustart[b]) P.first[b] = bu_lvl[ustart[b]];
-  }
+  P.slot.assign(T + 1, kNone);
+  for (uint64_t t = 0; t < T; ++t)
+    if (hasm[t]) P.slot[t] = (uint32_t)cursor[depth[t] - 1]++;
   P.lvls32.assign(P.lvl_start.begin(), P.lvl_start.end());
   // parse segments: every kSegTok tokens of a block, with the cursors there
   {
@@ -838,16 +784,6 @@ int build_plan(const lz::ArcView& v, Plan& P) {
     P.seg.reserve(tot);
     for (auto& o : per) P.seg.insert(P.seg.end(), o.begin(), o.end());
   }
-  P.utok.assign(NU + 1, 0);
-  for (uint64_t g = 0; g < NU; ++g) P.utok[g + 1] = P.utok[g] + ucnt[g];
-  P.slot.assign(T + 1, kNone);
-  for (uint64_t b = 0; b < v.nb; ++b) {
-    uint64_t i = mstart[b];
-    for (uint64_t u = ustart[b]; u < ustart[b + 1]; ++u) {
-      uint32_t g = uid_of[u];
-      for (uint32_t k = 0; k < ucnt[g]; ++k, ++i) P.slot[order[i]] = P.utok[g] + k;
-    }
-  }
   return 0;
 }
 
@@ -874,8 +810,6 @@ ArcDesc arc_desc(const lz_dev* h, uint8_t* out, uint64_t out_cap) {
   d.msrc_hi = (uintptr_t)out + out_cap;
   d.slot = h->d_slot;
   d.mtab = h->d_mtab;
-  d.first_lvl = h->d_first;
-  d.done_lvl = h->d_done;
   return d;
 }
 
@@ -883,13 +817,9 @@ KArgs base_args(const lz_dev* h) {
   KArgs A;
   memset(&A, 0, sizeof(A));
   A.one = arc_desc(h, nullptr, 0);
-  A.unit_blk = h->d_ublk;
-  A.unit_lvl = h->d_ulvl;
-  A.unit_next = h->d_unext;
-  A.unit_tok = h->d_utok;
-  A.unit_tok_end = h->d_utok + 1;
   A.lvl_start = h->d_lvls;
   A.tickets = h->d_tick;
+  A.wdone = h->d_wdone;
   A.seg = h->d_seg;
   A.nseg = h->n_seg;
   A.err = h->d_ctrl + 1;
@@ -908,14 +838,10 @@ kfn_t pick_kernel(uint32_t G, uint32_t U) {
   return nullptr;
 }
 
-int resolve_cfg(const lz_decode_cfg* cfg, uint32_t& G, uint32_t& U, uint32_t& sched, uint32_t* batch = nullptr) {
+int resolve_cfg(const lz_decode_cfg* cfg, uint32_t& G, uint32_t& U, uint32_t& sched) {
   G = cfg ? cfg->G : 64;
   U = cfg ? cfg->unroll : 2;
   sched = cfg ? cfg->schedule : 1;
-  if (batch) {
-    *batch = (cfg && cfg->unit_batch) ? cfg->unit_batch : 1;
-    if (*batch > G) return lz::fail(LZ_E_INVAL, "unit_batch must be at most G");
-  }
   if (cfg && cfg->wg_size && cfg->wg_size != 256) return lz::fail(LZ_E_INVAL, "wg_size must be 0 or 256");
   if (!(G == 8 || G == 16 || G == 32 || G == 64)) return lz::fail(LZ_E_INVAL, "G must be 8, 16, 32 or 64");
   if (!(U == 1 || U == 2 || U == 4)) return lz::fail(LZ_E_INVAL, "unroll must be 1, 2 or 4");
@@ -981,26 +907,16 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
   h->v.base = h->host_arc.data();
   uint8_t* base = (uint8_t*)d_buf;
   h->d_arc = base + L.arc;
-  h->d_done = (uint32_t*)(base + L.done);
   h->d_ctrl = (uint32_t*)(base + L.ctrl);
   h->d_slot = (uint32_t*)(base + L.slot);
-  h->d_ublk = (uint32_t*)(base + L.ublk);
-  h->d_ulvl = (uint32_t*)(base + L.ulvl);
-  h->d_unext = (uint32_t*)(base + L.unext);
-  h->d_utok = (uint32_t*)(base + L.utok);
-  h->d_first = (uint32_t*)(base + L.first);
   h->d_lvls = (uint32_t*)(base + L.lvls);
   h->d_tick = (uint32_t*)(base + L.tick);
+  h->d_wdone = (uint32_t*)(base + L.wdone);
   h->d_seg = (uint64_t*)(base + L.seg);
   h->n_seg = P.seg.size() / 8;
   h->d_mtab = (u32x4*)(base + L.mtab);
-  h->n_units = P.ublk.size();
   h->n_match = P.n_match;
   h->lvl_start = P.lvl_start;
-  h->h_ublk = P.ublk;
-  h->h_ulvl = P.ulvl;
-  h->h_unext = P.unext;
-  h->h_utok = P.utok;
   h->h_seg = P.seg;
   hipStream_t s = (hipStream_t)stream;
   int dev = 0;
@@ -1016,9 +932,7 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
     uint64_t bytes;
   };
   const Piece pieces[] = {
-      {h->d_slot, P.slot.data(), 4 * P.slot.size()},    {h->d_ublk, P.ublk.data(), 4 * P.ublk.size()},
-      {h->d_ulvl, P.ulvl.data(), 4 * P.ulvl.size()},    {h->d_unext, P.unext.data(), 4 * P.unext.size()},
-      {h->d_utok, P.utok.data(), 4 * P.utok.size()},    {h->d_first, P.first.data(), 4 * P.first.size()},
+      {h->d_slot, P.slot.data(), 4 * P.slot.size()},
       {h->d_lvls, P.lvls32.data(), 4 * P.lvls32.size()},
       {h->d_seg, P.seg.data(), 8 * P.seg.size()},
   };
@@ -1058,23 +972,22 @@ int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decod
   if (out_cap < h->v.n) return lz::fail(LZ_E_INVAL, "output capacity %llu < n %llu", (unsigned long long)out_cap,
                                         (unsigned long long)h->v.n);
   if (h->v.n && !d_out) return lz::fail(LZ_E_INVAL, "null output");
-  uint32_t G, U, sched, batch;
-  int rc = resolve_cfg(cfg, G, U, sched, &batch);
+  uint32_t G, U, sched;
+  int rc = resolve_cfg(cfg, G, U, sched);
   if (rc) return rc;
   if (sched == 0 && out_cap > 0xFFFFFFFFull)
     return lz::fail(LZ_E_INVAL, "schedule 0 addresses outputs below 4 GiB; use schedule 1");
   if (h->v.nb == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
-  lz_dev::GraphKey key{d_out, out_cap, G, U, sched, batch};
+  lz_dev::GraphKey key{d_out, out_cap, G, U, sched};
   for (auto& g : h->graphs)
     if (g.first == key) {
       HIPCHK(hipGraphLaunch(g.second, s));
       return 0;
     }
-  // build the launch sequence once: parse, then the match units
+  // build the launch sequence once: parse, then the match windows level by level
   KArgs A = base_args(h);
   A.one = arc_desc(h, d_out, out_cap);
-  A.unit_batch = batch;
   struct Launch {
     kfn_t k;
     uint64_t grid;
@@ -1083,22 +996,22 @@ int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decod
   std::vector<Launch> seq;
   kfn_t kp = pick_kernel<kModeParse>(G, U);
   seq.push_back({kp, grid_for(h->n_seg, resident_groups(kp, h->cu_count, G), G), A});
-  if (h->n_units) {
+  if (h->n_match) {
     if (sched == 0) {
       kfn_t k = pick_kernel<kModeFlow>(G, U);
-      KArgs a = A;
-      a.unit_lo = 0;
-      a.unit_hi = h->n_units;
-      seq.push_back({k, grid_for((h->n_units + batch - 1) / batch, resident_groups(k, h->cu_count, G), G), a});
+      uint64_t windows = 0;
+      for (size_t p = 0; p + 1 < h->lvl_start.size(); ++p)
+        windows += (h->lvl_start[p + 1] - h->lvl_start[p] + G - 1) / G;
+      seq.push_back({k, grid_for(windows, resident_groups(k, h->cu_count, G), G), A});
     } else {
       kfn_t k = pick_kernel<kModeLevels>(G, U);
       const uint64_t res = resident_groups(k, h->cu_count, G);
       for (size_t p = 0; p + 1 < h->lvl_start.size(); ++p) {
         KArgs a = A;
-        a.unit_lo = h->lvl_start[p];
-        a.unit_hi = h->lvl_start[p + 1];
-        if (a.unit_hi == a.unit_lo) continue;
-        seq.push_back({k, grid_for((a.unit_hi - a.unit_lo + batch - 1) / batch, res, G), a});
+        a.lo = h->lvl_start[p];
+        a.hi = h->lvl_start[p + 1];
+        if (a.hi == a.lo) continue;
+        seq.push_back({k, grid_for((a.hi - a.lo + G - 1) / G, res, G), a});
       }
     }
   }
@@ -1352,7 +1265,7 @@ int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const u
   // staging layout: dst | lit_off | src (u64) | lit_len | mlen (u32) | unit starts (u64, one unit per piece)
   const uint64_t np = P->p_dst.size();
   auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
-  P->staging_bytes = a256(8 * np) * 3 + a256(4 * np) * 2 + a256(8 * (np + 1));
+  P->staging_bytes = a256(8 * np) * 3 + a256(4 * np) * 2;
   P->scratch_bytes = P->staging_bytes + a256(P->data_bytes + 16);
   *out = P;
   return 0;
@@ -1394,8 +1307,6 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
   const uint64_t o_src = o; memcpy(st + o, P->p_src.data(), 8 * np); o += a256(8 * np);
   const uint64_t o_llen = o; memcpy(st + o, P->p_lit_len.data(), 4 * np); o += a256(4 * np);
   const uint64_t o_mlen = o; memcpy(st + o, P->p_mlen.data(), 4 * np); o += a256(4 * np);
-  const uint64_t o_units = o;
-  for (uint64_t i = 0; i <= np; ++i) ((uint64_t*)(st + o))[i] = i;  // one piece per unit
   uint8_t* D = (uint8_t*)d_scratch;
   HIPCHK(hipMemcpyAsync(D, st, P->staging_bytes, hipMemcpyHostToDevice, s));
   uint8_t* data = D + P->staging_bytes;
@@ -1413,8 +1324,8 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
     const uint64_t p0 = P->lvl_piece[l], p1 = P->lvl_piece[l + 1];
     if (p1 == p0) continue;
     KArgs a = A;
-    a.p_unit = (const uint64_t*)(D + o_units) + p0;
-    a.nunits = p1 - p0;
+    a.lo = p0;  // windows of G pieces (pieces of one depth are independent)
+    a.hi = p1;
     const bool gather = (l + 1 == L);
     if (l == 0) {  // literal pieces: archive literals -> scratch data
       a.one.lit = h->d_arc + h->v.off_lit;
@@ -1432,7 +1343,7 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
     a.one.msrc = data;
     a.one.msrc_lo = (uintptr_t)data;
     a.one.msrc_hi = (uintptr_t)data + P->data_bytes + 16;
-    hipLaunchKernelGGL(k, dim3((unsigned)grid_for(a.nunits, res, G)), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(k, dim3((unsigned)grid_for((p1 - p0 + G - 1) / G, res, G)), dim3(kWG), 0, s, a);
     HIPCHK(hipGetLastError());
   }
   return 0;
@@ -1489,26 +1400,34 @@ struct BatchGroup {
   std::vector<uint32_t> arcs;  // archive indices
 };
 
-uint64_t group_scratch(const std::vector<lz_dev*>& H, const BatchGroup& g, uint64_t* nseg_out, uint64_t* nu_out,
-                       uint64_t* nl_out) {
-  uint64_t nseg = 0, nu = 0, nl = 0;
+// windows of G match-table slots over every level of the group's archives
+uint64_t group_windows(const std::vector<lz_dev*>& H, const BatchGroup& g, uint32_t G, uint64_t* nl_out) {
+  uint64_t nw = 0, nl = 0;
   for (uint32_t i : g.arcs) {
-    nseg += H[i]->h_seg.size() / 8;
-    nu += H[i]->h_ublk.size();
-    nl = std::max<uint64_t>(nl, H[i]->lvl_start.size() ? H[i]->lvl_start.size() - 1 : 0);
+    const auto& ls = H[i]->lvl_start;
+    for (size_t p = 0; p + 1 < ls.size(); ++p) nw += (ls[p + 1] - ls[p] + G - 1) / G;
+    nl = std::max<uint64_t>(nl, ls.size() ? ls.size() - 1 : 0);
   }
+  if (nl_out) *nl_out = nl;
+  return nw;
+}
+
+uint64_t group_scratch(const std::vector<lz_dev*>& H, const BatchGroup& g, uint64_t* nseg_out, uint64_t* nw_out,
+                       uint64_t* nl_out) {
+  uint64_t nseg = 0, nl = 0;
+  for (uint32_t i : g.arcs) nseg += H[i]->h_seg.size() / 8;
+  const uint64_t nw = group_windows(H, g, g.cfg.G ? g.cfg.G : 64, &nl);
   auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
   if (nseg_out) *nseg_out = nseg;
-  if (nu_out) *nu_out = nu;
+  if (nw_out) *nw_out = nw;
   if (nl_out) *nl_out = nl;
-  return a256(sizeof(ArcDesc) * g.arcs.size()) + a256(64 * nseg) + 6 * a256(4 * (nu + 1)) + a256(4 * (nl + 1)) +
-         a256(4 * (nl + 1)) + 256;
+  return a256(sizeof(ArcDesc) * g.arcs.size()) + a256(64 * nseg) + a256(8 * (nw + 1)) + 3 * a256(4 * (nl + 1)) + 256;
 }
 
 std::vector<BatchGroup> make_groups(uint32_t count, const lz_decode_cfg* cfgs) {
   std::vector<BatchGroup> groups;
   for (uint32_t i = 0; i < count; ++i) {
-    lz_decode_cfg c{64, 2, 1, 0, 1};
+    lz_decode_cfg c{64, 2, 1, 0};
     if (cfgs) c = cfgs[i];
     if (!c.G) c.G = 64;
     if (!c.unroll) c.unroll = 2;
@@ -1538,6 +1457,7 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
                     const lz_decode_cfg* cfgs, void* d_scratch, uint64_t scratch_cap, void* stream, lz_batch** out) {
   if (!out || (count && (!handles || !d_out || !out_cap)) || !d_scratch) return lz::fail(LZ_E_INVAL, "null argument");
   *out = nullptr;
+  if (count >= (1u << 24)) return lz::fail(LZ_E_INVAL, "at most 2^24 - 1 archives per batch");
   std::vector<lz_dev*> H(handles, handles + count);
   for (uint32_t i = 0; i < count; ++i) {
     if (!H[i]) return lz::fail(LZ_E_INVAL, "null handle %u", i);
@@ -1575,25 +1495,19 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
   for (auto& g : groups) {
     uint32_t G, U, sched;
     (void)resolve_cfg(&g.cfg, G, U, sched);
-    uint64_t nseg, nu, nl;
-    group_scratch(H, g, &nseg, &nu, &nl);
+    uint64_t nseg, nw, nl;
+    group_scratch(H, g, &nseg, &nw, &nl);
     const uint64_t o_desc = off;
     const uint64_t o_seg = o_desc + a256(sizeof(ArcDesc) * g.arcs.size());
-    const uint64_t o_ublk = o_seg + a256(64 * nseg);
-    const uint64_t o_uarc = o_ublk + a256(4 * (nu + 1));
-    const uint64_t o_ulvl = o_uarc + a256(4 * (nu + 1));
-    const uint64_t o_unext = o_ulvl + a256(4 * (nu + 1));
-    const uint64_t o_utok = o_unext + a256(4 * (nu + 1));
-    const uint64_t o_utend = o_utok + a256(4 * (nu + 1));
-    const uint64_t o_lvls = o_utend + a256(4 * (nu + 1));
+    const uint64_t o_items = o_seg + a256(64 * nseg);
+    const uint64_t o_lvls = o_items + a256(8 * (nw + 1));
     const uint64_t o_tick = o_lvls + a256(4 * (nl + 1));
-    const uint64_t o_err = o_tick + a256(4 * (nl + 1));
+    const uint64_t o_wdone = o_tick + a256(4 * (nl + 1));
+    const uint64_t o_err = o_wdone + a256(4 * (nl + 1));
     off = o_err + 256;
     ArcDesc* desc = (ArcDesc*)(img.data() + o_desc);
     uint64_t* seg = (uint64_t*)(img.data() + o_seg);
-    uint32_t *ublk = (uint32_t*)(img.data() + o_ublk), *uarc = (uint32_t*)(img.data() + o_uarc);
-    uint32_t *ulvl = (uint32_t*)(img.data() + o_ulvl), *unext = (uint32_t*)(img.data() + o_unext);
-    uint32_t *utok = (uint32_t*)(img.data() + o_utok), *utend = (uint32_t*)(img.data() + o_utend);
+    uint64_t* items = (uint64_t*)(img.data() + o_items);
     uint32_t* lvls = (uint32_t*)(img.data() + o_lvls);
     uint64_t si = 0;
     for (uint32_t j = 0; j < g.arcs.size(); ++j) {
@@ -1605,61 +1519,47 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
         ++si;
       }
     }
-    // units of all archives, level-major
-    uint64_t ui = 0;
+    // windows of all archives, level-major
+    uint64_t wi = 0;
     for (uint64_t p = 0; p < nl; ++p) {
-      lvls[p] = (uint32_t)ui;
+      lvls[p] = (uint32_t)wi;
       for (uint32_t j = 0; j < g.arcs.size(); ++j) {
-        lz_dev* h = H[g.arcs[j]];
-        if (p + 1 >= h->lvl_start.size()) continue;
-        for (uint64_t u = h->lvl_start[p]; u < h->lvl_start[p + 1]; ++u, ++ui) {
-          ublk[ui] = h->h_ublk[u];
-          uarc[ui] = j;
-          ulvl[ui] = h->h_ulvl[u];
-          unext[ui] = h->h_unext[u];
-          utok[ui] = h->h_utok[u];
-          utend[ui] = h->h_utok[u + 1];
-        }
+        const auto& ls = H[g.arcs[j]]->lvl_start;
+        if (p + 1 >= ls.size()) continue;
+        for (uint64_t q = ls[p]; q < ls[p + 1]; q += G)
+          items[wi++] = q | (std::min<uint64_t>(G, ls[p + 1] - q) << 32) | ((uint64_t)j << 40);
       }
     }
-    lvls[nl] = (uint32_t)ui;
+    lvls[nl] = (uint32_t)wi;
     KArgs A;
     memset(&A, 0, sizeof(A));
     A.arcs = (const ArcDesc*)(D0 + o_desc);
     A.one = desc[0];
     A.seg = (const uint64_t*)(D0 + o_seg);
     A.nseg = nseg;
-    A.unit_blk = (const uint32_t*)(D0 + o_ublk);
-    A.unit_arc = (const uint32_t*)(D0 + o_uarc);
-    A.unit_lvl = (const uint32_t*)(D0 + o_ulvl);
-    A.unit_next = (const uint32_t*)(D0 + o_unext);
-    A.unit_tok = (const uint32_t*)(D0 + o_utok);
-    A.unit_tok_end = (const uint32_t*)(D0 + o_utend);
+    A.items = (const uint64_t*)(D0 + o_items);
     A.lvl_start = (const uint32_t*)(D0 + o_lvls);
     A.tickets = (uint32_t*)(D0 + o_tick);
+    A.wdone = (uint32_t*)(D0 + o_wdone);
     A.err = (uint32_t*)(D0 + o_err);
     A.n_levels = (uint32_t)nl;
-    A.unit_batch = 1;
     if (nseg) {
       kfn_t kp = pick_kernel<kModeParse>(G, U);
       seq.push_back({kp, grid_for(nseg, resident_groups(kp, cu, G), G), A});
     }
-    if (nu) {
+    if (nw) {
       if (sched == 0) {
         kfn_t k = pick_kernel<kModeFlow>(G, U);
-        KArgs a = A;
-        a.unit_lo = 0;
-        a.unit_hi = nu;
-        seq.push_back({k, grid_for(nu, resident_groups(k, cu, G), G), a});
+        seq.push_back({k, grid_for(nw, resident_groups(k, cu, G), G), A});
       } else {
         kfn_t k = pick_kernel<kModeLevels>(G, U);
         const uint64_t res = resident_groups(k, cu, G);
         for (uint64_t p = 0; p < nl; ++p) {
           KArgs a = A;
-          a.unit_lo = lvls[p];
-          a.unit_hi = lvls[p + 1];
-          if (a.unit_hi == a.unit_lo) continue;
-          seq.push_back({k, grid_for(a.unit_hi - a.unit_lo, res, G), a});
+          a.lo = lvls[p];
+          a.hi = lvls[p + 1];
+          if (a.hi == a.lo) continue;
+          seq.push_back({k, grid_for(a.hi - a.lo, res, G), a});
         }
       }
     }
@@ -1759,12 +1659,12 @@ extern "C" int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* cons
       C.push_back(out_cap[i]);
       bytes += handles[i]->v.n;
     }
-    lz_decode_cfg best{64, 2, 1, 0, 1};
+    lz_decode_cfg best{64, 2, 1, 0};
     float best_ms = 1e30f, default_ms = -1.f;
     for (uint32_t S : Ss)
       for (uint32_t G : Gs)
         for (uint32_t U : Us) {
-          lz_decode_cfg c{G, U, S, 0, 1};
+          lz_decode_cfg c{G, U, S, 0};
           bool too_big = false;
           if (S == 0)
             for (uint64_t cap : C) too_big = too_big || cap > 0xFFFFFFFFull;
@@ -1826,7 +1726,7 @@ struct lz_server {
   uint8_t* arena = nullptr;
   uint64_t arena_bytes = 0;
   uint32_t slots = 0;
-  lz_decode_cfg cfg{64, 2, 1, 0, 1};
+  lz_decode_cfg cfg{64, 2, 1, 0};
   hipStream_t streams[2] = {nullptr, nullptr};
   uint32_t next_stream = 0;
   struct Req {

@@ -825,9 +825,13 @@ namespace lz {
 // source interval is resolved by a binary search in the source block's runs
 // only; a source interval that spans two blocks is split.
 int compute_levels(const ArcView& v, uint32_t* levels, uint32_t* max_level, uint8_t* has_match) {
+  // Dependency depth: literal bytes 0, a match 1 + the largest depth among the
+  // writers of its source bytes (its own output excluded).  Per block, the
+  // output is kept as runs {start, depth} of the tokens' literal and match
+  // parts, so a source interval is answered by a binary search and a scan.
   struct Run {
     uint32_t start;  // offset in block
-    uint32_t level;
+    uint32_t depth;
   };
   std::vector<std::vector<Run>> runs(v.nb);
   uint32_t mx = 0;
@@ -836,10 +840,11 @@ int compute_levels(const ArcView& v, uint32_t* levels, uint32_t* max_level, uint
     int rc = walk_block(v, b, [&](uint64_t t, const Tok& k) {
       const uint64_t b0 = b << v.log2_bs;
       if (k.lit_len) mine.push_back(Run{uint32_t(k.dst - b0), 0});
-      uint32_t L = 0;
+      uint32_t dep = 0;
       if (k.mlen) {
         const uint64_t m0 = k.dst + k.lit_len;
         const uint64_t s = k.src, e = std::min(k.src + k.mlen, m0);  // own bytes excluded
+        uint32_t deepest = 0;
         for (uint64_t q = s; q < e;) {
           const uint64_t sb = q >> v.log2_bs;
           const uint64_t sb_end = std::min(e, (sb + 1) << v.log2_bs);
@@ -849,14 +854,15 @@ int compute_levels(const ArcView& v, uint32_t* levels, uint32_t* max_level, uint
           size_t i = std::upper_bound(R.begin(), R.end(), lo, [](uint32_t x, const Run& r) { return x < r.start; }) -
                      R.begin();
           i = i ? i - 1 : 0;
-          for (; i < R.size() && R[i].start < hi; ++i) L = std::max(L, R[i].level + (sb != b ? 1u : 0u));
+          for (; i < R.size() && R[i].start < hi; ++i) deepest = std::max(deepest, R[i].depth);
           q = sb_end;
         }
-        mine.push_back(Run{uint32_t(m0 - b0), L});
+        dep = deepest + 1;
+        mine.push_back(Run{uint32_t(m0 - b0), dep});
       }
-      if (levels) levels[t] = L;
+      if (levels) levels[t] = dep;
       if (has_match) has_match[t] = k.mlen ? 1 : 0;
-      mx = std::max(mx, L);
+      mx = std::max(mx, dep);
     });
     if (rc) return fail(LZ_E_CORRUPT, "block %llu fails validation", (unsigned long long)b);
   }

@@ -47,7 +47,7 @@ class Info(ctypes.Structure):
 
 
 class DecodeCfg(ctypes.Structure):
-    _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("wg_size", _u32), ("unit_batch", _u32)]
+    _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("wg_size", _u32)]
 
 
 class TuneReport(ctypes.Structure):
@@ -237,9 +237,9 @@ def fnv1a64(data, seed=0xcbf29ce484222325):
     return int(lib().lz_fnv1a64(a.ctypes.data, a.size, seed))
 
 
-def _cfg(G=64, unroll=2, schedule=1, unit_batch=0):
+def _cfg(G=64, unroll=2, schedule=1):
     c = DecodeCfg()
-    c.G, c.unroll, c.schedule, c.wg_size, c.unit_batch = G, unroll, schedule, 0, unit_batch
+    c.G, c.unroll, c.schedule, c.wg_size = G, unroll, schedule, 0
     return c
 
 
@@ -270,11 +270,11 @@ class DeviceArchive:
         self.levels = int(lib().lz_device_levels(h))
         self.device_bytes = nb.value
 
-    def decode(self, out=None, G=64, unroll=2, schedule=1, stream=None, check=True, unit_batch=0):
+    def decode(self, out=None, G=64, unroll=2, schedule=1, stream=None, check=True):
         import torch
         if out is None:
             out = torch.empty(max(self.n, 1), dtype=torch.uint8, device=self.buf.device)
-        c = _cfg(G, unroll, schedule, unit_batch)
+        c = _cfg(G, unroll, schedule)
         rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                     _stream(stream))
         if rc:
@@ -283,8 +283,8 @@ class DeviceArchive:
             self.check(stream)
         return out[:self.n]
 
-    def decode_async(self, out, G=64, unroll=2, schedule=1, stream=None, unit_batch=0):
-        c = _cfg(G, unroll, schedule, unit_batch)
+    def decode_async(self, out, G=64, unroll=2, schedule=1, stream=None):
+        c = _cfg(G, unroll, schedule)
         rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                     _stream(stream))
         if rc:

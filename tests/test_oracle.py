@@ -2,7 +2,7 @@
 published hash vectors, hand-worked parses, an independent brute-force
 (dynamic-programming) formulation of the greedy parse on tiny inputs,
 container bytes laid out by hand, closed-form entropies, and a schedule
-simulation for the dependency levels."""
+simulation for the dependency depths."""
 import os
 import struct
 
@@ -255,64 +255,85 @@ def test_split_matches_unsplit_execution():
     assert bytes(ref[:len(out)]) == bytes(out)
 
 
-# -------------------------------------------------------------- levels pins
+# -------------------------------------------------------------- depth pins
 
-def simulate_levels_ok(arc, lv):
-    """Replays the schedule: in pass p every block runs its level-p matches in
-    order (literals in pass 0).  A match may read a byte of another block only
-    if that byte was final before the pass began, and a byte of its own block
-    only if it was written earlier in the same or an earlier pass.  Also
-    checks each level is the smallest that works."""
+def replay_by_depth(arc, lv):
+    """Runs the decode the way the GPU schedule does: all literals first, then
+    pass p = 1, 2, ... executes every depth-p match at once against a snapshot
+    taken before the pass (only a match's own earlier bytes, its period, come
+    from the pass itself).  Every byte a match reads from the snapshot must
+    already be written, and each depth must be the smallest that allows this.
+    Returns the output, which must equal the sequential decode."""
     T = oracle.tokens(arc)
     n = oracle.info(arc)["n"]
-    bs = 1 << oracle.info(arc)["log2_bs"]
-    wlev = np.full(n, -1, dtype=np.int64)
+    out = np.zeros(n, dtype=np.uint8)
+    wdep = np.full(n, -1, dtype=np.int64)  # pass that wrote each byte
+    lit = np.frombuffer(oracle.decode(arc).tobytes(), dtype=np.uint8)  # only to fetch literal bytes
     for t in range(T["dst"].size):
         d, L = int(T["dst"][t]), int(T["lit_len"][t])
-        wlev[d:d + L] = 0
-        m0, M, s = d + L, int(T["mlen"][t]), int(T["src"][t])
-        if M == 0:
-            continue
-        p = int(lv[t])
-        need = 0
-        for q in range(s, min(s + M, m0)):
-            assert wlev[q] >= 0
-            if q // bs != T["blk"][t]:
-                need = max(need, wlev[q] + 1)
-                assert wlev[q] < p
-            else:
-                need = max(need, wlev[q])
-                assert wlev[q] <= p
-        assert p == need
-        wlev[m0:m0 + M] = p
-    return True
+        out[d:d + L] = lit[d:d + L]
+        wdep[d:d + L] = 0
+    mx = int(lv.max()) if lv.size else 0
+    for p in range(1, mx + 1):
+        snap, wsnap = out.copy(), wdep.copy()
+        for t in np.nonzero(lv == p)[0]:
+            m0 = int(T["dst"][t] + T["lit_len"][t])
+            M, s = int(T["mlen"][t]), int(T["src"][t])
+            assert M > 0
+            deepest = 0
+            for i in range(M):
+                q = s + i
+                if q < m0:
+                    assert 0 <= wsnap[q] < p, (t, q)
+                    deepest = max(deepest, int(wsnap[q]))
+                    out[m0 + i] = snap[q]
+                else:
+                    out[m0 + i] = out[q]  # own period, written earlier in this match
+            assert p == deepest + 1, (t, p, deepest)
+            wdep[m0:m0 + M] = p
+    assert np.all(lv[T["mlen"] == 0] == 0)
+    return out
 
 
-def test_levels_schedule_simulation():
+def test_depth_replay_equals_decode():
     x = synth.zipf_text(6000, seed=4)
     for lb in (9, 10, 12):
         ll, ml, sr, lit = oracle.encode(x, lb, (4, 6, 8, 10), (256, 1024, 4096))
         arc = oracle.write_archive(x.size, lb, ll, ml, sr, lit)
         lv, mx = oracle.levels(arc)
-        assert mx == lv.max()
-        assert simulate_levels_ok(arc, lv)
-    # generated stream: sources always >= 4 KiB back, so with 4 KiB blocks
-    # every match crosses blocks and levels grow by one per hop
-    n = 100_000
-    ll, ml, sr, lit = synth.geo_tokens(n, 32, seed=9, lit_prefix=4096, min_back=4096)
+        assert mx == lv.max() and mx >= 2
+        assert np.array_equal(replay_by_depth(arc, lv), x)
+    # generated stream with overlapping matches (sources from 1 byte back)
+    n = 60_000
+    ll, ml, sr, lit = synth.geo_tokens(n, 32, seed=9, lit_prefix=512, min_back=1)
     arc = oracle.write_archive(n, 12, ll, ml, sr, lit)
     lv, mx = oracle.levels(arc)
-    assert simulate_levels_ok(arc, lv)
-    assert mx >= 2
+    assert np.array_equal(replay_by_depth(arc, lv), oracle.exec_tokens(n, ll, ml, sr, lit))
 
 
-def test_levels_single_block_is_flat():
-    """Within one block nothing crosses blocks, so every level is 0."""
-    x = synth.zipf_text(4000, seed=8)
-    ll, ml, sr, lit = oracle.encode(x, 12, (4, 4, 4, 4))
-    arc = oracle.write_archive(x.size, 12, ll, ml, sr, lit)
-    lv, mx = oracle.levels(arc)
-    assert mx == 0
+def test_depth_hand_built():
+    """Literals 'abcd'; A copies [0,4) -> depth 1; B copies A's bytes -> 2;
+    C copies literals again -> 1; D reads B and C -> 3; E overlaps itself
+    (period 1) over a literal -> 1.  Block boundaries do not add depth."""
+    lit = np.frombuffer(b"abcdz", np.uint8)
+    # tokens (lit_len, mlen, src): dst advances by lit_len + mlen
+    ll = [4, 0, 0, 0, 1]
+    ml = [4, 4, 4, 8, 6]
+    sr = [0, 4, 0, 8, 24]  # E: literal 'z' at 24, copies from 24 (period 1)
+    for lb in (4, 5, 12):  # 16-byte, 32-byte and single blocks
+        n = sum(ll) + sum(ml)
+        arc = oracle.write_archive(n, lb, ll, ml, sr, lit, min_match=1)
+        T = oracle.tokens(arc)
+        lv, mx = oracle.levels(arc)
+        out = oracle.decode(arc)
+        assert bytes(out) == b"abcd" + b"abcd" * 3 + b"abcdabcd" + b"z" * 7
+        # depth of the match covering each output position of A..E
+        m0 = T["dst"] + T["lit_len"]
+        want = {4: 1, 8: 2, 12: 1, 16: 3, 25: 1}
+        for pos, dep in want.items():
+            k = np.nonzero((m0 <= pos) & (pos < m0 + T["mlen"]))[0]
+            assert k.size == 1 and lv[k[0]] == dep, (lb, pos, lv)
+        assert mx == 3
 
 
 # ------------------------------------------------------------- entropy pins
