@@ -129,6 +129,15 @@ struct Desc {
   uint32_t a_len, b_len, base, ca;
 };
 
+// U chunks of one lane: loaded window, destination chunk, byte range
+template <int U>
+struct ChunkSet {
+  u32x4 v[U];
+  uintptr_t cdst[U], win[U];
+  int lo[U], hi[U];
+  bool fast[U], from_out[U];
+};
+
 template <int G>
 __device__ __forceinline__ uint64_t gscan64(uint64_t v, int gl, uint64_t& total) {
   uint64_t x = v;
@@ -137,7 +146,12 @@ __device__ __forceinline__ uint64_t gscan64(uint64_t v, int gl, uint64_t& total)
     uint64_t y = __shfl_up(x, d, G);
     if (gl >= d) x += y;
   }
-  total = __shfl(x, G - 1, G);
+  if constexpr (G == 64) {
+    total = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(x >> 32), 63) << 32) |
+            __builtin_amdgcn_readlane((uint32_t)x, 63);
+  } else {
+    total = __shfl(x, G - 1, G);
+  }
   return x - v;
 }
 
@@ -149,7 +163,8 @@ __device__ __forceinline__ uint32_t gscan32(uint32_t v, int gl, uint32_t& total)
     uint32_t y = __shfl_up(x, d, G);
     if (gl >= d) x += y;
   }
-  total = __shfl(x, G - 1, G);
+  if constexpr (G == 64) total = __builtin_amdgcn_readlane(x, 63);
+  else total = __shfl(x, G - 1, G);
   return x - v;
 }
 
@@ -158,6 +173,25 @@ template <int G>
 __device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int gw) {
   if constexpr (G == 64) return ballot;
   else return (ballot >> (gw * G)) & ((1ull << G) - 1);
+}
+
+// Group-uniform values.  With G = 64 a group is a whole wave, so these live in
+// scalar registers (and branches on them are scalar).
+template <int G>
+__device__ __forceinline__ uint64_t uni(uint64_t x) {
+  if constexpr (G == 64) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+  } else {
+    return x;
+  }
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t uni32(uint32_t x) {
+  if constexpr (G == 64) return __builtin_amdgcn_readfirstlane(x);
+  else return x;
 }
 
 __device__ __forceinline__ uint32_t nchunks(uintptr_t d, uint32_t len) {
@@ -281,10 +315,11 @@ __device__ __forceinline__ void compiler_barrier() { asm volatile("" ::: "memory
 
 __device__ __forceinline__ void mem_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
-template <int G, int U, int MODE>
+template <int G, int U, int MODE, bool BATCH>
 __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
   static_assert(G == 8 || G == 16 || G == 32 || G == 64, "G");
   constexpr bool kCoh = (MODE == kModeFlow);
+  constexpr bool kOnlyMatch = (MODE == kModeFlow || MODE == kModeLevels);
   __shared__ Desc s_desc[kWG];
   __shared__ uint32_t s_base[kWG];
 
@@ -293,7 +328,7 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
   const int gw = lane / G;             // group in wave
   const int gslot = threadIdx.x - gl;  // first LDS slot of this group
   const uint64_t ngroups = (uint64_t)gridDim.x * (kWG / G);
-  const uint64_t gid = (uint64_t)blockIdx.x * (kWG / G) + threadIdx.x / G;
+  const uint64_t gid = uni<G>((uint64_t)blockIdx.x * (kWG / G) + threadIdx.x / G);
   ArcDesc D = A.one;
   uint64_t bs = 1ull << D.log2_bs;
   uintptr_t out_b = (uintptr_t)D.out;
@@ -301,8 +336,8 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
   __amdgpu_buffer_rsrc_t out_r = __builtin_amdgcn_make_buffer_rsrc((void*)D.out, 0, (int)out_cap32, 0x00020000);
   // switches the group to archive `aid` of a batch
   auto use_arc = [&](uint32_t aid) {
-    if (!A.arcs) return;
-    D = A.arcs[aid];
+    if constexpr (!BATCH) return;
+    D = A.arcs[uni32<G>(aid)];
     bs = 1ull << D.log2_bs;
     out_b = (uintptr_t)D.out;
     out_cap32 = (uint32_t)min<uint64_t>(D.msrc_hi - D.msrc_lo, 0xFFFFFFFFull);
@@ -357,7 +392,7 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
           }
           uint32_t w = 0;
           if (gl == 0) w = atomicAdd(A.tickets + cur_lvl, 1u);
-          w = __shfl(w, 0, G);
+          w = (G == 64) ? __builtin_amdgcn_readfirstlane(w) : __shfl(w, 0, G);
           if (w < level_windows(cur_lvl)) {
             lvl = cur_lvl;
             if (A.items) set_window(A.lvl_start[lvl] + w, 0, 0);
@@ -432,7 +467,7 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
           // ---------------------------------------------- the level below must be complete
           uint32_t c = 0;
           if (gl == 0) c = __hip_atomic_load(A.wdone + (lvl - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          c = __shfl(c, 0, G);
+          c = (G == 64) ? __builtin_amdgcn_readfirstlane(c) : __shfl(c, 0, G);
           if (c >= level_windows(lvl - 1)) {
             started = true;
             ready = lvl;
@@ -557,7 +592,9 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
         s_desc[threadIdx.x] = d;
         s_base[threadIdx.x] = base;
         compiler_barrier();
-        for (uint32_t r = 0; r < C; r += G * U) {
+        // Chunks are taken G * U at a time: all U loads of a lane are in
+        // flight before its first store.
+        auto prep = [&](uint32_t r, ChunkSet<U>& cs) {
           // owner of chunk k: the last lane whose first chunk is <= k
           uint32_t own[U];
 #pragma unroll
@@ -568,16 +605,13 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
             for (int i = 0; i < U; ++i)
               if (s_base[gslot + own[i] + step] <= r + i * G + gl) own[i] += step;
           }
-          u32x4 v[U];
-          uintptr_t cdst[U], win[U];
-          int lo[U], hi[U];
-          bool fast[U], from_out[U];
 #pragma unroll
           for (int i = 0; i < U; ++i) {
             const uint32_t k = r + i * G + gl;
             const Desc& e = s_desc[gslot + own[i]];
             const uint32_t q = k - e.base;
-            const bool m = q >= e.ca;
+            // match passes copy matches only, the parse literal runs only
+            const bool m = kOnlyMatch ? true : (MODE == kModeParse) ? false : (q >= e.ca);
             const uintptr_t Dd = m ? e.b_dst : e.a_dst;
             const uintptr_t S = m ? e.b_src : e.a_src;
             const uint32_t L = m ? e.b_len : e.a_len;
@@ -586,40 +620,46 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
             const intptr_t l0 = (intptr_t)Dd - (intptr_t)s0;
             const intptr_t h0 = (intptr_t)(Dd + L) - (intptr_t)s0;
             const bool valid = k < C;
-            lo[i] = l0 > 0 ? (int)l0 : 0;
-            hi[i] = valid ? (h0 < 16 ? (int)h0 : 16) : 0;
-            cdst[i] = s0;
-            win[i] = S + (s0 - Dd);
-            from_out[i] = m;
+            cs.lo[i] = l0 > 0 ? (int)l0 : 0;
+            cs.hi[i] = valid ? (h0 < 16 ? (int)h0 : 16) : 0;
+            cs.cdst[i] = s0;
+            cs.win[i] = S + (s0 - Dd);
+            cs.from_out[i] = m;
             const uintptr_t lb = m ? D.msrc_lo : D.lit_lo, hb = m ? D.msrc_hi : D.lit_hi;
-            fast[i] = valid && win[i] >= lb && win[i] + 16 <= hb;
+            cs.fast[i] = valid && cs.win[i] >= lb && cs.win[i] + 16 <= hb;
           }
-          // all loads in flight before the first store (a buffer load out of
-          // range returns zeros)
+          // every lane loads (a buffer load out of range returns zeros)
 #pragma unroll
           for (int i = 0; i < U; ++i) {
-            if (kCoh && from_out[i])
-              v[i] = __builtin_amdgcn_raw_buffer_load_b128(out_r, fast[i] ? (int)(uint32_t)(win[i] - out_b) : 0, 0,
-                                                           kSC1);
+            if (kCoh && cs.from_out[i])
+              cs.v[i] = __builtin_amdgcn_raw_buffer_load_b128(
+                  out_r, cs.fast[i] ? (int)(uint32_t)(cs.win[i] - out_b) : 0, 0, kSC1);
             else
-              v[i] = *gptr<const u32x4_a1>(fast[i] ? win[i] : (uintptr_t)g_pad16);
+              cs.v[i] = *gptr<const u32x4_a1>(cs.fast[i] ? cs.win[i] : (uintptr_t)g_pad16);
           }
+        };
+        auto commit = [&](ChunkSet<U>& cs) {
 #pragma unroll
           for (int i = 0; i < U; ++i)
-            if (!fast[i] && hi[i] > lo[i]) {
-              if (kCoh && from_out[i])
-                v[i] = coh_load_bytes(out_r, (uint32_t)(win[i] - out_b), lo[i], hi[i]);
+            if (!cs.fast[i] && cs.hi[i] > cs.lo[i]) {
+              if (kCoh && cs.from_out[i])
+                cs.v[i] = coh_load_bytes(out_r, (uint32_t)(cs.win[i] - out_b), cs.lo[i], cs.hi[i]);
               else
-                v[i] = load_bytes(win[i], lo[i], hi[i]);
+                cs.v[i] = load_bytes(cs.win[i], cs.lo[i], cs.hi[i]);
             }
 #pragma unroll
           for (int i = 0; i < U; ++i)
-            if (hi[i] > lo[i]) {
+            if (cs.hi[i] > cs.lo[i]) {
               if (kCoh)
-                coh_store_chunk(out_r, (uint32_t)(cdst[i] - out_b), v[i], lo[i], hi[i]);
+                coh_store_chunk(out_r, (uint32_t)(cs.cdst[i] - out_b), cs.v[i], cs.lo[i], cs.hi[i]);
               else
-                store_chunk(cdst[i], v[i], lo[i], hi[i]);
+                store_chunk(cs.cdst[i], cs.v[i], cs.lo[i], cs.hi[i]);
             }
+        };
+        for (uint32_t r = 0; r < C; r += G * U) {
+          ChunkSet<U> cs;
+          prep(r, cs);
+          commit(cs);
         }
         compiler_barrier();
         // ---------------------------------------------- retire segments
@@ -830,9 +870,9 @@ KArgs base_args(const lz_dev* h) {
 typedef void (*kfn_t)(KArgs);
 
 template <int MODE>
-kfn_t pick_kernel(uint32_t G, uint32_t U) {
+kfn_t pick_kernel(uint32_t G, uint32_t U, bool batch = false) {
 #define K(g, u) \
-  if (G == g && U == u) return k_lz<g, u, MODE>;
+  if (G == g && U == u) return batch ? k_lz<g, u, MODE, true> : k_lz<g, u, MODE, false>;
   K(8, 1) K(8, 2) K(8, 4) K(16, 1) K(16, 2) K(16, 4) K(32, 1) K(32, 2) K(32, 4) K(64, 1) K(64, 2) K(64, 4)
 #undef K
   return nullptr;
@@ -1544,15 +1584,15 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
     A.err = (uint32_t*)(D0 + o_err);
     A.n_levels = (uint32_t)nl;
     if (nseg) {
-      kfn_t kp = pick_kernel<kModeParse>(G, U);
+      kfn_t kp = pick_kernel<kModeParse>(G, U, true);
       seq.push_back({kp, grid_for(nseg, resident_groups(kp, cu, G), G), A});
     }
     if (nw) {
       if (sched == 0) {
-        kfn_t k = pick_kernel<kModeFlow>(G, U);
+        kfn_t k = pick_kernel<kModeFlow>(G, U, true);
         seq.push_back({k, grid_for(nw, resident_groups(k, cu, G), G), A});
       } else {
-        kfn_t k = pick_kernel<kModeLevels>(G, U);
+        kfn_t k = pick_kernel<kModeLevels>(G, U, true);
         const uint64_t res = resident_groups(k, cu, G);
         for (uint64_t p = 0; p < nl; ++p) {
           KArgs a = A;
