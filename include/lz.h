@@ -148,12 +148,15 @@ typedef struct lz_dev lz_dev; /* opaque handle of a device-resident archive */
  * {8,16,32,64}); unroll = 16-byte chunks per lane per step (1, 2, 4).
  * schedule 0 = every depth in one launch, a window starting once all windows
  * of the depth below have finished (per-depth counters); schedule 1 = one
- * launch per depth.  NULL config = G 64, unroll 2, schedule 1. */
+ * launch per depth, except that the deepest depths that each have at most
+ * `tail` windows of 64 matches run in a single one-workgroup launch with a
+ * barrier between depths (0 = 32 windows; 0xFFFFFFFF = no such launch).
+ * NULL config = G 64, unroll 2, schedule 1, tail 0. */
 typedef struct lz_decode_cfg {
   uint32_t G;
   uint32_t unroll;
   uint32_t schedule;
-  uint32_t wg_size; /* threads per workgroup: 0 or 256 */
+  uint32_t tail;
 } lz_decode_cfg;
 
 /* Device bytes lz_device_open needs for this archive: the archive itself, the

@@ -74,11 +74,15 @@ constexpr int kModeFlow = 0;    // every level in one launch, per-level completi
 constexpr int kModeLevels = 1;  // the windows of one level, no waits
 constexpr int kModePure = 2;    // pre-decoded tokens, sources in a reference buffer
 constexpr int kModeParse = 3;   // parse blocks, copy literals, fill the match table
+constexpr int kModeTail = 4;    // the last, small levels in one workgroup, a barrier between levels
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint64_t kSegTok = 256;  // tokens per parse segment
 
 constexpr uint64_t kIdleTicks = 500000000ull;  // 5 s of the 100 MHz clock without progress
 constexpr int kWG = 256;
+constexpr int kWGTail = 1024;           // one workgroup: 16 waves, a group (G = 64) per wave
+constexpr uint32_t kTailWindows = 32;   // default: levels of at most this many windows form the tail
+constexpr uint32_t kTailOff = 0xFFFFFFFFu;  // no tail launch
 
 // One archive and its output, as the kernels see it.
 struct ArcDesc {
@@ -133,9 +137,9 @@ struct Desc {
 template <int U>
 struct ChunkSet {
   u32x4 v[U];
-  uintptr_t cdst[U], win[U];
-  int lo[U], hi[U];
-  bool fast[U], from_out[U];
+  uintptr_t dst[U], win[U];
+  int len[U], sh[U];  // bytes stored (16, 1..15, or 0), first byte of them in v
+  bool slow[U], from_out[U];
 };
 
 template <int G>
@@ -194,13 +198,10 @@ __device__ __forceinline__ uint32_t uni32(uint32_t x) {
   else return x;
 }
 
-__device__ __forceinline__ uint32_t nchunks(uintptr_t d, uint32_t len) {
-  return len ? (uint32_t)(((d + len + 15) >> 4) - (d >> 4)) : 0u;
-}
-
-__device__ __forceinline__ uint32_t dword_at(const u32x4& v, int i) {  // i = dword index 0..3
-  return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
-}
+// 16-byte chunks of a segment: chunk q covers [16q, 16q + 16), the last one is
+// moved back to end at the segment's end (it rewrites bytes of the chunk before
+// it with the same values); a segment below 16 bytes is one short chunk.
+__device__ __forceinline__ uint32_t nchunks(uint32_t len) { return (len + 15u) >> 4; }
 
 // Read target of the lanes whose window is read byte by byte: every lane
 // issues its 16-byte load unconditionally, so the loads of a step stay in
@@ -215,47 +216,50 @@ __device__ __forceinline__ u32x4 load_bytes(uintptr_t w, int lo, int hi) {
   return u32x4{d[0], d[1], d[2], d[3]};
 }
 
-// Writes bytes [lo, hi) of a 16-byte aligned chunk at a with naturally aligned
-// stores only (no read-modify-write of bytes outside the range).
-__device__ __forceinline__ void store_chunk(uintptr_t a, const u32x4& v, int lo, int hi) {
-  if (lo == 0 && hi == 16) {
-    *gptr<u32x4>(a) = v;
+typedef unsigned long long u64_a1 __attribute__((aligned(1)));
+typedef unsigned int u32_a1 __attribute__((aligned(1)));
+typedef unsigned short u16_a1 __attribute__((aligned(1)));
+
+// 8 bytes of v starting at byte o (0..15); bytes past the 16th read as zero
+__device__ __forceinline__ uint64_t bytes_at(const u32x4& v, int o) {
+  const int dw = o >> 2, b = o & 3;
+  const uint32_t a0 = dw == 0 ? v.x : dw == 1 ? v.y : dw == 2 ? v.z : v.w;
+  const uint32_t a1 = dw == 0 ? v.y : dw == 1 ? v.z : dw == 2 ? v.w : 0u;
+  const uint32_t a2 = dw == 0 ? v.z : dw == 1 ? v.w : 0u;
+  const uint32_t lo = __builtin_amdgcn_alignbyte(a1, a0, b);
+  const uint32_t hi = __builtin_amdgcn_alignbyte(a2, a1, b);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// A segment of len < 16 bytes whose bytes are v[sh, sh + len): two stores of
+// the largest power-of-two width w <= len, at its start and ending at its end.
+template <typename ST8, typename ST4, typename ST2, typename ST1>
+__device__ __forceinline__ void store_short(const u32x4& v, int sh, int len, ST8 st8, ST4 st4, ST2 st2, ST1 st1) {
+  const int w = len >= 8 ? 8 : len >= 4 ? 4 : len >= 2 ? 2 : 1;
+  const uint64_t first = bytes_at(v, sh), last = bytes_at(v, sh + len - w);
+  if (w == 8) {
+    st8(0, first);
+    st8(len - 8, last);
+  } else if (w == 4) {
+    st4(0, (uint32_t)first);
+    st4(len - 4, (uint32_t)last);
+  } else if (w == 2) {
+    st2(0, (uint16_t)first);
+    st2(len - 2, (uint16_t)last);
+  } else {
+    st1(0, (uint8_t)first);
+  }
+}
+
+__device__ __forceinline__ void store_seg(uintptr_t a, const u32x4& v, int sh, int len) {
+  if (len == 16) {
+    *gptr<u32x4_a1>(a) = v;
     return;
   }
-  int i = lo;
-  if ((i & 1) && i < hi) {
-    *gptr<uint8_t>(a + i) = (uint8_t)(dword_at(v, i >> 2) >> (8 * (i & 3)));
-    i += 1;
-  }
-  if ((i & 2) && i + 2 <= hi) {
-    *gptr<uint16_t>(a + i) = (uint16_t)(dword_at(v, i >> 2) >> (8 * (i & 3)));
-    i += 2;
-  }
-  if ((i & 4) && i + 4 <= hi) {
-    *gptr<uint32_t>(a + i) = dword_at(v, i >> 2);
-    i += 4;
-  }
-  if ((i & 8) && i + 8 <= hi) {
-    uint64_t q = (uint64_t)dword_at(v, i >> 2) | ((uint64_t)dword_at(v, (i >> 2) + 1) << 32);
-    *gptr<uint64_t>(a + i) = q;
-    i += 8;
-  }
-  if (i + 8 <= hi) {
-    uint64_t q = (uint64_t)dword_at(v, i >> 2) | ((uint64_t)dword_at(v, (i >> 2) + 1) << 32);
-    *gptr<uint64_t>(a + i) = q;
-    i += 8;
-  }
-  if (i + 4 <= hi) {
-    *gptr<uint32_t>(a + i) = dword_at(v, i >> 2);
-    i += 4;
-  }
-  if (i + 2 <= hi) {
-    *gptr<uint16_t>(a + i) = (uint16_t)(dword_at(v, i >> 2) >> (8 * (i & 3)));
-    i += 2;
-  }
-  if (i + 1 <= hi) {
-    *gptr<uint8_t>(a + i) = (uint8_t)(dword_at(v, i >> 2) >> (8 * (i & 3)));
-  }
+  store_short(
+      v, sh, len, [&](int o, uint64_t x) { *gptr<u64_a1>(a + o) = x; },
+      [&](int o, uint32_t x) { *gptr<u32_a1>(a + o) = x; }, [&](int o, uint16_t x) { *gptr<u16_a1>(a + o) = x; },
+      [&](int o, uint8_t x) { *gptr<uint8_t>(a + o) = x; });
 }
 
 // ---- coherent output path (schedule 0) -------------------------------------
@@ -273,42 +277,19 @@ __device__ __forceinline__ u32x4 coh_load_bytes(__amdgpu_buffer_rsrc_t r, uint32
   return u32x4{d[0], d[1], d[2], d[3]};
 }
 
-__device__ __forceinline__ void coh_store_chunk(__amdgpu_buffer_rsrc_t r, uint32_t a, const u32x4& v, int lo, int hi) {
-  if (lo == 0 && hi == 16) {
+__device__ __forceinline__ void coh_store_seg(__amdgpu_buffer_rsrc_t r, uint32_t a, const u32x4& v, int sh, int len) {
+  if (len == 16) {
     __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)a, 0, kSC1);
     return;
   }
-  int i = lo;
-  if ((i & 1) && i < hi) {
-    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(dword_at(v, i >> 2) >> (8 * (i & 3))), r, (int)(a + i), 0, kSC1);
-    i += 1;
-  }
-  if ((i & 2) && i + 2 <= hi) {
-    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(dword_at(v, i >> 2) >> (8 * (i & 3))), r, (int)(a + i), 0, kSC1);
-    i += 2;
-  }
-  if ((i & 4) && i + 4 <= hi) {
-    __builtin_amdgcn_raw_buffer_store_b32(dword_at(v, i >> 2), r, (int)(a + i), 0, kSC1);
-    i += 4;
-  }
-  if ((i & 8) && i + 8 <= hi) {
-    __builtin_amdgcn_raw_buffer_store_b64(u32x2{dword_at(v, i >> 2), dword_at(v, (i >> 2) + 1)}, r, (int)(a + i), 0, kSC1);
-    i += 8;
-  }
-  if (i + 8 <= hi) {
-    __builtin_amdgcn_raw_buffer_store_b64(u32x2{dword_at(v, i >> 2), dword_at(v, (i >> 2) + 1)}, r, (int)(a + i), 0, kSC1);
-    i += 8;
-  }
-  if (i + 4 <= hi) {
-    __builtin_amdgcn_raw_buffer_store_b32(dword_at(v, i >> 2), r, (int)(a + i), 0, kSC1);
-    i += 4;
-  }
-  if (i + 2 <= hi) {
-    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(dword_at(v, i >> 2) >> (8 * (i & 3))), r, (int)(a + i), 0, kSC1);
-    i += 2;
-  }
-  if (i + 1 <= hi)
-    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(dword_at(v, i >> 2) >> (8 * (i & 3))), r, (int)(a + i), 0, kSC1);
+  store_short(
+      v, sh, len,
+      [&](int o, uint64_t x) {
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{(uint32_t)x, (uint32_t)(x >> 32)}, r, (int)(a + o), 0, kSC1);
+      },
+      [&](int o, uint32_t x) { __builtin_amdgcn_raw_buffer_store_b32(x, r, (int)(a + o), 0, kSC1); },
+      [&](int o, uint16_t x) { __builtin_amdgcn_raw_buffer_store_b16(x, r, (int)(a + o), 0, kSC1); },
+      [&](int o, uint8_t x) { __builtin_amdgcn_raw_buffer_store_b8(x, r, (int)(a + o), 0, kSC1); });
 }
 
 __device__ __forceinline__ void compiler_barrier() { asm volatile("" ::: "memory"); }
@@ -316,19 +297,26 @@ __device__ __forceinline__ void compiler_barrier() { asm volatile("" ::: "memory
 __device__ __forceinline__ void mem_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
 template <int G, int U, int MODE, bool BATCH>
-__global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
+__global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs A) {
   static_assert(G == 8 || G == 16 || G == 32 || G == 64, "G");
+  static_assert(MODE != kModeTail || G == 64, "a tail group is a whole wave (barriers are per wave)");
+  constexpr int WG = (MODE == kModeTail) ? kWGTail : kWG;
+  if (blockDim.x != (unsigned)WG) {  // the group layout assumes WG threads
+    if (threadIdx.x == 0) atomicOr(A.err, 2u);
+    return;
+  }
+  // schedule 0 reads and writes output bytes at device scope
   constexpr bool kCoh = (MODE == kModeFlow);
-  constexpr bool kOnlyMatch = (MODE == kModeFlow || MODE == kModeLevels);
-  __shared__ Desc s_desc[kWG];
-  __shared__ uint32_t s_base[kWG];
+  constexpr bool kOnlyMatch = (MODE == kModeFlow || MODE == kModeLevels || MODE == kModeTail);
+  __shared__ Desc s_desc[WG];
+  __shared__ uint32_t s_base[WG];
 
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);       // lane in group
   const int gw = lane / G;             // group in wave
   const int gslot = threadIdx.x - gl;  // first LDS slot of this group
-  const uint64_t ngroups = (uint64_t)gridDim.x * (kWG / G);
-  const uint64_t gid = uni<G>((uint64_t)blockIdx.x * (kWG / G) + threadIdx.x / G);
+  const uint64_t ngroups = (uint64_t)gridDim.x * (WG / G);
+  const uint64_t gid = uni<G>((uint64_t)blockIdx.x * (WG / G) + threadIdx.x / G);
   ArcDesc D = A.one;
   uint64_t bs = 1ull << D.log2_bs;
   uintptr_t out_b = (uintptr_t)D.out;
@@ -352,7 +340,7 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
   // work item state (replicated on the group's lanes)
   bool finished = false, have_item = false, started = true;
   uint64_t iter = 0;
-  uint32_t lvl = 0, cur_lvl = 0, ready = 0;  // schedule 0: levels <= ready may start
+  uint32_t lvl = 0, cur_lvl = (MODE == kModeTail) ? (uint32_t)A.lo : 0u, ready = 0;  // schedule 0: levels <= ready may start
   if (MODE == kModeParse) {
     for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < A.n_levels; i += (uint64_t)gridDim.x * kWG) {
       A.tickets[i] = 0u;
@@ -402,6 +390,30 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
             break;
           }
           ++cur_lvl;
+        }
+      } else if (MODE == kModeTail) {
+        // one workgroup shares each level's windows; a barrier closes the level
+        for (;;) {
+          if (cur_lvl >= A.hi) {
+            finished = true;
+            break;
+          }
+          const uint64_t k = gid + iter * ngroups;
+          if (k < level_windows(cur_lvl)) {
+            ++iter;
+            lvl = cur_lvl;
+            if (A.items) set_window(A.lvl_start[lvl] + k, 0, 0);
+            else set_window(k, A.lvl_start[lvl], A.lvl_start[lvl + 1]);
+            have_item = true;
+            break;
+          }
+          // every store of this wave has completed before the barrier (the
+          // barrier itself does not wait for them)
+          compiler_barrier();
+          __builtin_amdgcn_s_waitcnt(0);
+          __syncthreads();
+          ++cur_lvl;
+          iter = 0;
         }
       } else if (MODE == kModeLevels) {
         const uint64_t k = gid + iter * ngroups;
@@ -575,8 +587,8 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
         const bool inc_m = piece > 0;
         const uintptr_t a_dst = out_b + l_dst;
         const uintptr_t b_dst = out_b + m_dst + m_done;
-        const uint32_t ca = inc_l ? nchunks(a_dst, l_len) : 0u;
-        const uint32_t cb = inc_m ? nchunks(b_dst, piece) : 0u;
+        const uint32_t ca = inc_l ? nchunks(l_len) : 0u;
+        const uint32_t cb = inc_m ? nchunks(piece) : 0u;
         uint32_t C;
         const uint32_t base = gscan32<G>(ca + cb, gl, C);
         Desc d;
@@ -616,44 +628,59 @@ __global__ __launch_bounds__(kWG) void k_lz(KArgs A) {
             const uintptr_t S = m ? e.b_src : e.a_src;
             const uint32_t L = m ? e.b_len : e.a_len;
             const uint32_t qq = m ? q - e.ca : q;
-            const uintptr_t s0 = (Dd & ~(uintptr_t)15) + 16 * (uintptr_t)qq;
-            const intptr_t l0 = (intptr_t)Dd - (intptr_t)s0;
-            const intptr_t h0 = (intptr_t)(Dd + L) - (intptr_t)s0;
             const bool valid = k < C;
-            cs.lo[i] = l0 > 0 ? (int)l0 : 0;
-            cs.hi[i] = valid ? (h0 < 16 ? (int)h0 : 16) : 0;
-            cs.cdst[i] = s0;
-            cs.win[i] = S + (s0 - Dd);
-            cs.from_out[i] = m;
             const uintptr_t lb = m ? D.msrc_lo : D.lit_lo, hb = m ? D.msrc_hi : D.lit_hi;
-            cs.fast[i] = valid && cs.win[i] >= lb && cs.win[i] + 16 <= hb;
+            cs.from_out[i] = m;
+            cs.slow[i] = false;
+            cs.sh[i] = 0;
+            if (L >= 16) {
+              // full chunk (windows of a segment of 16 bytes or more stay inside it)
+              const uint32_t off = min(16u * qq, L - 16u);
+              cs.dst[i] = Dd + off;
+              cs.win[i] = S + off;
+              cs.len[i] = valid ? 16 : 0;
+            } else {
+              // short segment: the window starts at its source, or ends at its
+              // end near the top of the readable range
+              cs.dst[i] = Dd;
+              cs.len[i] = valid ? (int)L : 0;
+              if (S + 16 <= hb) {
+                cs.win[i] = S;
+              } else if (S + L >= lb + 16) {
+                cs.win[i] = S + L - 16;
+                cs.sh[i] = 16 - (int)L;
+              } else {
+                cs.win[i] = S;
+                cs.slow[i] = true;
+              }
+            }
           }
           // every lane loads (a buffer load out of range returns zeros)
 #pragma unroll
           for (int i = 0; i < U; ++i) {
             if (kCoh && cs.from_out[i])
               cs.v[i] = __builtin_amdgcn_raw_buffer_load_b128(
-                  out_r, cs.fast[i] ? (int)(uint32_t)(cs.win[i] - out_b) : 0, 0, kSC1);
+                  out_r, cs.slow[i] ? 0 : (int)(uint32_t)(cs.win[i] - out_b), 0, kSC1);
             else
-              cs.v[i] = *gptr<const u32x4_a1>(cs.fast[i] ? cs.win[i] : (uintptr_t)g_pad16);
+              cs.v[i] = *gptr<const u32x4_a1>(cs.slow[i] ? (uintptr_t)g_pad16 : cs.win[i]);
           }
         };
         auto commit = [&](ChunkSet<U>& cs) {
 #pragma unroll
           for (int i = 0; i < U; ++i)
-            if (!cs.fast[i] && cs.hi[i] > cs.lo[i]) {
+            if (cs.slow[i] && cs.len[i] > 0) {
               if (kCoh && cs.from_out[i])
-                cs.v[i] = coh_load_bytes(out_r, (uint32_t)(cs.win[i] - out_b), cs.lo[i], cs.hi[i]);
+                cs.v[i] = coh_load_bytes(out_r, (uint32_t)(cs.win[i] - out_b), 0, cs.len[i]);
               else
-                cs.v[i] = load_bytes(cs.win[i], cs.lo[i], cs.hi[i]);
+                cs.v[i] = load_bytes(cs.win[i], 0, cs.len[i]);
             }
 #pragma unroll
           for (int i = 0; i < U; ++i)
-            if (cs.hi[i] > cs.lo[i]) {
+            if (cs.len[i] > 0) {
               if (kCoh)
-                coh_store_chunk(out_r, (uint32_t)(cs.cdst[i] - out_b), cs.v[i], cs.lo[i], cs.hi[i]);
+                coh_store_seg(out_r, (uint32_t)(cs.dst[i] - out_b), cs.v[i], cs.sh[i], cs.len[i]);
               else
-                store_chunk(cs.cdst[i], cs.v[i], cs.lo[i], cs.hi[i]);
+                store_seg(cs.dst[i], cs.v[i], cs.sh[i], cs.len[i]);
             }
         };
         for (uint32_t r = 0; r < C; r += G * U) {
@@ -713,9 +740,9 @@ struct lz_dev {
   struct GraphKey {
     uint8_t* out;
     uint64_t cap;
-    uint32_t G, U, sched;
+    uint32_t G, U, sched, tail;
     bool operator==(const GraphKey& o) const {
-      return out == o.out && cap == o.cap && G == o.G && U == o.U && sched == o.sched;
+      return out == o.out && cap == o.cap && G == o.G && U == o.U && sched == o.sched && tail == o.tail;
     }
   };
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
@@ -878,11 +905,25 @@ kfn_t pick_kernel(uint32_t G, uint32_t U, bool batch = false) {
   return nullptr;
 }
 
-int resolve_cfg(const lz_decode_cfg* cfg, uint32_t& G, uint32_t& U, uint32_t& sched) {
+kfn_t pick_tail(uint32_t U, bool batch) {
+  if (U == 1) return batch ? k_lz<64, 1, kModeTail, true> : k_lz<64, 1, kModeTail, false>;
+  if (U == 2) return batch ? k_lz<64, 2, kModeTail, true> : k_lz<64, 2, kModeTail, false>;
+  return batch ? k_lz<64, 4, kModeTail, true> : k_lz<64, 4, kModeTail, false>;
+}
+
+// First level of the tail: every level from there on has at most `limit`
+// windows (returns n_levels when the tail would hold fewer than two levels).
+uint64_t tail_start(const std::vector<uint64_t>& windows, uint32_t limit) {
+  uint64_t p = windows.size();
+  while (p > 0 && windows[p - 1] <= limit) --p;
+  return (windows.size() - p >= 2) ? p : windows.size();
+}
+
+int resolve_cfg(const lz_decode_cfg* cfg, uint32_t& G, uint32_t& U, uint32_t& sched, uint32_t* tail = nullptr) {
   G = cfg ? cfg->G : 64;
   U = cfg ? cfg->unroll : 2;
   sched = cfg ? cfg->schedule : 1;
-  if (cfg && cfg->wg_size && cfg->wg_size != 256) return lz::fail(LZ_E_INVAL, "wg_size must be 0 or 256");
+  if (tail) *tail = (cfg && cfg->tail) ? cfg->tail : kTailWindows;
   if (!(G == 8 || G == 16 || G == 32 || G == 64)) return lz::fail(LZ_E_INVAL, "G must be 8, 16, 32 or 64");
   if (!(U == 1 || U == 2 || U == 4)) return lz::fail(LZ_E_INVAL, "unroll must be 1, 2 or 4");
   if (sched > 1) return lz::fail(LZ_E_INVAL, "schedule must be 0 or 1");
@@ -1012,14 +1053,14 @@ int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decod
   if (out_cap < h->v.n) return lz::fail(LZ_E_INVAL, "output capacity %llu < n %llu", (unsigned long long)out_cap,
                                         (unsigned long long)h->v.n);
   if (h->v.n && !d_out) return lz::fail(LZ_E_INVAL, "null output");
-  uint32_t G, U, sched;
-  int rc = resolve_cfg(cfg, G, U, sched);
+  uint32_t G, U, sched, tail;
+  int rc = resolve_cfg(cfg, G, U, sched, &tail);
   if (rc) return rc;
   if (sched == 0 && out_cap > 0xFFFFFFFFull)
     return lz::fail(LZ_E_INVAL, "schedule 0 addresses outputs below 4 GiB; use schedule 1");
   if (h->v.nb == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
-  lz_dev::GraphKey key{d_out, out_cap, G, U, sched};
+  lz_dev::GraphKey key{d_out, out_cap, G, U, sched, tail};
   for (auto& g : h->graphs)
     if (g.first == key) {
       HIPCHK(hipGraphLaunch(g.second, s));
@@ -1032,6 +1073,7 @@ int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decod
     kfn_t k;
     uint64_t grid;
     KArgs a;
+    unsigned block = kWG;
   };
   std::vector<Launch> seq;
   kfn_t kp = pick_kernel<kModeParse>(G, U);
@@ -1046,12 +1088,22 @@ int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decod
     } else {
       kfn_t k = pick_kernel<kModeLevels>(G, U);
       const uint64_t res = resident_groups(k, h->cu_count, G);
-      for (size_t p = 0; p + 1 < h->lvl_start.size(); ++p) {
+      const uint64_t NL = h->lvl_start.size() - 1;
+      std::vector<uint64_t> win(NL);
+      for (uint64_t p = 0; p < NL; ++p) win[p] = (h->lvl_start[p + 1] - h->lvl_start[p] + 63) / 64;
+      const uint64_t pt = (tail == kTailOff || out_cap > 0xFFFFFFFFull) ? NL : tail_start(win, tail);
+      for (uint64_t p = 0; p < pt; ++p) {
         KArgs a = A;
         a.lo = h->lvl_start[p];
         a.hi = h->lvl_start[p + 1];
         if (a.hi == a.lo) continue;
         seq.push_back({k, grid_for((a.hi - a.lo + G - 1) / G, res, G), a});
+      }
+      if (pt < NL) {  // the deepest levels: one workgroup, windows of 64 matches
+        KArgs a = A;
+        a.lo = pt;
+        a.hi = NL;
+        seq.push_back({pick_tail(U, false), 1, a, (unsigned)kWGTail});
       }
     }
   }
@@ -1064,7 +1116,7 @@ int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decod
     void* args[] = {&L.a};
     kp2.func = (void*)L.k;
     kp2.gridDim = dim3((unsigned)L.grid);
-    kp2.blockDim = dim3(kWG);
+    kp2.blockDim = dim3(L.block);
     kp2.sharedMemBytes = 0;
     kp2.kernelParams = args;
     kp2.extra = nullptr;
@@ -1473,7 +1525,9 @@ std::vector<BatchGroup> make_groups(uint32_t count, const lz_decode_cfg* cfgs) {
     if (!c.unroll) c.unroll = 2;
     size_t k = 0;
     for (; k < groups.size(); ++k)
-      if (groups[k].cfg.G == c.G && groups[k].cfg.unroll == c.unroll && groups[k].cfg.schedule == c.schedule) break;
+      if (groups[k].cfg.G == c.G && groups[k].cfg.unroll == c.unroll && groups[k].cfg.schedule == c.schedule &&
+          groups[k].cfg.tail == c.tail)
+        break;
     if (k == groups.size()) groups.push_back(BatchGroup{c, {}});
     groups[k].arcs.push_back(i);
   }
@@ -1527,14 +1581,15 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
     kfn_t k;
     uint64_t grid;
     KArgs a;
+    unsigned block = kWG;
   };
   std::vector<Launch> seq;
   uint64_t off = 0;
   int cu = 0;
   for (lz_dev* h : H) cu = std::max(cu, h->cu_count);
   for (auto& g : groups) {
-    uint32_t G, U, sched;
-    (void)resolve_cfg(&g.cfg, G, U, sched);
+    uint32_t G, U, sched, tail;
+    (void)resolve_cfg(&g.cfg, G, U, sched, &tail);
     uint64_t nseg, nw, nl;
     group_scratch(H, g, &nseg, &nw, &nl);
     const uint64_t o_desc = off;
@@ -1594,12 +1649,23 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
       } else {
         kfn_t k = pick_kernel<kModeLevels>(G, U, true);
         const uint64_t res = resident_groups(k, cu, G);
-        for (uint64_t p = 0; p < nl; ++p) {
+        std::vector<uint64_t> win(nl);
+        for (uint64_t p = 0; p < nl; ++p) win[p] = lvls[p + 1] - lvls[p];
+        bool small = true;  // the tail addresses outputs below 4 GiB
+        for (uint32_t i : g.arcs) small = small && out_cap[i] <= 0xFFFFFFFFull;
+        const uint64_t pt = (tail == kTailOff || !small) ? nl : tail_start(win, tail);
+        for (uint64_t p = 0; p < pt; ++p) {
           KArgs a = A;
           a.lo = lvls[p];
           a.hi = lvls[p + 1];
           if (a.hi == a.lo) continue;
           seq.push_back({k, grid_for(a.hi - a.lo, res, G), a});
+        }
+        if (pt < nl) {  // the deepest levels: one workgroup over their windows
+          KArgs a = A;
+          a.lo = pt;
+          a.hi = nl;
+          seq.push_back({pick_tail(U, true), 1, a, (unsigned)kWGTail});
         }
       }
     }
@@ -1621,7 +1687,7 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
     void* args[] = {&L.a};
     kp2.func = (void*)L.k;
     kp2.gridDim = dim3((unsigned)L.grid);
-    kp2.blockDim = dim3(kWG);
+    kp2.blockDim = dim3(L.block);
     kp2.kernelParams = args;
     hipGraphNode_t node;
     hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp2);

@@ -47,7 +47,7 @@ class Info(ctypes.Structure):
 
 
 class DecodeCfg(ctypes.Structure):
-    _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("wg_size", _u32)]
+    _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("tail", _u32)]
 
 
 class TuneReport(ctypes.Structure):
@@ -237,9 +237,12 @@ def fnv1a64(data, seed=0xcbf29ce484222325):
     return int(lib().lz_fnv1a64(a.ctypes.data, a.size, seed))
 
 
-def _cfg(G=64, unroll=2, schedule=1):
+TAIL_OFF = 0xFFFFFFFF
+
+
+def _cfg(G=64, unroll=2, schedule=1, tail=0):
     c = DecodeCfg()
-    c.G, c.unroll, c.schedule, c.wg_size = G, unroll, schedule, 0
+    c.G, c.unroll, c.schedule, c.tail = G, unroll, schedule, tail
     return c
 
 
@@ -270,11 +273,11 @@ class DeviceArchive:
         self.levels = int(lib().lz_device_levels(h))
         self.device_bytes = nb.value
 
-    def decode(self, out=None, G=64, unroll=2, schedule=1, stream=None, check=True):
+    def decode(self, out=None, G=64, unroll=2, schedule=1, stream=None, check=True, tail=0):
         import torch
         if out is None:
             out = torch.empty(max(self.n, 1), dtype=torch.uint8, device=self.buf.device)
-        c = _cfg(G, unroll, schedule)
+        c = _cfg(G, unroll, schedule, tail)
         rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                     _stream(stream))
         if rc:
@@ -283,8 +286,8 @@ class DeviceArchive:
             self.check(stream)
         return out[:self.n]
 
-    def decode_async(self, out, G=64, unroll=2, schedule=1, stream=None):
-        c = _cfg(G, unroll, schedule)
+    def decode_async(self, out, G=64, unroll=2, schedule=1, stream=None, tail=0):
+        c = _cfg(G, unroll, schedule, tail)
         rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                     _stream(stream))
         if rc:
