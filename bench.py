@@ -66,12 +66,106 @@ def time_decode(torch, da, out, G, U, sched, warmup, steps):
     return float(np.mean(ms)), float(np.median(ms)), wall
 
 
-def cpu_oracle_time(arc, n):
+def time_stages(torch, da, out, G, U, sched, steps):
+    """Parse launch and match passes timed apart (HIP events on the stream that
+    launches them, i.e. torch's current stream)."""
+    st = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for a, b, c in ev:
+        a.record(st)
+        da.decode_stage(out, 1, G=G, unroll=U, schedule=sched)
+        b.record(st)
+        da.decode_stage(out, 2, G=G, unroll=U, schedule=sched)
+        c.record(st)
+    torch.cuda.synchronize()
+    da.check()
+    parse = float(np.mean([a.elapsed_time(b) for a, b, c in ev]))
+    match = float(np.mean([b.elapsed_time(c) for a, b, c in ev]))
+    return parse, match
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("lz_device.hip", "lz_internal.h"):
+        with open(os.path.join(ROOT, "paper_2607_18541_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_fastq1g.json")
+
+
+def measured_traffic(kernels):
+    """HBM bytes per decode moved by `kernels` (all their launches), from the
+    committed counter summary, if that was taken from the current kernel
+    source (else None)."""
+    if not os.path.exists(TRAFFIC_JSON):
+        return None
+    with open(TRAFFIC_JSON) as fh:
+        t = json.load(fh)
+    if t.get("source_sha256") != source_digest():
+        return None
+    got = [t.get("kernels", {}).get(k) for k in kernels]
+    if got[0] is None:
+        return None
+    return int(sum(k["traffic_bytes_per_decode"] for k in got if k))
+
+
+def traffic_from_counters(fetch_csv, write_csv, steps, n, command):
+    """Writes the traffic summary from two rocprofv3 --pmc runs of
+    `bench.py --profile-run` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).
+    Each counter is scaled by what it reads for the calibration kernel of the
+    same run, which reads n bytes and writes n bytes."""
+    import csv
+    import re
+
+    def per_kernel(path):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"]
+            m = re.search(r"k_lz<(\d+), (\d+), (\d+), (true|false)>", name)
+            key = "k_lz<%s, %s, %s, %s>" % m.groups() if m else ("calibration" if "bitwise_not" in name else None)
+            if key is None:
+                continue
+            a = acc.setdefault(key, [0, 0.0])
+            a[0] += 1
+            a[1] += float(r["Counter_Value"]) * 1024.0
+        return acc
+    fetch, write = per_kernel(fetch_csv), per_kernel(write_csv)
+    fs = n / fetch["calibration"][1]
+    ws = n / write["calibration"][1]
+    kernels = {}
+    for k in fetch:
+        if k == "calibration" or k not in write:
+            continue
+        kernels[k] = {"launches_per_decode": fetch[k][0] / steps,
+                      "fetch_bytes_per_decode": round(fetch[k][1] * fs / steps),
+                      "write_bytes_per_decode": round(write[k][1] * ws / steps),
+                      "traffic_bytes_per_decode": round((fetch[k][1] * fs + write[k][1] * ws) / steps)}
+    out = {"source_sha256": source_digest(), "workload": "FASTQ-like 1 GiB, 12/16/24/32", "steps": steps,
+           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4), "command": command, "kernels": kernels}
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
+def cpu_oracle_time(arc, n, min_s=10.0):
+    """The oracle's sequential decode of the whole archive, repeated until at
+    least min_s seconds of CPU time (single thread)."""
     import oracle
-    t0 = time.perf_counter()
-    out = oracle.decode(arc)
-    dt = time.perf_counter() - t0
-    return dt, out
+    reps, total = 0, 0.0
+    out = None
+    while total < min_s:
+        t0 = time.perf_counter()
+        out = oracle.decode(arc)
+        total += time.perf_counter() - t0
+        reps += 1
+    return total / reps, reps, out
+
+
+def achieved_all(t):
+    return t["alg_bytes"] / (t["mean_ms"] * 1e-3) / 1e9
 
 
 def run_fastq(args, torch, lz):
@@ -105,18 +199,35 @@ def run_fastq(args, torch, lz):
             raise SystemExit(f"{name}: GPU decode differs from the input")
         alg, tok_bytes = algorithmic_bytes(arc, info)
         log("decoded %s: %.3f ms per decode, %.2f GB/s, bit-exact" % (name, mean_ms, n / mean_ms / 1e6))
+        parse_ms, match_ms = time_stages(torch, da, out, args.G, args.unroll, args.schedule, args.steps)
+        if not bool(torch.equal(out, torch.from_numpy(x).to(dev))):
+            raise SystemExit(f"{name}: staged GPU decode differs from the input")
+        log("stages %s: parse %.3f ms, match passes %.3f ms" % (name, parse_ms, match_ms))
         res[name] = {
             "arc": arc, "info": info, "mean_ms": mean_ms, "median_ms": med_ms, "wall_s": wall,
             "gbps": n / (mean_ms * 1e-3) / 1e9, "alg_bytes": alg, "tok_bytes": tok_bytes,
             "ratio_raw": n / arc.size, "ratio_entropy": n / ent, "enc_s": enc_s, "open_s": open_s,
-            "levels": da.levels,
+            "levels": da.levels, "parse_ms": parse_ms, "match_ms": match_ms,
         }
         da.close()
         del out
         torch.cuda.empty_cache()
     t = res["tuned"]
     b = res["base"]
-    achieved = t["alg_bytes"] / (t["mean_ms"] * 1e-3) / 1e9
+    # the two kernels of a decode and their algorithmic bytes: the parse launch
+    # reads the token streams and literals and writes the literals; the match
+    # passes read and write every match byte once
+    ti = t["info"]
+    parse_alg = t["tok_bytes"] + 2 * (ti["n"] - ti["match_bytes"])
+    match_alg = 2 * ti["match_bytes"]
+    G, U = args.G, args.unroll
+    kparse = ["k_lz<%d, %d, 3, false>" % (G, U)]
+    kmatch = ["k_lz<%d, %d, 1, false>" % (G, U), "k_lz<64, %d, 4, false>" % U]
+    if t["parse_ms"] >= t["match_ms"]:
+        dom, dom_alg, dom_ms = kparse, parse_alg, t["parse_ms"]
+    else:
+        dom, dom_alg, dom_ms = kmatch, match_alg, t["match_ms"]
+    achieved = dom_alg / (dom_ms * 1e-3) / 1e9
     line = {
         "metric": "match-phase decode GB/s (device-resident) + ratio, 6/8/10/12 vs 12/16/24/32",
         "value": round(t["gbps"], 3),
@@ -148,18 +259,50 @@ def run_fastq(args, torch, lz):
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "alg_bytes_per_launch": t["alg_bytes"],
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
+            "kernel": " + ".join(dom), "alg_bytes_per_decode": dom_alg, "ms_per_decode": round(dom_ms, 4),
+        },
+        "stages": {
+            "parse": {"kernel": kparse[0], "ms": round(t["parse_ms"], 4), "alg_bytes": parse_alg,
+                      "alg_gbps": round(parse_alg / t["parse_ms"] / 1e6, 2)},
+            "match": {"kernel": " + ".join(kmatch), "ms": round(t["match_ms"], 4), "alg_bytes": match_alg,
+                      "alg_gbps": round(match_alg / t["match_ms"] / 1e6, 2), "depths": t["levels"]},
+            "whole_decode_alg_gbps": round(achieved_all(t), 2),
         },
     }
     if not args.no_cpu:
         log("timing the CPU oracle decode")
-        dt, out = cpu_oracle_time(t["arc"], n)
+        dt, reps, out = cpu_oracle_time(t["arc"], n)
         assert np.array_equal(out, x)
         line["cpu_baseline"] = {"value": round(n / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-                                "sample": "whole tuned archive (%d output bytes), one sequential decode incl. "
-                                          "validation" % n}
+                                "sample": "whole 12/16/24/32 archive (%d output bytes), sequential decode incl. "
+                                          "validation, mean of %d runs" % (n, reps)}
     return line
+
+
+def run_profile(args, torch, lz):
+    """For counter collection: the 12/16/24/32 archive decoded `steps` times,
+    then one plain elementwise kernel over the n output bytes (reads n bytes,
+    writes n bytes) that calibrates the memory counters."""
+    import synth
+    dev = torch.device("cuda:0")
+    x = synth.fastq(args.size, seed=3)
+    n = int(x.size)
+    log("encoding")
+    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain)
+    da = lz.DeviceArchive(arc, device=dev)
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    for i in range(args.steps):
+        da.decode_async(out, G=args.G, unroll=args.unroll, schedule=args.schedule)
+        log("decode %d launched" % i)
+    torch.cuda.synchronize()
+    da.check()
+    if not bool(torch.equal(out, torch.from_numpy(x).to(dev))):
+        raise SystemExit("GPU decode differs from the input")
+    y = torch.empty_like(out)
+    torch.bitwise_not(out, out=y)
+    torch.cuda.synchronize()
+    return {"profile_run": True, "n": n, "steps": args.steps, "calibration": "bitwise_not over n bytes"}
 
 
 def run_sweep(args, torch, lz):
@@ -204,7 +347,17 @@ def main():
     ap.add_argument("--schedule", type=int, default=1)
     ap.add_argument("--max-chain", dest="max_chain", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="decode the 12/16/24/32 archive `steps` times plus a calibration kernel (counter runs)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic summary from the counter CSVs of two --profile-run runs")
+    ap.add_argument("--command", default="", help="with --traffic-from: the profiling command, recorded")
     args = ap.parse_args()
+    if args.traffic_from:
+        n = len(__import__("synth").fastq(args.size, seed=3))
+        print(json.dumps(traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.steps, n,
+                                               args.command)))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; multi-GPU runs are not part of this build", file=sys.stderr)
         sys.exit(2)
@@ -214,7 +367,9 @@ def main():
         print("no GPU", file=sys.stderr)
         sys.exit(1)
     lz.lib()
-    if args.workload == "sweep":
+    if args.profile_run:
+        line = run_profile(args, torch, lz)
+    elif args.workload == "sweep":
         if args.size == 1 << 30:
             args.size = 1 << 28
         line = run_sweep(args, torch, lz)

@@ -173,6 +173,13 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
  * resident).  Asynchronous on `stream`.  out_cap < n gives LZ_E_INVAL. */
 int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cfg* cfg, void* stream);
 
+/* The two stages of lz_decode_device as separate launch sequences (to time or
+ * schedule them apart): stage 1 = the parse launch (literal runs written, the
+ * match table filled), stage 2 = the match passes, which must follow stage 1
+ * of the same handle and output on the same stream; stage 0 = both. */
+int lz_decode_device_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cfg* cfg, int stage,
+                           void* stream);
+
 /* Synchronises `stream` and reports a device-side failure of the last decode
  * on this handle (LZ_E_BUSY if a bounded wait expired), else 0. */
 int lz_device_check(lz_dev* h, void* stream);

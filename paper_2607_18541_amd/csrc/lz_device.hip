@@ -740,9 +740,10 @@ struct lz_dev {
   struct GraphKey {
     uint8_t* out;
     uint64_t cap;
-    uint32_t G, U, sched, tail;
+    uint32_t G, U, sched, tail, stage;
     bool operator==(const GraphKey& o) const {
-      return out == o.out && cap == o.cap && G == o.G && U == o.U && sched == o.sched && tail == o.tail;
+      return out == o.out && cap == o.cap && G == o.G && U == o.U && sched == o.sched && tail == o.tail &&
+             stage == o.stage;
     }
   };
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
@@ -1048,8 +1049,14 @@ uint64_t lz_device_n(const lz_dev* h) { return h ? h->v.n : 0; }
 uint32_t lz_device_levels(const lz_dev* h) { return h ? (uint32_t)(h->lvl_start.size() ? h->lvl_start.size() - 1 : 0) : 0; }
 void lz_device_close(lz_dev* h) { delete h; }
 
-int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cfg* cfg, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// stage 0: parse and match passes; 1: parse only; 2: match passes only
+int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cfg* cfg, int stage, void* stream) {
   if (!h) return lz::fail(LZ_E_INVAL, "null handle");
+  if (stage < 0 || stage > 2) return lz::fail(LZ_E_INVAL, "stage must be 0, 1 or 2");
   if (out_cap < h->v.n) return lz::fail(LZ_E_INVAL, "output capacity %llu < n %llu", (unsigned long long)out_cap,
                                         (unsigned long long)h->v.n);
   if (h->v.n && !d_out) return lz::fail(LZ_E_INVAL, "null output");
@@ -1060,7 +1067,7 @@ int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decod
     return lz::fail(LZ_E_INVAL, "schedule 0 addresses outputs below 4 GiB; use schedule 1");
   if (h->v.nb == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
-  lz_dev::GraphKey key{d_out, out_cap, G, U, sched, tail};
+  lz_dev::GraphKey key{d_out, out_cap, G, U, sched, tail, (uint32_t)stage};
   for (auto& g : h->graphs)
     if (g.first == key) {
       HIPCHK(hipGraphLaunch(g.second, s));
@@ -1077,8 +1084,8 @@ int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decod
   };
   std::vector<Launch> seq;
   kfn_t kp = pick_kernel<kModeParse>(G, U);
-  seq.push_back({kp, grid_for(h->n_seg, resident_groups(kp, h->cu_count, G), G), A});
-  if (h->n_match) {
+  if (stage != 2) seq.push_back({kp, grid_for(h->n_seg, resident_groups(kp, h->cu_count, G), G), A});
+  if (h->n_match && stage != 1) {
     if (sched == 0) {
       kfn_t k = pick_kernel<kModeFlow>(G, U);
       uint64_t windows = 0;
@@ -1135,6 +1142,19 @@ int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decod
   h->graphs.push_back({key, exec});
   HIPCHK(hipGraphLaunch(exec, s));
   return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cfg* cfg, void* stream) {
+  return decode_stage(h, d_out, out_cap, cfg, 0, stream);
+}
+
+int lz_decode_device_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cfg* cfg, int stage,
+                           void* stream) {
+  return decode_stage(h, d_out, out_cap, cfg, stage, stream);
 }
 
 int lz_device_check(lz_dev* h, void* stream) {

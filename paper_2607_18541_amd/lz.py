@@ -77,6 +77,7 @@ def lib():
             "lz_device_bytes": (ctypes.c_int, [_vp, _u64, _p64]),
             "lz_device_open": (ctypes.c_int, [_vp, _u64, _vp, _u64, _vp, ctypes.POINTER(_vp)]),
             "lz_decode_device": (ctypes.c_int, [_vp, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
+            "lz_decode_device_stage": (ctypes.c_int, [_vp, _vp, _u64, ctypes.POINTER(DecodeCfg), ctypes.c_int, _vp]),
             "lz_device_check": (ctypes.c_int, [_vp, _vp]),
             "lz_device_n": (_u64, [_vp]),
             "lz_device_levels": (_u32, [_vp]),
@@ -292,6 +293,14 @@ class DeviceArchive:
                                     _stream(stream))
         if rc:
             raise LzError(rc, "lz_decode_device")
+
+    def decode_stage(self, out, stage, G=64, unroll=2, schedule=1, stream=None, tail=0):
+        """Stage 1 = parse launch, 2 = match passes (after stage 1), 0 = both."""
+        c = _cfg(G, unroll, schedule, tail)
+        rc = lib().lz_decode_device_stage(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
+                                          int(stage), _stream(stream))
+        if rc:
+            raise LzError(rc, "lz_decode_device_stage")
 
     def check(self, stream=None):
         rc = lib().lz_device_check(self.h, _stream(stream))

@@ -205,3 +205,30 @@ def test_purecopy_matches_reference(m):
             lz.purecopy(T(dst), T(loff), T(ll), T(sr), T(ml), T(us), T(lit), T(ref), out, G=G, unroll=U)
             torch.cuda.synchronize()
             assert torch.equal(out, T(ref))
+
+
+def test_stages_and_tail_settings_agree():
+    """Parse and match passes launched apart, and every tail setting (no tail
+    launch, tail of one-window depths, default, everything after the first
+    depth), give the oracle's bytes."""
+    dev = _dev()
+    x = synth.fastq(3 << 20, seed=9)
+    arc = lz.encode(x, 14, lz.BASE_THR)
+    exp = torch.from_numpy(oracle.decode(arc)).to(dev)
+    da = lz.DeviceArchive(arc, device=dev)
+    assert da.levels >= 8
+    out = torch.full((da.n + 32,), 0x3C, dtype=torch.uint8, device=dev)
+    print("[stages] staged decode", flush=True)
+    da.decode_stage(out, 1)
+    da.decode_stage(out, 2)
+    da.check()
+    torch.cuda.synchronize()
+    assert torch.equal(out[:da.n], exp)
+    for tail in (lz.TAIL_OFF, 1, 0, 1 << 20):
+        print(f"[stages] tail={tail}", flush=True)
+        out.fill_(0x3C)
+        got = da.decode(out, tail=tail)
+        torch.cuda.synchronize()
+        assert torch.equal(got, exp), tail
+        assert bool((out[da.n:] == 0x3C).all().item())
+    da.close()
