@@ -76,7 +76,9 @@ constexpr int kModePure = 2;    // pre-decoded tokens, sources in a reference bu
 constexpr int kModeParse = 3;   // parse blocks, copy literals, fill the match table
 constexpr int kModeTail = 4;    // the last, small levels in one workgroup, a barrier between levels
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr uint64_t kSegTok = 256;  // tokens per parse segment
+constexpr uint64_t kSegTok = 256;    // tokens per parse segment
+constexpr uint32_t kWinBytes = 4096;  // a match window holds at most this many bytes ...
+constexpr uint32_t kWinMatches = 64;  // ... and at most this many matches
 
 constexpr uint64_t kIdleTicks = 500000000ull;  // 5 s of the 100 MHz clock without progress
 constexpr int kWG = 256;
@@ -109,15 +111,15 @@ struct KArgs {
   // parse segments: per segment {t_start, t_end, blk_t_end, pos, lit, x16, x32, archive << 32 | blk}
   const uint64_t* seg;
   uint64_t nseg;
-  // Match windows.  Single archive: implicit windows of G consecutive
-  // match-table slots.  Batch: explicit windows {slot | count << 32 | archive << 40}.
-  const uint64_t* items;
-  const uint32_t* lvl_start;  // per level: first slot (implicit) or first window (explicit); n_levels + 1
+  // Match windows, depth-major: {first slot, count | archive << 8, bytes of the
+  // first match to skip, end byte of the last match (0 = its length)}
+  const u32x4* items;
+  const uint32_t* lvl_start;  // per depth: first window; n_levels + 1 entries
   uint32_t* tickets;          // per level: windows taken (schedule 0)
   uint32_t* wdone;            // per level: windows finished (schedule 0)
   uint32_t* err;
   uint32_t n_levels;
-  uint64_t lo, hi;  // schedule 1 and mode 2: slot or token range (implicit) / window range (explicit)
+  uint64_t lo, hi;  // schedule 1: window range; mode 2: token range (implicit items)
   // mode 2 (pre-decoded tokens)
   const uint64_t* p_dst;
   const uint64_t* p_lit_off;
@@ -332,10 +334,9 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
     out_r = __builtin_amdgcn_make_buffer_rsrc((void*)D.out, 0, (int)out_cap32, 0x00020000);
   };
   // windows of a level (schedule 0)
-  auto level_windows = [&](uint32_t p) -> uint32_t {
-    const uint32_t n = A.lvl_start[p + 1] - A.lvl_start[p];
-    return A.items ? n : (n + G - 1) / G;
-  };
+  // a window holds up to 64 matches; a group of G lanes takes 64 / G parts of it
+  constexpr uint32_t kParts = 64 / G;
+  auto level_windows = [&](uint32_t p) -> uint32_t { return (A.lvl_start[p + 1] - A.lvl_start[p]) * kParts; };
 
   // work item state (replicated on the group's lanes)
   bool finished = false, have_item = false, started = true;
@@ -356,16 +357,18 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
   uint32_t idle = 0;
   uint64_t t_last = 0;
   // a window: explicit record, or the w-th run of G slots from `base`
-  auto set_window = [&](uint64_t k, uint64_t base, uint64_t end) {
-    if (A.items) {
-      const uint64_t e = A.items[k];
-      use_arc((uint32_t)(e >> 40));
-      t_next = e & 0xFFFFFFFFull;
-      t_end = t_next + ((e >> 32) & 0xFFull);
-    } else {
-      t_next = base + k * G;
-      t_end = min(t_next + G, end);
-    }
+  uint32_t w_skip = 0, w_take = 0;  // the window's first-match skip and last-match end
+  uint64_t t_first = 0, t_win_end = 0;
+  // part k of the window list starting at window `base`
+  auto set_window = [&](uint64_t base, uint64_t k) {
+    const u32x4 e = gld(A.items, base + k / kParts);
+    use_arc(e.y >> 8);
+    t_first = uni<G>(e.x);
+    t_win_end = uni<G>((uint64_t)e.x + (e.y & 0xFFu));
+    t_next = min(t_first + (k % kParts) * G, t_win_end);
+    t_end = min(t_next + G, t_win_end);
+    w_skip = uni32<G>(e.z);
+    w_take = uni32<G>(e.w);
   };
 
   for (;;) {
@@ -383,8 +386,7 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
           w = (G == 64) ? __builtin_amdgcn_readfirstlane(w) : __shfl(w, 0, G);
           if (w < level_windows(cur_lvl)) {
             lvl = cur_lvl;
-            if (A.items) set_window(A.lvl_start[lvl] + w, 0, 0);
-            else set_window(w, A.lvl_start[lvl], A.lvl_start[lvl + 1]);
+            set_window(A.lvl_start[lvl], w);
             have_item = true;
             started = lvl <= ready;
             break;
@@ -402,8 +404,7 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
           if (k < level_windows(cur_lvl)) {
             ++iter;
             lvl = cur_lvl;
-            if (A.items) set_window(A.lvl_start[lvl] + k, 0, 0);
-            else set_window(k, A.lvl_start[lvl], A.lvl_start[lvl + 1]);
+            set_window(A.lvl_start[lvl], k);
             have_item = true;
             break;
           }
@@ -418,12 +419,10 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
       } else if (MODE == kModeLevels) {
         const uint64_t k = gid + iter * ngroups;
         ++iter;
-        const uint64_t cnt = A.items ? A.hi - A.lo : (A.hi - A.lo + G - 1) / G;
-        if (k >= cnt) {
+        if (k >= (A.hi - A.lo) * kParts) {
           finished = true;
         } else {
-          if (A.items) set_window(A.lo + k, 0, 0);
-          else set_window(k, A.lo, A.hi);
+          set_window(A.lo, k);
           have_item = true;
         }
       } else if (MODE == kModePure) {
@@ -501,6 +500,7 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
           // ---------------------------------------------- next G tokens
           const uint64_t t = t_next + gl;
           const bool valid = t < t_end;
+          uint32_t m_done_init = 0;
           // every lane loads (lanes past the end reread the last token), so the
           // loads of a step are issued together and waited for once
           const uint64_t tc = valid ? t : t_end - 1;
@@ -570,10 +570,13 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
             m_len = r.y;
             m_src = (uint64_t)r.z | ((uint64_t)(r.w >> 16) << 32);
             l_len = 0;
+            // a long match is split over windows: this window's byte range of it
+            if (valid && t + 1 == t_win_end && w_take) m_len = w_take;
+            if (valid && t == t_first) m_done_init = w_skip;
           }
           const uint64_t cnt = min((uint64_t)G, t_end - t_next);
           t_next += cnt;
-          m_done = 0;
+          m_done = m_done_init;
           l_pend = l_len > 0;
           progressed = true;
         }
@@ -596,7 +599,9 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
         d.a_src = (uintptr_t)D.lit + l_src;
         d.a_len = inc_l ? l_len : 0u;
         d.b_dst = b_dst;
-        d.b_src = (uintptr_t)D.msrc + m_src;
+        // a periodic match copies each piece from the start of its period; any
+        // other match (or the part of it this window starts at) from src + done
+        d.b_src = (uintptr_t)D.msrc + m_src + ((m_dst - m_src < m_len) ? 0u : m_done);
         d.b_len = inc_m ? piece : 0u;
         d.base = base;
         d.ca = ca;
@@ -727,14 +732,16 @@ struct lz_dev {
   uint32_t* d_ctrl = nullptr;  // [1] error flag
   uint32_t* d_slot = nullptr;
   uint32_t* d_lvls = nullptr;
+  u32x4* d_win = nullptr;
   uint32_t* d_tick = nullptr;
   uint32_t* d_wdone = nullptr;
   uint64_t* d_seg = nullptr;
   uint64_t n_seg = 0;
   u32x4* d_mtab = nullptr;
   uint64_t n_match = 0;
-  std::vector<uint64_t> lvl_start;  // first match-table slot of each level, n_levels + 1 entries
-  std::vector<uint64_t> h_seg;      // host copy of the parse segments (batch decodes merge them)
+  std::vector<uint64_t> lvl_start;  // first window of each depth, n_levels + 1 entries
+  std::vector<uint64_t> h_seg;      // host copies of the parse segments and windows (batch decodes merge them)
+  std::vector<uint32_t> h_win;
   int cu_count = 0;
   // replayable launch sequences, one per (output, config)
   struct GraphKey {
@@ -764,7 +771,7 @@ struct lz_dev {
 namespace {
 
 struct DevLayout {
-  uint64_t arc, ctrl, slot, lvls, tick, wdone, seg, mtab, total;
+  uint64_t arc, ctrl, slot, lvls, tick, wdone, seg, win, mtab, total;
 };
 
 // Device layout for an archive; level and match counts are bounded by n_tok.
@@ -779,7 +786,8 @@ DevLayout layout(const lz::ArcView& v) {
   L.tick = a256(L.lvls + 4 * (T + 2));
   L.wdone = a256(L.tick + 4 * (T + 2));
   L.seg = a256(L.wdone + 4 * (T + 2));
-  L.mtab = a256(L.seg + 64 * (T / kSegTok + v.nb + 2));
+  L.win = a256(L.seg + 64 * (T / kSegTok + v.nb + 2));
+  L.mtab = a256(L.win + 16 * (T + v.n / kWinBytes + 2));
   L.total = a256(L.mtab + 16 * (T + 1));
   return L;
 }
@@ -790,10 +798,28 @@ DevLayout layout(const lz::ArcView& v) {
     if (e_ != hipSuccess) return lz::fail(LZ_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
   } while (0)
 
+// fn(b) for every block b, on up to 16 host threads
+template <typename F>
+void parallel_blocks(const lz::ArcView& v, F fn) {
+  std::vector<std::thread> pool;
+  const unsigned W = std::min<unsigned>(lz::hw_threads(0), 16);
+  std::atomic<uint64_t> next{0};
+  for (unsigned w = 0; w < W; ++w)
+    pool.emplace_back([&] {
+      for (;;) {
+        const uint64_t b = next.fetch_add(1);
+        if (b >= v.nb) break;
+        fn(b);
+      }
+    });
+  for (auto& t : pool) t.join();
+}
+
 // Host plan: dependency depth of every match -> match-table slots ordered by
 // (depth, token); parse segments with their stream cursors.
 struct Plan {
   std::vector<uint32_t> slot, lvls32;
+  std::vector<uint32_t> win;  // windows, 4 words each
   std::vector<uint64_t> seg;  // parse segments, 8 words each
   std::vector<uint64_t> lvl_start;
   uint64_t n_match = 0;
@@ -818,12 +844,61 @@ int build_plan(const lz::ArcView& v, Plan& P) {
     }
   P.n_match = M;
   if (M > 0xFFFFFFF0ull) return lz::fail(LZ_E_INVAL, "too many matches for 32-bit plan indices");
-  P.lvl_start.assign(NL + 1, 0);
-  for (uint64_t p = 0; p < NL; ++p) P.lvl_start[p + 1] = P.lvl_start[p] + cnt[p + 1];
-  std::vector<uint64_t> cursor(P.lvl_start.begin(), P.lvl_start.end());
+  std::vector<uint64_t> sstart(NL + 1, 0);  // first slot of each depth
+  for (uint64_t p = 0; p < NL; ++p) sstart[p + 1] = sstart[p] + cnt[p + 1];
+  std::vector<uint64_t> cursor(sstart.begin(), sstart.end());
   P.slot.assign(T + 1, kNone);
+  std::vector<uint32_t> tok_of(M + 1, 0), len_of(M + 1, 0);
+  std::vector<uint8_t> periodic(M + 1, 0);
   for (uint64_t t = 0; t < T; ++t)
-    if (hasm[t]) P.slot[t] = (uint32_t)cursor[depth[t] - 1]++;
+    if (hasm[t]) {
+      P.slot[t] = (uint32_t)cursor[depth[t] - 1]++;
+      tok_of[P.slot[t]] = (uint32_t)t;
+    }
+  // lengths, and whether a match overlaps its own output
+  {
+    std::atomic<int> bad{0};
+    parallel_blocks(v, [&](uint64_t b) {
+      int r = lz::walk_block(v, b, [&](uint64_t t, const lz::Tok& k) {
+        if (!k.mlen) return;
+        const uint32_t sl = P.slot[t];
+        len_of[sl] = (uint32_t)k.mlen;
+        periodic[sl] = (k.dst + k.lit_len - k.src < k.mlen) ? 1 : 0;
+      });
+      if (r) bad.store(r);
+    });
+    if (bad.load()) return lz::fail(LZ_E_CORRUPT, "archive fails validation");
+  }
+  // windows of each depth: at most kWinMatches matches and kWinBytes bytes; a
+  // longer match that does not overlap itself is split into kWinBytes pieces
+  P.lvl_start.assign(NL + 1, 0);
+  for (uint64_t p = 0; p < NL; ++p) {
+    P.lvl_start[p] = P.win.size() / 4;
+    uint64_t w0 = 0, wc = 0, wb = 0;
+    auto flush = [&] {
+      if (!wc) return;
+      const uint32_t rec[4] = {(uint32_t)w0, (uint32_t)wc, 0u, 0u};
+      P.win.insert(P.win.end(), rec, rec + 4);
+      wc = wb = 0;
+    };
+    for (uint64_t sl = sstart[p]; sl < sstart[p + 1]; ++sl) {
+      const uint32_t L = len_of[sl];
+      if (!periodic[sl] && L > kWinBytes) {
+        flush();
+        for (uint32_t off = 0; off < L; off += kWinBytes) {
+          const uint32_t rec[4] = {(uint32_t)sl, 1u, off, std::min(off + kWinBytes, L)};
+          P.win.insert(P.win.end(), rec, rec + 4);
+        }
+        continue;
+      }
+      if (wc && (wc == kWinMatches || wb + L > kWinBytes)) flush();
+      if (!wc) w0 = sl;
+      ++wc;
+      wb += L;
+    }
+    flush();
+  }
+  P.lvl_start[NL] = P.win.size() / 4;
   P.lvls32.assign(P.lvl_start.begin(), P.lvl_start.end());
   // parse segments: every kSegTok tokens of a block, with the cursors there
   {
@@ -886,6 +961,7 @@ KArgs base_args(const lz_dev* h) {
   memset(&A, 0, sizeof(A));
   A.one = arc_desc(h, nullptr, 0);
   A.lvl_start = h->d_lvls;
+  A.items = h->d_win;
   A.tickets = h->d_tick;
   A.wdone = h->d_wdone;
   A.seg = h->d_seg;
@@ -992,6 +1068,7 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
   h->d_ctrl = (uint32_t*)(base + L.ctrl);
   h->d_slot = (uint32_t*)(base + L.slot);
   h->d_lvls = (uint32_t*)(base + L.lvls);
+  h->d_win = (u32x4*)(base + L.win);
   h->d_tick = (uint32_t*)(base + L.tick);
   h->d_wdone = (uint32_t*)(base + L.wdone);
   h->d_seg = (uint64_t*)(base + L.seg);
@@ -1000,6 +1077,7 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
   h->n_match = P.n_match;
   h->lvl_start = P.lvl_start;
   h->h_seg = P.seg;
+  h->h_win = P.win;
   hipStream_t s = (hipStream_t)stream;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -1016,6 +1094,7 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
   const Piece pieces[] = {
       {h->d_slot, P.slot.data(), 4 * P.slot.size()},
       {h->d_lvls, P.lvls32.data(), 4 * P.lvls32.size()},
+      {h->d_win, P.win.data(), 4 * P.win.size()},
       {h->d_seg, P.seg.data(), 8 * P.seg.size()},
   };
   uint64_t stage = v.total;
@@ -1088,25 +1167,23 @@ int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cf
   if (h->n_match && stage != 1) {
     if (sched == 0) {
       kfn_t k = pick_kernel<kModeFlow>(G, U);
-      uint64_t windows = 0;
-      for (size_t p = 0; p + 1 < h->lvl_start.size(); ++p)
-        windows += (h->lvl_start[p + 1] - h->lvl_start[p] + G - 1) / G;
+      const uint64_t windows = h->lvl_start.back() * (64 / G);
       seq.push_back({k, grid_for(windows, resident_groups(k, h->cu_count, G), G), A});
     } else {
       kfn_t k = pick_kernel<kModeLevels>(G, U);
       const uint64_t res = resident_groups(k, h->cu_count, G);
       const uint64_t NL = h->lvl_start.size() - 1;
       std::vector<uint64_t> win(NL);
-      for (uint64_t p = 0; p < NL; ++p) win[p] = (h->lvl_start[p + 1] - h->lvl_start[p] + 63) / 64;
+      for (uint64_t p = 0; p < NL; ++p) win[p] = h->lvl_start[p + 1] - h->lvl_start[p];
       const uint64_t pt = (tail == kTailOff || out_cap > 0xFFFFFFFFull) ? NL : tail_start(win, tail);
       for (uint64_t p = 0; p < pt; ++p) {
         KArgs a = A;
         a.lo = h->lvl_start[p];
         a.hi = h->lvl_start[p + 1];
         if (a.hi == a.lo) continue;
-        seq.push_back({k, grid_for((a.hi - a.lo + G - 1) / G, res, G), a});
+        seq.push_back({k, grid_for((a.hi - a.lo) * (64 / G), res, G), a});
       }
-      if (pt < NL) {  // the deepest levels: one workgroup, windows of 64 matches
+      if (pt < NL) {  // the deepest levels: one workgroup
         KArgs a = A;
         a.lo = pt;
         a.hi = NL;
@@ -1513,11 +1590,12 @@ struct BatchGroup {
 };
 
 // windows of G match-table slots over every level of the group's archives
-uint64_t group_windows(const std::vector<lz_dev*>& H, const BatchGroup& g, uint32_t G, uint64_t* nl_out) {
+// windows over every depth of the group's archives
+uint64_t group_windows(const std::vector<lz_dev*>& H, const BatchGroup& g, uint64_t* nl_out) {
   uint64_t nw = 0, nl = 0;
   for (uint32_t i : g.arcs) {
     const auto& ls = H[i]->lvl_start;
-    for (size_t p = 0; p + 1 < ls.size(); ++p) nw += (ls[p + 1] - ls[p] + G - 1) / G;
+    nw += ls.empty() ? 0 : ls.back();
     nl = std::max<uint64_t>(nl, ls.size() ? ls.size() - 1 : 0);
   }
   if (nl_out) *nl_out = nl;
@@ -1528,12 +1606,12 @@ uint64_t group_scratch(const std::vector<lz_dev*>& H, const BatchGroup& g, uint6
                        uint64_t* nl_out) {
   uint64_t nseg = 0, nl = 0;
   for (uint32_t i : g.arcs) nseg += H[i]->h_seg.size() / 8;
-  const uint64_t nw = group_windows(H, g, g.cfg.G ? g.cfg.G : 64, &nl);
+  const uint64_t nw = group_windows(H, g, &nl);
   auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
   if (nseg_out) *nseg_out = nseg;
   if (nw_out) *nw_out = nw;
   if (nl_out) *nl_out = nl;
-  return a256(sizeof(ArcDesc) * g.arcs.size()) + a256(64 * nseg) + a256(8 * (nw + 1)) + 3 * a256(4 * (nl + 1)) + 256;
+  return a256(sizeof(ArcDesc) * g.arcs.size()) + a256(64 * nseg) + a256(16 * (nw + 1)) + 3 * a256(4 * (nl + 1)) + 256;
 }
 
 std::vector<BatchGroup> make_groups(uint32_t count, const lz_decode_cfg* cfgs) {
@@ -1615,14 +1693,14 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
     const uint64_t o_desc = off;
     const uint64_t o_seg = o_desc + a256(sizeof(ArcDesc) * g.arcs.size());
     const uint64_t o_items = o_seg + a256(64 * nseg);
-    const uint64_t o_lvls = o_items + a256(8 * (nw + 1));
+    const uint64_t o_lvls = o_items + a256(16 * (nw + 1));
     const uint64_t o_tick = o_lvls + a256(4 * (nl + 1));
     const uint64_t o_wdone = o_tick + a256(4 * (nl + 1));
     const uint64_t o_err = o_wdone + a256(4 * (nl + 1));
     off = o_err + 256;
     ArcDesc* desc = (ArcDesc*)(img.data() + o_desc);
     uint64_t* seg = (uint64_t*)(img.data() + o_seg);
-    uint64_t* items = (uint64_t*)(img.data() + o_items);
+    uint32_t* items = (uint32_t*)(img.data() + o_items);
     uint32_t* lvls = (uint32_t*)(img.data() + o_lvls);
     uint64_t si = 0;
     for (uint32_t j = 0; j < g.arcs.size(); ++j) {
@@ -1639,10 +1717,15 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
     for (uint64_t p = 0; p < nl; ++p) {
       lvls[p] = (uint32_t)wi;
       for (uint32_t j = 0; j < g.arcs.size(); ++j) {
-        const auto& ls = H[g.arcs[j]]->lvl_start;
+        const lz_dev* h = H[g.arcs[j]];
+        const auto& ls = h->lvl_start;
         if (p + 1 >= ls.size()) continue;
-        for (uint64_t q = ls[p]; q < ls[p + 1]; q += G)
-          items[wi++] = q | (std::min<uint64_t>(G, ls[p + 1] - q) << 32) | ((uint64_t)j << 40);
+        for (uint64_t q = ls[p]; q < ls[p + 1]; ++q, ++wi) {
+          items[4 * wi] = h->h_win[4 * q];
+          items[4 * wi + 1] = h->h_win[4 * q + 1] | (j << 8);
+          items[4 * wi + 2] = h->h_win[4 * q + 2];
+          items[4 * wi + 3] = h->h_win[4 * q + 3];
+        }
       }
     }
     lvls[nl] = (uint32_t)wi;
@@ -1652,7 +1735,7 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
     A.one = desc[0];
     A.seg = (const uint64_t*)(D0 + o_seg);
     A.nseg = nseg;
-    A.items = (const uint64_t*)(D0 + o_items);
+    A.items = (const u32x4*)(D0 + o_items);
     A.lvl_start = (const uint32_t*)(D0 + o_lvls);
     A.tickets = (uint32_t*)(D0 + o_tick);
     A.wdone = (uint32_t*)(D0 + o_wdone);
@@ -1665,7 +1748,7 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
     if (nw) {
       if (sched == 0) {
         kfn_t k = pick_kernel<kModeFlow>(G, U, true);
-        seq.push_back({k, grid_for(nw, resident_groups(k, cu, G), G), A});
+        seq.push_back({k, grid_for(nw * (64 / G), resident_groups(k, cu, G), G), A});
       } else {
         kfn_t k = pick_kernel<kModeLevels>(G, U, true);
         const uint64_t res = resident_groups(k, cu, G);
@@ -1679,7 +1762,7 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
           a.lo = lvls[p];
           a.hi = lvls[p + 1];
           if (a.hi == a.lo) continue;
-          seq.push_back({k, grid_for(a.hi - a.lo, res, G), a});
+          seq.push_back({k, grid_for((a.hi - a.lo) * (64 / G), res, G), a});
         }
         if (pt < nl) {  // the deepest levels: one workgroup over their windows
           KArgs a = A;
