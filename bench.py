@@ -305,6 +305,187 @@ def run_profile(args, torch, lz):
     return {"profile_run": True, "n": n, "steps": args.steps, "calibration": "bitwise_not over n bytes"}
 
 
+def copy_units(span, G, max_bytes):
+    """Token ranges for the pure-copy control: a new unit starts where the
+    output offset crosses a multiple of max_bytes, and every G tokens inside
+    such a stretch (so at most G tokens, about max_bytes bytes each)."""
+    span = np.asarray(span, dtype=np.int64)
+    T = span.size
+    if T == 0:
+        return np.zeros(1, dtype=np.uint64)
+    bucket = (np.concatenate([[0], np.cumsum(span)[:-1]]) // max_bytes)
+    first = np.concatenate([[True], bucket[1:] != bucket[:-1]])
+    start_of = np.maximum.accumulate(np.where(first, np.arange(T), 0))
+    cut = first | ((np.arange(T) - start_of) % G == 0)
+    return np.concatenate([np.nonzero(cut)[0], [T]]).astype(np.uint64)
+
+
+def run_batch(args, torch, lz):
+    """Batched decode: `count` independent archives, sizes log-uniform from
+    4 KiB to 16 MiB, even ones Zipf text and odd ones FASTQ-like reads,
+    thresholds alternating 6/8/10/12 and 12/16/24/32.  Timed three ways: one
+    decode call per archive (each its own launch sequence), one batch graph
+    with the default configuration, and one batch graph with the per-bucket
+    configuration the autotuner picks."""
+    import synth
+    dev = torch.device("cuda:0")
+    k = args.count
+    sizes = synth.loguniform(k, 4096, 16 << 20, 4)
+    das, outs, ins = [], [], []
+    total = 0
+    t0 = time.perf_counter()
+    for i, sz in enumerate(sizes):
+        sz = int(sz)
+        x = synth.zipf_text(sz, seed=4000 + i) if i % 2 == 0 else synth.fastq(sz, seed=4000 + i)
+        thr = (lz.BASE_THR, lz.TUNED_THR)[(i // 2) % 2]
+        arc = lz.encode(x, args.log2_bs, thr, lz.BOUNDS_CFG, max_chain=args.max_chain)
+        da = lz.DeviceArchive(arc, device=dev)
+        das.append(da)
+        outs.append(torch.empty(max(da.n, 1), dtype=torch.uint8, device=dev))
+        ins.append(torch.from_numpy(x).to(dev))
+        total += da.n
+        if (i + 1) % 256 == 0:
+            log("encoded and opened %d/%d archives (%.2f GiB) in %.0fs" % (i + 1, k, total / 2**30,
+                                                                       time.perf_counter() - t0))
+
+    def check(label):
+        for i, (o, x) in enumerate(zip(outs, ins)):
+            if not bool(torch.equal(o[:x.numel()], x)):
+                raise SystemExit("%s: archive %d differs" % (label, i))
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    res = {}
+    for o in outs:
+        o.fill_(0)
+    ms = timed(lambda: [d.decode_async(o, G=args.G, unroll=args.unroll) for d, o in zip(das, outs)], args.steps)
+    check("per-archive")
+    res["per_archive"] = {"ms": round(ms, 3), "gbps": round(total / ms / 1e6, 2)}
+    log("per-archive launches: %.3f ms, %.1f GB/s" % (ms, total / ms / 1e6))
+    for o in outs:
+        o.fill_(0)
+    b = lz.Batch(das, outs, None)
+    ms = timed(b.launch, args.steps)
+    check("batch")
+    res["batch_default"] = {"ms": round(ms, 3), "gbps": round(total / ms / 1e6, 2), "launches": b.launches}
+    log("one batch graph (G=64, U=2): %.3f ms, %.1f GB/s" % (ms, total / ms / 1e6))
+    b.destroy()
+    cfgs, report = lz.autotune(das, outs, reps=2)
+    log("autotuned %d buckets" % len(report))
+    for o in outs:
+        o.fill_(0)
+    b = lz.Batch(das, outs, cfgs)
+    ms = timed(b.launch, args.steps)
+    check("batch autotuned")
+    res["batch_autotuned"] = {"ms": round(ms, 3), "gbps": round(total / ms / 1e6, 2), "launches": b.launches,
+                              "buckets": [{"bytes": [r["min_bytes"], r["max_bytes"]], "archives": r["archives"],
+                                           "best": list(r["best"]), "best_ms": round(r["best_ms"], 4),
+                                           "default_ms": round(r["default_ms"], 4)} for r in report]}
+    log("one batch graph, autotuned: %.3f ms, %.1f GB/s" % (ms, total / ms / 1e6))
+    b.destroy()
+    best = max(v["gbps"] for v in res.values())
+    return {"metric": "batched decode GB/s (device-resident)", "value": best, "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": res["batch_autotuned"]["ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "%d archives, log-uniform 4 KiB-16 MiB, %d B total, half Zipf text, half "
+                                   "FASTQ-like, thresholds alternating" % (k, total)},
+            "detail": res}
+
+
+def run_serve(args, torch, lz):
+    """Serving loop: Poisson arrivals of range decodes (lengths log-uniform
+    16 KiB-64 MiB, offsets uniform) against one device-resident FASTQ-like
+    archive, admitted by slots and arena memory, one merged launch group per
+    tick.  Latency = submit to observed completion (host clock)."""
+    import synth
+    dev = torch.device("cuda:0")
+    n = args.size
+    t0 = time.perf_counter()
+    x = synth.fastq(n, seed=5)
+    n = int(x.size)
+    log("generated %d B in %.0fs" % (n, time.perf_counter() - t0))
+    seg = (1 << 30) if n > (3 << 30) else 0
+    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain, segment=seg)
+    log("encoded: %d B archive (ratio %.3f) in %.0fs" % (arc.size, n / arc.size, time.perf_counter() - t0))
+    da = lz.DeviceArchive(arc, device=dev)
+    log("opened on the device (%d depths)" % da.levels)
+    del arc
+    k = args.requests
+    lens = synth.loguniform(k, 16 << 10, 64 << 20, 51).astype(np.int64)
+    offs = (synth.uniform(k, 52) * (n - lens)).astype(np.int64)
+    # one-at-a-time service time: a few requests served one after another
+    t1 = time.perf_counter()
+    for i in range(8):
+        da.decode_range(int(offs[i]), int(lens[i]))
+    torch.cuda.synchronize()
+    per_req = (time.perf_counter() - t1) / 8
+    rows = []
+    for load in [float(v) for v in str(args.load).split(",")]:
+        rate = load / per_req  # requests per second offered
+        gaps = -np.log(1.0 - synth.uniform(k, 53)) / rate
+        arrive = np.cumsum(gaps)
+        srv = lz.Server(da, args.arena << 20, slots=args.slots)
+        lat = np.zeros(k)
+        pending = {}
+        nxt = 0
+        done = 0
+        T0 = time.perf_counter()
+        last_log = T0
+        while done < k:
+            now = time.perf_counter() - T0
+            while nxt < k and arrive[nxt] <= now:
+                rid = srv.submit(int(offs[nxt]), int(lens[nxt]))
+                pending[rid] = (nxt, T0 + arrive[nxt])
+                nxt += 1
+            srv.tick()
+            for rid in list(pending):
+                st, _ = srv.status(rid)
+                if st == 2:
+                    i, ta = pending.pop(rid)
+                    lat[i] = time.perf_counter() - ta
+                    srv.release(rid)
+                    done += 1
+            if time.perf_counter() - last_log > 10:
+                last_log = time.perf_counter()
+                log("load %.1f: served %d/%d requests" % (load, done, k))
+            if nxt < k and not pending:
+                time.sleep(max(0.0, min(0.001, arrive[nxt] - (time.perf_counter() - T0))))
+        wall = time.perf_counter() - T0
+        hw = srv.stats()["arena_high_water"]
+        srv.destroy()
+        tot = int(lens.sum())
+        rows.append({"load": load, "offered_req_per_s": round(rate, 2), "gbps": round(tot / wall / 1e9, 3),
+                     "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                     "mean_ms": round(float(lat.mean()) * 1e3, 2), "wall_s": round(wall, 2),
+                     "arena_high_water": int(hw)})
+        log("load %.1f: %s" % (load, json.dumps(rows[-1])))
+    # every tenth request checked against the input
+    for i in range(0, k, 10):
+        got = da.decode_range(int(offs[i]), int(lens[i]))
+        if not bool(torch.equal(got, torch.from_numpy(x[offs[i]:offs[i] + lens[i]]).to(dev))):
+            raise SystemExit("range %d differs" % i)
+    best = max(rows, key=lambda r: r["gbps"])
+    return {"metric": "range-serving GB/s and latency", "value": best["gbps"], "unit": "GB/s",
+            "n_gpus": 1, "steps": k, "warmup": 8, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "FASTQ-like %d B (12/16/24/32, %s), %d Poisson range requests of 16 KiB-64 MiB "
+                                   "per load level" % (n, "1 GiB segments" if seg else "one segment", k),
+                       "arena_mib": args.arena, "slots": args.slots},
+            "detail": {"alone_ms": round(per_req * 1e3, 2), "mean_request_bytes": int(lens.mean()),
+                       "loads": rows, "best": best}}
+
+
 def run_sweep(args, torch, lz):
     """Granularity sweep (the copy sweep of Table II): generated streams of n
     bytes whose match lengths are geometric with mean m, sources uniform over
@@ -350,8 +531,7 @@ def run_sweep(args, torch, lz):
         out = torch.empty(n, dtype=torch.uint8, device=dev)
         pc_alg = n + int(mlv.sum()) + int(llv.sum()) + T * 28
         for G in (8, 16, 32, 64):
-            us = g(np.minimum(np.arange(0, T + G, G), T), np.uint64)
-            us = torch.unique_consecutive(us)
+            us = g(copy_units(llv + mlv, G, 2048), np.uint64)
             lz.purecopy(tdst, tlo, tll, tsrc, tml, us, tlit, ref, out, G=G, unroll=args.unroll)
             torch.cuda.synchronize()
             if not bool(torch.equal(out, ref)):
@@ -384,7 +564,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fastq", choices=["fastq", "sweep"])
+    ap.add_argument("--workload", default="fastq", choices=["fastq", "sweep", "batch", "serve"])
+    ap.add_argument("--count", type=int, default=4096, help="batch: archives")
+    ap.add_argument("--requests", type=int, default=300, help="serve: requests")
+    ap.add_argument("--load", default="1,4,16", help="serve: offered rate / one-at-a-time rate (comma list)")
+    ap.add_argument("--arena", type=int, default=4096, help="serve: arena MiB")
+    ap.add_argument("--slots", type=int, default=64, help="serve: request slots")
     ap.add_argument("--size", type=int, default=1 << 30)
     ap.add_argument("--log2-bs", dest="log2_bs", type=int, default=16)
     ap.add_argument("--G", type=int, default=64)
@@ -418,6 +603,10 @@ def main():
         if args.size == 1 << 30:
             args.size = 1 << 28
         line = run_sweep(args, torch, lz)
+    elif args.workload == "batch":
+        line = run_batch(args, torch, lz)
+    elif args.workload == "serve":
+        line = run_serve(args, torch, lz)
     else:
         line = run_fastq(args, torch, lz)
     print(json.dumps(line), flush=True)

@@ -181,7 +181,9 @@ int lz_decode_device_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz
                            void* stream);
 
 /* Synchronises `stream` and reports a device-side failure of the last decode
- * on this handle (LZ_E_BUSY if a bounded wait expired), else 0. */
+ * on this handle: LZ_E_BUSY if a bounded wait expired, LZ_E_CORRUPT if a match
+ * record outside the output was skipped, LZ_E_INVAL for a launch of the wrong
+ * workgroup size; else 0. */
 int lz_device_check(lz_dev* h, void* stream);
 
 uint64_t lz_device_n(const lz_dev* h);
@@ -192,17 +194,22 @@ void lz_device_close(lz_dev* h);
 
 /* Region seek on a device-resident archive (Abstract; Sec. 1 "Positioning":
  * random access into compressed-resident data without whole-file decode).
- * A plan covers `count` ranges [off[i], off[i]+len[i]): the host computes the
- * token closure of each range (every token the range's bytes depend on through
- * match sources), lays it out in output order in device scratch and orders
- * its copies by dependency depth.  LZ_E_RANGE if a range leaves [0, n).  Plans
- * are host objects; free with lz_range_plan_free after the stream that ran
- * them has completed. */
+ * A plan covers `count` ranges [off[i], off[i]+len[i]).  The host first
+ * computes the token closure of each range (every token the range's bytes
+ * depend on through match sources), lays it out in output order in device
+ * scratch and orders its copies by dependency depth.  Closures cost host work
+ * per byte, so once they exceed max(1 MiB, E/256) bytes, E = the largest range
+ * end, the plan instead decodes every token before E on the device (parse
+ * segments and depth windows of that prefix) into scratch and gathers the
+ * ranges from it.  LZ_E_RANGE if a range leaves [0, n).  Plans are host
+ * objects; free with lz_range_plan_free after the stream that ran them has
+ * completed. */
 typedef struct lz_range_plan lz_range_plan;
 int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const uint64_t* len, lz_range_plan** plan);
 uint64_t lz_range_plan_scratch_bytes(const lz_range_plan* plan); /* device scratch lz_range_run needs */
 uint64_t lz_range_plan_levels(const lz_range_plan* plan);        /* match depths (launches) */
-uint64_t lz_range_plan_closure_bytes(const lz_range_plan* plan); /* decoded bytes incl. the ranges */
+uint64_t lz_range_plan_closure_bytes(const lz_range_plan* plan); /* closure bytes (0 for a prefix plan) */
+uint64_t lz_range_plan_prefix_bytes(const lz_range_plan* plan);  /* prefix decoded (0 for a closure plan) */
 void lz_range_plan_free(lz_range_plan* plan);
 
 /* Runs a plan on `stream`: range i is written to d_out[out_off[i], +len[i]),

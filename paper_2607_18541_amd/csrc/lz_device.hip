@@ -49,6 +49,7 @@
 #include <map>
 #include <mutex>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "lz_internal.h"
@@ -77,8 +78,12 @@ constexpr int kModeParse = 3;   // parse blocks, copy literals, fill the match t
 constexpr int kModeTail = 4;    // the last, small levels in one workgroup, a barrier between levels
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint64_t kSegTok = 256;    // tokens per parse segment
-constexpr uint32_t kWinBytes = 4096;  // a match window holds at most this many bytes ...
+constexpr uint32_t kWinBytes = 2048;  // a match window holds at most this many bytes ...
 constexpr uint32_t kWinMatches = 64;  // ... and at most this many matches
+constexpr uint64_t kWinSpan = 1ull << 20;  // and its matches start within this many output bytes
+constexpr uint64_t kClosureMin = 1ull << 20;  // range closures of up to max(1 MiB, prefix / 256) bytes;
+constexpr uint64_t kClosureRatio = 256;       // beyond that the prefix is decoded instead
+constexpr uint64_t kGatherPiece = 64ull << 10;  // ranges are gathered into the output in pieces of this size
 
 constexpr uint64_t kIdleTicks = 500000000ull;  // 5 s of the 100 MHz clock without progress
 constexpr int kWG = 256;
@@ -570,6 +575,10 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
             m_len = r.y;
             m_src = (uint64_t)r.z | ((uint64_t)(r.w >> 16) << 32);
             l_len = 0;
+            if (valid && (m_src >= m_dst || m_dst + m_len > D.n)) {  // not a record of this archive
+              m_len = 0;
+              atomicOr(A.err, 4u);
+            }
             // a long match is split over windows: this window's byte range of it
             if (valid && t + 1 == t_win_end && w_take) m_len = w_take;
             if (valid && t == t_first) m_done_init = w_skip;
@@ -742,6 +751,7 @@ struct lz_dev {
   std::vector<uint64_t> lvl_start;  // first window of each depth, n_levels + 1 entries
   std::vector<uint64_t> h_seg;      // host copies of the parse segments and windows (batch decodes merge them)
   std::vector<uint32_t> h_win;
+  std::vector<uint64_t> h_wdst;  // per window: output position of its first byte
   int cu_count = 0;
   // replayable launch sequences, one per (output, config)
   struct GraphKey {
@@ -819,7 +829,8 @@ void parallel_blocks(const lz::ArcView& v, F fn) {
 // (depth, token); parse segments with their stream cursors.
 struct Plan {
   std::vector<uint32_t> slot, lvls32;
-  std::vector<uint32_t> win;  // windows, 4 words each
+  std::vector<uint32_t> win;   // windows, 4 words each
+  std::vector<uint64_t> wdst;  // per window: output position of its first match
   std::vector<uint64_t> seg;  // parse segments, 8 words each
   std::vector<uint64_t> lvl_start;
   uint64_t n_match = 0;
@@ -849,6 +860,7 @@ int build_plan(const lz::ArcView& v, Plan& P) {
   std::vector<uint64_t> cursor(sstart.begin(), sstart.end());
   P.slot.assign(T + 1, kNone);
   std::vector<uint32_t> tok_of(M + 1, 0), len_of(M + 1, 0);
+  std::vector<uint64_t> dst_of(M + 1, 0);
   std::vector<uint8_t> periodic(M + 1, 0);
   for (uint64_t t = 0; t < T; ++t)
     if (hasm[t]) {
@@ -863,6 +875,7 @@ int build_plan(const lz::ArcView& v, Plan& P) {
         if (!k.mlen) return;
         const uint32_t sl = P.slot[t];
         len_of[sl] = (uint32_t)k.mlen;
+        dst_of[sl] = k.dst + k.lit_len;
         periodic[sl] = (k.dst + k.lit_len - k.src < k.mlen) ? 1 : 0;
       });
       if (r) bad.store(r);
@@ -879,6 +892,7 @@ int build_plan(const lz::ArcView& v, Plan& P) {
       if (!wc) return;
       const uint32_t rec[4] = {(uint32_t)w0, (uint32_t)wc, 0u, 0u};
       P.win.insert(P.win.end(), rec, rec + 4);
+      P.wdst.push_back(dst_of[w0]);
       wc = wb = 0;
     };
     for (uint64_t sl = sstart[p]; sl < sstart[p + 1]; ++sl) {
@@ -888,10 +902,11 @@ int build_plan(const lz::ArcView& v, Plan& P) {
         for (uint32_t off = 0; off < L; off += kWinBytes) {
           const uint32_t rec[4] = {(uint32_t)sl, 1u, off, std::min(off + kWinBytes, L)};
           P.win.insert(P.win.end(), rec, rec + 4);
+          P.wdst.push_back(dst_of[sl] + off);
         }
         continue;
       }
-      if (wc && (wc == kWinMatches || wb + L > kWinBytes)) flush();
+      if (wc && (wc == kWinMatches || wb + L > kWinBytes || dst_of[sl] >= dst_of[w0] + kWinSpan)) flush();
       if (!wc) w0 = sl;
       ++wc;
       wb += L;
@@ -1078,6 +1093,7 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
   h->lvl_start = P.lvl_start;
   h->h_seg = P.seg;
   h->h_win = P.win;
+  h->h_wdst = P.wdst;
   hipStream_t s = (hipStream_t)stream;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -1240,7 +1256,9 @@ int lz_device_check(lz_dev* h, void* stream) {
   uint32_t err = 0;
   HIPCHK(hipMemcpyAsync(&err, h->d_ctrl + 1, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (err) return lz::fail(LZ_E_BUSY, "a bounded device wait expired (err %u)", err);
+  if (err & 1u) return lz::fail(LZ_E_BUSY, "a bounded device wait expired (err %u)", err);
+  if (err & 4u) return lz::fail(LZ_E_CORRUPT, "a match record outside the output was skipped (err %u)", err);
+  if (err) return lz::fail(LZ_E_INVAL, "a kernel was launched with the wrong workgroup size (err %u)", err);
   return 0;
 }
 
@@ -1295,6 +1313,11 @@ int lz_purecopy_device(uint64_t ntok, const uint64_t* d_dst, const uint64_t* d_l
 
 struct lz_range_plan {
   uint64_t count = 0;
+  // prefix mode: every token before prefix_end is decoded into the scratch
+  // data (parse segments [0, nseg), depth p windows [first, win_hi[p]))
+  bool prefix = false;
+  uint64_t prefix_end = 0, nseg = 0;
+  std::vector<uint64_t> win_hi;
   std::vector<uint64_t> range_src;   // per range: scratch-data offset of byte off
   std::vector<uint64_t> range_len;
   uint64_t data_bytes = 0;           // scratch-data bytes
@@ -1302,6 +1325,7 @@ struct lz_range_plan {
   std::vector<uint64_t> p_dst, p_lit_off, p_src;
   std::vector<uint32_t> p_lit_len, p_mlen;
   std::vector<uint64_t> lvl_piece;   // first piece of each level (D+2 entries)
+  std::vector<uint64_t> g_range, g_off;  // gather pieces: range and offset inside it
   uint64_t scratch_bytes = 0;        // total device scratch for lz_range_run
   uint8_t* staging = nullptr;        // pinned copy of the piece arrays
   uint64_t staging_bytes = 0;
@@ -1331,11 +1355,13 @@ struct NeedTok {
   uint32_t level;    // match depth
 };
 
-// Token closure of [off, off+len): needed tokens sorted by dst.
-void closure(lz_dev* h, uint64_t off, uint64_t len, std::vector<NeedTok>& need) {
+// Token closure of [off, off+len): needed tokens sorted by dst.  Stops and
+// returns false once the needed tokens span more than `budget` bytes.
+bool closure(lz_dev* h, uint64_t off, uint64_t len, std::vector<NeedTok>& need, uint64_t budget) {
   const uint32_t lb = h->v.log2_bs;
   std::vector<std::pair<uint64_t, uint64_t>> work{{off, off + len}};
-  std::vector<std::vector<uint8_t>> seen(h->v.nb);
+  std::unordered_map<uint64_t, std::vector<uint8_t>> seen;  // visited blocks: tokens taken
+  uint64_t bytes = 0;
   need.clear();
   while (!work.empty()) {
     auto [a, e] = work.back();
@@ -1354,6 +1380,8 @@ void closure(lz_dev* h, uint64_t off, uint64_t len, std::vector<NeedTok>& need) 
         if (t.dst + t.ll + t.ml <= a || sb[i]) continue;
         sb[i] = 1;
         need.push_back(NeedTok{t.dst, t.lit_off, t.src, t.ll, t.ml, 0, 0});
+        bytes += (uint64_t)t.ll + t.ml;
+        if (bytes > budget) return false;
         if (t.ml) {
           const uint64_t m0 = t.dst + t.ll;
           work.push_back({t.src, std::min(t.src + t.ml, m0)});
@@ -1363,6 +1391,7 @@ void closure(lz_dev* h, uint64_t off, uint64_t len, std::vector<NeedTok>& need) 
     }
   }
   std::sort(need.begin(), need.end(), [](const NeedTok& x, const NeedTok& y) { return x.dst < y.dst; });
+  return true;
 }
 
 // Index of the needed token containing output position x (it exists).
@@ -1391,13 +1420,25 @@ int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const u
     std::vector<std::vector<std::array<uint64_t, 5>>> by_lvl(1);  // dst, lit_off, lit_len, src, mlen
     std::vector<NeedTok> need;
     uint64_t base = 0;
-    for (uint64_t r = 0; r < count; ++r) {
+    // A closure costs host work per byte, a prefix decode runs on the device at
+    // HBM speed: closures are tried while they stay within a budget that grows
+    // with the prefix the ranges would need.
+    uint64_t end = 0;
+    for (uint64_t r = 0; r < count; ++r) end = std::max(end, off[r] + len[r]);
+    uint64_t budget = std::max<uint64_t>(kClosureMin, end / kClosureRatio);
+    for (uint64_t r = 0; r < count && !P->prefix; ++r) {
       P->range_len.push_back(len[r]);
       if (len[r] == 0) {
         P->range_src.push_back(base);
         continue;
       }
-      closure(h, off[r], len[r], need);
+      if (!closure(h, off[r], len[r], need, budget)) {
+        P->prefix = true;
+        break;
+      }
+      uint64_t spent = 0;
+      for (auto& t : need) spent += (uint64_t)t.ll + t.ml;
+      budget -= std::min(budget, spent);
       uint64_t acc = 0;
       for (auto& t : need) {
         t.scratch = base + acc;
@@ -1426,6 +1467,32 @@ int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const u
       P->range_src.push_back(need[j].scratch + (off[r] - need[j].dst));
       base += acc;
     }
+    if (P->prefix) {
+      // decode every token before `end` into the scratch data, then gather
+      by_lvl.assign(1, {});
+      P->range_len.assign(len, len + count);
+      P->range_src.assign(off, off + count);
+      P->prefix_end = end;
+      base = h->v.n;
+      // windows starting before `end` have all their matches before
+      // end + kWinSpan: their records come from the parse of those blocks
+      const uint64_t last_blk = end ? (std::min(h->v.n, end + kWinSpan) - 1) >> h->v.log2_bs : 0;
+      // parse segments are in block order: those of blocks <= last_blk come first
+      uint64_t lo = 0, hi = h->h_seg.size() / 8;
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi) / 2;
+        if ((h->h_seg[8 * mid + 7] & 0xFFFFFFFFull) <= last_blk) lo = mid + 1;
+        else hi = mid;
+      }
+      P->nseg = end ? lo : 0;
+      const size_t NL = h->lvl_start.size() ? h->lvl_start.size() - 1 : 0;
+      P->win_hi.assign(NL, 0);
+      for (size_t p = 0; p < NL; ++p) {
+        // windows of depth p whose first byte lies before `end`
+        auto b0 = h->h_wdst.begin() + h->lvl_start[p], b1 = h->h_wdst.begin() + h->lvl_start[p + 1];
+        P->win_hi[p] = (uint64_t)(std::lower_bound(b0, b1, end) - h->h_wdst.begin());
+      }
+    }
     P->data_bytes = base;
     P->lvl_piece.push_back(0);
     for (auto& L : by_lvl) {
@@ -1438,14 +1505,18 @@ int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const u
       }
       P->lvl_piece.push_back(P->p_dst.size());
     }
-    // gather pieces: one per range, reading the scratch data as "literals"
-    for (uint64_t r = 0; r < count; ++r) {
-      P->p_dst.push_back(0);  // output offsets are given at run time
-      P->p_lit_off.push_back(P->range_src[r]);
-      P->p_lit_len.push_back((uint32_t)0);
-      P->p_src.push_back(0);
-      P->p_mlen.push_back(0);
-    }
+    // gather pieces: every range in pieces of kGatherPiece bytes, reading the
+    // scratch data as "literals"; output offsets are given at run time
+    for (uint64_t r = 0; r < count; ++r)
+      for (uint64_t o = 0; o < len[r]; o += kGatherPiece) {
+        P->g_range.push_back(r);
+        P->g_off.push_back(o);
+        P->p_dst.push_back(0);
+        P->p_lit_off.push_back(P->range_src[r] + o);
+        P->p_lit_len.push_back((uint32_t)std::min<uint64_t>(kGatherPiece, len[r] - o));
+        P->p_src.push_back(0);
+        P->p_mlen.push_back(0);
+      }
     P->lvl_piece.push_back(P->p_dst.size());
   } catch (const std::bad_alloc&) {
     delete P;
@@ -1461,8 +1532,13 @@ int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const u
 }
 
 uint64_t lz_range_plan_scratch_bytes(const lz_range_plan* P) { return P ? P->scratch_bytes : 0; }
-uint64_t lz_range_plan_levels(const lz_range_plan* P) { return P && P->lvl_piece.size() > 2 ? P->lvl_piece.size() - 3 : 0; }
-uint64_t lz_range_plan_closure_bytes(const lz_range_plan* P) { return P ? P->data_bytes : 0; }
+uint64_t lz_range_plan_levels(const lz_range_plan* P) {
+  if (!P) return 0;
+  if (P->prefix) return P->win_hi.size();
+  return P->lvl_piece.size() > 2 ? P->lvl_piece.size() - 3 : 0;
+}
+uint64_t lz_range_plan_closure_bytes(const lz_range_plan* P) { return P ? (P->prefix ? 0 : P->data_bytes) : 0; }
+uint64_t lz_range_plan_prefix_bytes(const lz_range_plan* P) { return P && P->prefix ? P->prefix_end : 0; }
 void lz_range_plan_free(lz_range_plan* P) { delete P; }
 
 int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, const uint64_t* out_off,
@@ -1481,10 +1557,8 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
   const uint64_t np = P->p_dst.size();
   auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
   // gather pieces take the caller's output offsets
-  for (uint64_t r = 0; r < P->count; ++r) {
-    P->p_dst[P->lvl_piece[P->lvl_piece.size() - 2] + r] = out_off[r];
-    P->p_lit_len[P->lvl_piece[P->lvl_piece.size() - 2] + r] = (uint32_t)P->range_len[r];
-  }
+  const uint64_t g0 = P->lvl_piece[P->lvl_piece.size() - 2];
+  for (size_t i = 0; i < P->g_range.size(); ++i) P->p_dst[g0 + i] = out_off[P->g_range[i]] + P->g_off[i];
   if (!P->staging && hipHostMalloc((void**)&P->staging, P->staging_bytes, 0) != hipSuccess) {
     P->staging = nullptr;
     return lz::fail(LZ_E_NOMEM, "pinned staging allocation failed");
@@ -1506,6 +1580,28 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
   A.p_src = (const uint64_t*)(D + o_src);
   A.p_lit_len = (const uint32_t*)(D + o_llen);
   A.p_mlen = (const uint32_t*)(D + o_mlen);
+  if (P->prefix) {
+    // every token before the prefix end, decoded into the scratch data
+    KArgs A = base_args(h);
+    A.one = arc_desc(h, data, h->v.n);
+    A.nseg = P->nseg;
+    if (P->nseg) {
+      kfn_t kp = pick_kernel<kModeParse>(G, U);
+      hipLaunchKernelGGL(kp, dim3((unsigned)grid_for(P->nseg, resident_groups(kp, h->cu_count, G), G)), dim3(kWG), 0,
+                         s, A);
+      HIPCHK(hipGetLastError());
+    }
+    kfn_t kl = pick_kernel<kModeLevels>(G, U);
+    const uint64_t rl = resident_groups(kl, h->cu_count, G);
+    for (size_t p = 0; p < P->win_hi.size(); ++p) {
+      KArgs a = A;
+      a.lo = h->lvl_start[p];
+      a.hi = P->win_hi[p];
+      if (a.hi <= a.lo) continue;
+      hipLaunchKernelGGL(kl, dim3((unsigned)grid_for((a.hi - a.lo) * (64 / G), rl, G)), dim3(kWG), 0, s, a);
+      HIPCHK(hipGetLastError());
+    }
+  }
   kfn_t k = pick_kernel<kModePure>(G, U);
   const uint64_t res = resident_groups(k, h->cu_count, G);
   const size_t L = P->lvl_piece.size() - 1;  // levels incl. literal and gather

@@ -86,6 +86,7 @@ def lib():
             "lz_range_plan_scratch_bytes": (_u64, [_vp]),
             "lz_range_plan_levels": (_u64, [_vp]),
             "lz_range_plan_closure_bytes": (_u64, [_vp]),
+            "lz_range_plan_prefix_bytes": (_u64, [_vp]),
             "lz_range_plan_free": (None, [_vp]),
             "lz_range_run": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
             "lz_range_scratch_bytes": (ctypes.c_int, [_vp, _u64, _u64, _p64]),
@@ -383,6 +384,7 @@ class RangePlan:
         self.scratch_bytes = int(lib().lz_range_plan_scratch_bytes(p))
         self.levels = int(lib().lz_range_plan_levels(p))
         self.closure_bytes = int(lib().lz_range_plan_closure_bytes(p))
+        self.prefix_bytes = int(lib().lz_range_plan_prefix_bytes(p))
 
     def run(self, out, out_offs, scratch, G=64, unroll=2, stream=None):
         """Enqueues the plan; range i lands at out[out_offs[i]:+lens[i]]."""

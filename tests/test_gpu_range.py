@@ -91,11 +91,26 @@ def test_range_errors():
     assert bytes(got.cpu().numpy()) == bytes(x[49_990:])
 
 
-def test_range_closure_is_small_against_the_file():
-    """A 16 KiB seek decodes far less than the prefix before it."""
+def test_range_plan_modes():
+    """A seek whose closure is small is served from its closure; one whose
+    closure would exceed max(1 MiB, end / 256) decodes its prefix on the
+    device instead.  Both give the input's bytes."""
     dev = _dev()
+    z = synth.zipf_text(8 << 20, seed=5)
+    da = lz.DeviceArchive(lz.encode(z, 16, lz.TUNED_THR), device=dev)
+    p = da.range_plan([100], [4096])
+    assert p.prefix_bytes == 0 and 0 < p.closure_bytes < (1 << 20)
+    p.free()
+    da.close()
     x = synth.fastq(8 << 20, seed=5)
     da = lz.DeviceArchive(lz.encode(x, 16, lz.TUNED_THR), device=dev)
-    p = da.range_plan([6 << 20], [16 << 10])
-    assert p.closure_bytes < (1 << 20)
+    p = da.range_plan([6 << 20, 1 << 20], [16 << 10, 1 << 20])
+    assert p.prefix_bytes == (6 << 20) + (16 << 10) and p.closure_bytes == 0
+    out = torch.zeros((17 << 16) + (1 << 20), dtype=torch.uint8, device=dev)
+    scratch = torch.empty(p.scratch_bytes, dtype=torch.uint8, device=dev)
+    p.run(out, np.array([0, 16 << 10], np.uint64), scratch)
+    torch.cuda.synchronize()
+    assert bytes(out[:16 << 10].cpu().numpy()) == bytes(x[6 << 20:(6 << 20) + (16 << 10)])
+    assert bytes(out[16 << 10:(16 << 10) + (1 << 20)].cpu().numpy()) == bytes(x[1 << 20:2 << 20])
     p.free()
+    da.close()
