@@ -415,7 +415,8 @@ def run_serve(args, torch, lz):
     n = int(x.size)
     log("generated %d B in %.0fs" % (n, time.perf_counter() - t0))
     seg = (1 << 30) if n > (3 << 30) else 0
-    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain, segment=seg)
+    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain, segment=seg,
+                    progress=lambda d, t: log("encoded %d of %d input bytes" % (d, t)))
     log("encoded: %d B archive (ratio %.3f) in %.0fs" % (arc.size, n / arc.size, time.perf_counter() - t0))
     da = lz.DeviceArchive(arc, device=dev)
     log("opened on the device (%d depths)" % da.levels)

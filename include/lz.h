@@ -71,6 +71,10 @@ typedef struct lz_params {
   uint32_t n_threads;  /* encoder threads; 0 = hardware concurrency */
   uint64_t segment;    /* 0 = whole-prefix window; else sources stay inside
                           aligned segments of this many bytes (multiple of bs) */
+  /* optional: called on the calling thread after each segment is parsed with
+   * the input bytes done so far and the total; user is passed through */
+  void (*progress)(uint64_t done, uint64_t total, void* user);
+  void* progress_user;
 } lz_params;
 
 /* Fills the defaults: 64 KiB blocks, thresholds 6/8/10/12, bounds 4 KiB /

@@ -82,7 +82,7 @@ constexpr uint32_t kWinBytes = 2048;  // a match window holds at most this many 
 constexpr uint32_t kWinMatches = 64;  // ... and at most this many matches
 constexpr uint64_t kWinSpan = 1ull << 20;  // and its matches start within this many output bytes
 constexpr uint64_t kClosureMin = 1ull << 20;  // range closures of up to max(1 MiB, prefix / 256) bytes;
-constexpr uint64_t kClosureRatio = 256;       // beyond that the prefix is decoded instead
+constexpr uint64_t kClosureRatio = 4096;      // beyond that the prefix is decoded instead
 constexpr uint64_t kGatherPiece = 64ull << 10;  // ranges are gathered into the output in pieces of this size
 
 constexpr uint64_t kIdleTicks = 500000000ull;  // 5 s of the 100 MHz clock without progress
@@ -120,6 +120,7 @@ struct KArgs {
   // first match to skip, end byte of the last match (0 = its length)}
   const u32x4* items;
   const uint32_t* lvl_start;  // per depth: first window; n_levels + 1 entries
+  const uint32_t* lvl_hi;     // per depth: end of its windows to run (null = all of them)
   uint32_t* tickets;          // per level: windows taken (schedule 0)
   uint32_t* wdone;            // per level: windows finished (schedule 0)
   uint32_t* err;
@@ -341,7 +342,9 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
   // windows of a level (schedule 0)
   // a window holds up to 64 matches; a group of G lanes takes 64 / G parts of it
   constexpr uint32_t kParts = 64 / G;
-  auto level_windows = [&](uint32_t p) -> uint32_t { return (A.lvl_start[p + 1] - A.lvl_start[p]) * kParts; };
+  auto level_windows = [&](uint32_t p) -> uint32_t {
+    return ((A.lvl_hi ? A.lvl_hi[p] : A.lvl_start[p + 1]) - A.lvl_start[p]) * kParts;
+  };
 
   // work item state (replicated on the group's lanes)
   bool finished = false, have_item = false, started = true;
@@ -1191,7 +1194,7 @@ int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cf
       const uint64_t NL = h->lvl_start.size() - 1;
       std::vector<uint64_t> win(NL);
       for (uint64_t p = 0; p < NL; ++p) win[p] = h->lvl_start[p + 1] - h->lvl_start[p];
-      const uint64_t pt = (tail == kTailOff || out_cap > 0xFFFFFFFFull) ? NL : tail_start(win, tail);
+      const uint64_t pt = (tail == kTailOff) ? NL : tail_start(win, tail);
       for (uint64_t p = 0; p < pt; ++p) {
         KArgs a = A;
         a.lo = h->lvl_start[p];
@@ -1525,7 +1528,7 @@ int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const u
   // staging layout: dst | lit_off | src (u64) | lit_len | mlen (u32) | unit starts (u64, one unit per piece)
   const uint64_t np = P->p_dst.size();
   auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
-  P->staging_bytes = a256(8 * np) * 3 + a256(4 * np) * 2;
+  P->staging_bytes = a256(8 * np) * 3 + a256(4 * np) * 2 + a256(4 * P->win_hi.size());
   P->scratch_bytes = P->staging_bytes + a256(P->data_bytes + 16);
   *out = P;
   return 0;
@@ -1570,6 +1573,9 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
   const uint64_t o_src = o; memcpy(st + o, P->p_src.data(), 8 * np); o += a256(8 * np);
   const uint64_t o_llen = o; memcpy(st + o, P->p_lit_len.data(), 4 * np); o += a256(4 * np);
   const uint64_t o_mlen = o; memcpy(st + o, P->p_mlen.data(), 4 * np); o += a256(4 * np);
+  const uint64_t o_hi = o;
+  for (size_t p = 0; p < P->win_hi.size(); ++p) ((uint32_t*)(st + o))[p] = (uint32_t)P->win_hi[p];
+  o += a256(4 * P->win_hi.size());
   uint8_t* D = (uint8_t*)d_scratch;
   HIPCHK(hipMemcpyAsync(D, st, P->staging_bytes, hipMemcpyHostToDevice, s));
   uint8_t* data = D + P->staging_bytes;
@@ -1593,12 +1599,24 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
     }
     kfn_t kl = pick_kernel<kModeLevels>(G, U);
     const uint64_t rl = resident_groups(kl, h->cu_count, G);
-    for (size_t p = 0; p < P->win_hi.size(); ++p) {
+    const uint64_t NL = P->win_hi.size();
+    std::vector<uint64_t> cnt(NL);
+    for (uint64_t p = 0; p < NL; ++p) cnt[p] = P->win_hi[p] - h->lvl_start[p];
+    const uint64_t pt = tail_start(cnt, kTailWindows);
+    for (uint64_t p = 0; p < pt; ++p) {
       KArgs a = A;
       a.lo = h->lvl_start[p];
       a.hi = P->win_hi[p];
       if (a.hi <= a.lo) continue;
       hipLaunchKernelGGL(kl, dim3((unsigned)grid_for((a.hi - a.lo) * (64 / G), rl, G)), dim3(kWG), 0, s, a);
+      HIPCHK(hipGetLastError());
+    }
+    if (pt < NL) {  // the deepest depths of the prefix in one workgroup
+      KArgs a = A;
+      a.lo = pt;
+      a.hi = NL;
+      a.lvl_hi = (const uint32_t*)(D + o_hi);
+      hipLaunchKernelGGL(pick_tail(U, false), dim3(1), dim3(kWGTail), 0, s, a);
       HIPCHK(hipGetLastError());
     }
   }
@@ -1850,9 +1868,7 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
         const uint64_t res = resident_groups(k, cu, G);
         std::vector<uint64_t> win(nl);
         for (uint64_t p = 0; p < nl; ++p) win[p] = lvls[p + 1] - lvls[p];
-        bool small = true;  // the tail addresses outputs below 4 GiB
-        for (uint32_t i : g.arcs) small = small && out_cap[i] <= 0xFFFFFFFFull;
-        const uint64_t pt = (tail == kTailOff || !small) ? nl : tail_start(win, tail);
+        const uint64_t pt = (tail == kTailOff) ? nl : tail_start(win, tail);
         for (uint64_t p = 0; p < pt; ++p) {
           KArgs a = A;
           a.lo = lvls[p];

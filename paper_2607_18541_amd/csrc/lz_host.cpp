@@ -593,6 +593,7 @@ static int encode_impl(const uint8_t* in, uint64_t n, const lz_params* p, const 
         e.slo.resize(toks.size() * sizeof(BTok));
         memcpy(e.slo.data(), toks.data(), toks.size() * sizeof(BTok));
       });
+      if (p->progress) p->progress(s1, n, p->progress_user);
     }
   } catch (const std::bad_alloc&) {
     return fail(LZ_E_NOMEM, "encoder allocation failed");

@@ -33,9 +33,12 @@ class LzError(RuntimeError):
         self.rc = rc
 
 
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p)
+
+
 class Params(ctypes.Structure):
     _fields_ = [("log2_bs", _u32), ("thr", _u32 * 4), ("bound", _u64 * 3), ("max_chain", _u32),
-                ("n_threads", _u32), ("segment", _u64)]
+                ("n_threads", _u32), ("segment", _u64), ("progress", PROGRESS_FN), ("progress_user", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -160,10 +163,14 @@ def params(log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=
     return p
 
 
-def encode(x, log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0):
-    """Greedy parse with per-distance-class thresholds into a container."""
+def encode(x, log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0, progress=None):
+    """Greedy parse with per-distance-class thresholds into a container.
+    progress(done, total), if given, is called after each segment."""
     x = _u8(x)
     p = params(log2_bs, thr, bounds, max_chain, n_threads, segment)
+    if progress is not None:
+        cb = PROGRESS_FN(lambda d, t, u: progress(int(d), int(t)))
+        p.progress = cb
     pa = _vp()
     sz = _u64()
     rc = lib().lz_encode(x.ctypes.data, x.size, ctypes.byref(p), ctypes.byref(pa), ctypes.byref(sz))
