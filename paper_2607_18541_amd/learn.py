@@ -244,7 +244,10 @@ def evaluate(files, sel, log2_bs, torch, lam=1.0):
         rows.append({"size_learned": sl, "size_fixed": sf, "ms_learned": tl, "ms_fixed": tf,
                      "J": sl / sf + lam * tl / tf, "non_fixed_blocks": float(np.mean(k != FIXED))})
     J = float(np.mean([r["J"] for r in rows]))
-    return {"mean_J": J, "gain_vs_fixed": (1.0 + lam) - J, "files": rows}
+    return {"mean_J": J, "gain_vs_fixed": (1.0 + lam) - J, "files": rows,
+            "size_ratio": float(np.mean([r["size_learned"] / r["size_fixed"] for r in rows])),
+            "time_ratio": float(np.mean([r["ms_learned"] / r["ms_fixed"] for r in rows])),
+            "non_fixed_blocks": float(np.mean([r["non_fixed_blocks"] for r in rows]))}
 
 
 def run(n_files=100, blocks_per_file=100, log2_bs=16, epochs=50, seed=5, lam=1.0, out=None):
@@ -274,7 +277,9 @@ def run(n_files=100, blocks_per_file=100, log2_bs=16, epochs=50, seed=5, lam=1.0
     ev = evaluate(files[n_tr + n_va:], sel, log2_bs, torch, lam)
     res = {"files": n_files, "blocks_per_file": blocks_per_file, "log2_bs": log2_bs, "epochs": epochs,
            "loss_first": hist[0], "loss_last": hist[-1], "val_accuracy": acc, "test_mean_J": ev["mean_J"],
-           "fixed_J": 1.0 + lam, "test_gain": ev["gain_vs_fixed"], "time_model": M["time_model"],
+           "fixed_J": 1.0 + lam, "test_gain": ev["gain_vs_fixed"], "test_size_ratio": ev["size_ratio"],
+           "test_time_ratio": ev["time_ratio"], "test_non_fixed_blocks": ev["non_fixed_blocks"],
+           "time_model": M["time_model"],
            "label_hist": np.bincount(np.concatenate(M["labels"]), minlength=16).tolist(),
            "test_files": ev["files"], "seconds": time.time() - t0}
     if out:
