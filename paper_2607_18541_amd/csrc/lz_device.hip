@@ -304,6 +304,126 @@ __device__ __forceinline__ void compiler_barrier() { asm volatile("" ::: "memory
 
 __device__ __forceinline__ void mem_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
+// v with its bytes moved up by s (0..15) positions (v's byte b lands at b + s)
+__device__ __forceinline__ void shift_up(uint64_t lo, uint64_t hi, uint32_t s, uint64_t& rlo, uint64_t& rhi) {
+  const uint32_t b = 8u * (s & 7u);
+  const uint64_t carry = b ? (lo >> (64u - b)) : 0ull;
+  const uint64_t l1 = lo << b, h1 = (hi << b) | carry;
+  rlo = (s >= 8u) ? 0ull : l1;
+  rhi = (s >= 8u) ? l1 : h1;
+}
+
+// Literal bytes of G tokens written as the aligned 16-byte blocks of their
+// output span [sp0, sp1).  Every byte of the span is a literal of some run or
+// a match byte; match bytes receive arbitrary values here and are rewritten by
+// the match passes, so the literal stores are whole aligned blocks (only the two
+// end blocks, shared with neighbouring spans, are written byte-exact).
+// The literals of the G runs are consecutive in the literal stream, so one
+// 16-byte load covers a block: run j's bytes sit at their block position minus
+// the match bytes between the block's first run and run j.
+// Blocks per lane and pass of the span copy (the U loads of a lane are in
+// flight together; measured best at 4 on gfx950 for FASTQ-like literals).
+constexpr int kSpanUnroll = 4;
+
+template <int G, int U>
+__device__ __forceinline__ void parse_span(uint64_t sp0, uint64_t sp1, uint64_t l_dst, uint32_t l_len, uintptr_t l_src,
+                                           uintptr_t lit_lo, uintptr_t lit_hi, uintptr_t out_b, int gl, int gslot,
+                                           uint32_t* s_base, Desc* s_desc) {
+  // blocks are aligned in the address space; A0 is the first block's address
+  const uintptr_t ab0 = out_b + sp0, ab1 = out_b + sp1;
+  const uintptr_t A0 = ab0 & ~(uintptr_t)15;
+  const uint32_t C = (uint32_t)(((ab1 + 15u) >> 4) - (ab0 >> 4));
+  const uint32_t e0 = (uint32_t)(ab0 - A0), e1 = (uint32_t)(ab1 - A0);  // span, relative to A0
+  // run starts relative to A0 (nondecreasing over the group's lanes), lengths,
+  // and the literal address of each run's first byte
+  s_base[gslot + gl] = (uint32_t)(out_b + l_dst - A0);
+  s_desc[gslot + gl].a_len = l_len;
+  s_desc[gslot + gl].a_src = l_src;
+  compiler_barrier();
+  constexpr uint32_t kAny = 1u << 8, kSlow = 1u << 9;
+  // window address of a block whose first literal byte is in run k
+  auto window = [&](uint32_t A, uint32_t k) -> uintptr_t {
+    return s_desc[gslot + k].a_src + (uintptr_t)((int64_t)A - (int64_t)s_base[gslot + k]);
+  };
+  // blocks r..r + G * U: per block its first literal run (| kAny, kSlow), and its window loaded
+  auto issue = [&](uint32_t r, uint32_t (&f)[U], u32x4 (&v)[U]) {
+    if (r >= C) return;
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      const uint32_t A = 16u * (r + i * G + gl);
+      // the last run starting at or before the block (run 0 when none does)
+      uint32_t own = 0;
+#pragma unroll
+      for (int step = G / 2; step >= 1; step >>= 1)
+        if (s_base[gslot + own + step] <= A) own += step;
+      // the block's first literal byte: in run `own`, or a later run starting inside the block
+      uint32_t k = own;
+      for (;;) {
+        const uint32_t lk = s_desc[gslot + k].a_len;
+        const bool none = lk == 0 || s_base[gslot + k] + lk <= A;  // no literal at or after A
+        if (!none || k + 1 >= (uint32_t)G || s_base[gslot + k + 1] >= A + 16u) break;
+        ++k;
+      }
+      const uint32_t bk = s_base[gslot + k], lk = s_desc[gslot + k].a_len;
+      const bool any = (r + i * G + gl < C) && lk > 0 && bk < A + 16u && bk + lk > A;
+      const uintptr_t W = window(A, k);
+      const bool slow = any && (W < lit_lo || W + 16u > lit_hi);
+      f[i] = k | (any ? kAny : 0u) | (slow ? kSlow : 0u);
+      v[i] = *gptr<const u32x4_a1>((any && !slow) ? W : (uintptr_t)g_pad16);
+    }
+  };
+  auto finish = [&](uint32_t r, const uint32_t (&f)[U], u32x4 (&v)[U]) {
+    if (r >= C) return;
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      if (r + i * G + gl >= C) continue;
+      const uint32_t A = 16u * (r + i * G + gl);
+      const uint32_t k0 = f[i] & 0xFFu;
+      if (f[i] & kSlow) {
+        const uintptr_t W = window(A, k0);
+        const int lo = W < lit_lo ? (int)(lit_lo - W) : 0;
+        const int hi = W + 16u > lit_hi ? (int)(lit_hi - W) : 16;
+        v[i] = load_bytes(W, lo, hi);
+      }
+      uint64_t lo = (uint64_t)v[i].x | ((uint64_t)v[i].y << 32), hi = (uint64_t)v[i].z | ((uint64_t)v[i].w << 32);
+      if (f[i] & kAny) {
+        // later runs starting inside the block: their bytes from v, moved up
+        const uint64_t vlo = lo, vhi = hi;
+        const uint32_t bk = s_base[gslot + k0];
+        const uintptr_t sk = s_desc[gslot + k0].a_src;
+        for (uint32_t j = k0 + 1; j < (uint32_t)G && s_base[gslot + j] < A + 16u; ++j) {
+          const uint32_t bj = s_base[gslot + j];
+          if (s_desc[gslot + j].a_len == 0) continue;
+          const uint32_t st = bj - A;                                                // first block byte of run j
+          const uint32_t sh = (bj - bk) - (uint32_t)(s_desc[gslot + j].a_src - sk);  // match bytes skipped
+          uint64_t rlo, rhi;
+          shift_up(vlo, vhi, sh, rlo, rhi);
+          const uint64_t mlo = st >= 8u ? 0ull : (~0ull << (8u * st));
+          const uint64_t mhi = st >= 8u ? (~0ull << (8u * (st - 8u))) : ~0ull;
+          lo = (lo & ~mlo) | (rlo & mlo);
+          hi = (hi & ~mhi) | (rhi & mhi);
+        }
+      }
+      const u32x4 o = u32x4{(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
+      // bytes of the span in this block
+      const uint32_t b0 = e0 > A ? e0 - A : 0u;
+      const uint32_t b1 = min(16u, e1 - A);
+      const uintptr_t a = A0 + A;
+      if (b1 - b0 == 16u)
+        *gptr<u32x4>(a) = o;  // a is 16-byte aligned
+      else
+        store_seg(a + b0, o, (int)b0, (int)(b1 - b0));
+    }
+  };
+  uint32_t f[U];
+  u32x4 v[U];
+  for (uint32_t r = 0; r < C; r += G * U) {
+    issue(r, f, v);
+    finish(r, f, v);
+  }
+  compiler_barrier();
+}
+
 template <int G, int U, int MODE, bool BATCH>
 __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs A) {
   static_assert(G == 8 || G == 16 || G == 32 || G == 64, "G");
@@ -358,6 +478,7 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
     if (blockIdx.x == 0 && threadIdx.x == 0) *A.err = 0u;
   }
   uint64_t t_next = 0, t_end = 0, blk_t_end = 0, pos = 0, bend = 0, litc = 0, xc = 0, yc = 0;
+  uint64_t sp0 = 0, sp1 = 0;  // parse: output span of the current G tokens
   // this lane's buffered token
   uint64_t l_dst = 0, l_src = 0, m_dst = 0, m_src = 0;
   uint32_t l_len = 0, m_len = 0, m_done = 0;
@@ -559,7 +680,10 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
             xc += tot16;
             yc += tot32;
             litc += lit_tot;
+            sp0 = pos;
             pos += span_tot;
+            // the span ends at the block's end when it holds the block's last token
+            sp1 = (min(t_next + G, t_end) == blk_t_end) ? bend : pos;
             // record the match in plan order; only literal runs are copied here
             if (valid && mlen > 0) {
               const uint64_t md = tdst + lit_len;
@@ -589,9 +713,15 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
           const uint64_t cnt = min((uint64_t)G, t_end - t_next);
           t_next += cnt;
           m_done = m_done_init;
-          l_pend = l_len > 0;
+          l_pend = (MODE == kModeParse) ? (sp1 > sp0) : (l_len > 0);
           progressed = true;
         }
+      } else if (MODE == kModeParse) {
+        // ------------------------------------------------ the span's aligned 16-byte blocks
+        parse_span<G, kSpanUnroll>(sp0, sp1, l_dst, l_len, (uintptr_t)D.lit + l_src, D.lit_lo, D.lit_hi, out_b, gl, gslot,
+                         s_base, s_desc);
+        l_pend = false;
+        progressed = true;
       } else {
         // ------------------------------------------------ one pass over every pending segment
         // Matches of one level never read each other's output, so every lane

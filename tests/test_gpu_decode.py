@@ -232,3 +232,23 @@ def test_stages_and_tail_settings_agree():
         assert torch.equal(got, exp), tail
         assert bool((out[da.n:] == 0x3C).all().item())
     da.close()
+
+
+@pytest.mark.parametrize("off", [1, 7, 8, 15])
+def test_unaligned_output_address(off):
+    """Output views at every class of misalignment: literal blocks are aligned
+    in the address space, so the span ends move; nothing outside [off, off+n)."""
+    dev = _dev()
+    x = synth.fastq(300_000, seed=off)
+    arc = lz.encode(x, 14, lz.TUNED_THR)
+    da = lz.DeviceArchive(arc, device=dev)
+    exp_t = torch.from_numpy(x).to(dev)
+    for G, U, S in [(64, 2, 1), (16, 4, 0), (32, 1, 1)]:
+        print(f"[unaligned off={off}] G={G} U={U} sched={S}", flush=True)
+        buf = torch.full((da.n + 64,), 0x5A, dtype=torch.uint8, device=dev)
+        view = buf[off:off + da.n]
+        got = da.decode(view, G=G, unroll=U, schedule=S)
+        torch.cuda.synchronize()
+        assert torch.equal(got, exp_t)
+        assert bool((buf[:off] == 0x5A).all().item()) and bool((buf[off + da.n:] == 0x5A).all().item())
+    da.close()
