@@ -164,6 +164,43 @@ def cpu_oracle_time(arc, n, min_s=10.0):
     return total / reps, reps, out
 
 
+def cpu_levels_time(arc, x, min_s=3.0):
+    """The level-parallel CPU decode (all host cores; tokens and depths
+    prepared outside the timer, as the device plan is), repeated for at least
+    min_s seconds; checked equal to the input."""
+    import oracle
+    prep = oracle.levels_prepare(arc)
+    out = np.zeros(prep["n"], dtype=np.uint8)
+    reps, total, threads = 0, 0.0, 1
+    while total < min_s:
+        t0 = time.perf_counter()
+        threads = oracle.decode_levels_omp(prep, out)
+        total += time.perf_counter() - t0
+        reps += 1
+    if not np.array_equal(out, x):
+        raise SystemExit("level-parallel CPU decode differs from the input")
+    return total / reps, reps, threads, prep["max_depth"]
+
+
+def copy_ceiling(torch, n, steps):
+    """Device-to-device copy of n bytes (reads n, writes n): the plain streaming
+    ceiling the decode's algorithmic rate is also set against."""
+    a = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        b.copy_(a)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n / (ms * 1e-3) / 1e9
+
+
 def achieved_all(t):
     return t["alg_bytes"] / (t["mean_ms"] * 1e-3) / 1e9
 
@@ -228,6 +265,8 @@ def run_fastq(args, torch, lz):
     else:
         dom, dom_alg, dom_ms = kmatch, match_alg, t["match_ms"]
     achieved = dom_alg / (dom_ms * 1e-3) / 1e9
+    ceiling = copy_ceiling(torch, n, max(args.steps, 5))
+    log("streaming copy ceiling: %.1f GB/s (read + write)" % ceiling)
     line = {
         "metric": "match-phase decode GB/s (device-resident) + ratio, 6/8/10/12 vs 12/16/24/32",
         "value": round(t["gbps"], 3),
@@ -261,6 +300,7 @@ def run_fastq(args, torch, lz):
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
             "kernel": " + ".join(dom), "alg_bytes_per_decode": dom_alg, "ms_per_decode": round(dom_ms, 4),
+            "copy_ceiling": round(ceiling, 1), "frac_of_copy": round(achieved / ceiling, 4),
         },
         "stages": {
             "parse": {"kernel": kparse[0], "ms": round(t["parse_ms"], 4), "alg_bytes": parse_alg,
@@ -277,6 +317,12 @@ def run_fastq(args, torch, lz):
         line["cpu_baseline"] = {"value": round(n / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
                                 "sample": "whole 12/16/24/32 archive (%d output bytes), sequential decode incl. "
                                           "validation, mean of %d runs" % (n, reps)}
+        log("timing the level-parallel CPU decode")
+        dt, reps, threads, depth = cpu_levels_time(t["arc"], x)
+        line["cpu_parallel"] = {"value": round(n / dt / 1e9, 4), "unit": "GB/s", "cores": threads,
+                                "kind": "oracle tokens, depth-parallel (OpenMP)",
+                                "sample": "whole 12/16/24/32 archive, %d depths, tokens and depths prepared "
+                                          "outside the timer, mean of %d runs" % (depth, reps)}
     return line
 
 

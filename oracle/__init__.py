@@ -67,6 +67,10 @@ def lib():
         L.or_entropy_size.argtypes = [_vp, _u64, ctypes.POINTER(ctypes.c_double), _vp]
         L.or_purecopy.restype = None
         L.or_purecopy.argtypes = [_u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.or_lit_stream.restype = ctypes.c_int
+        L.or_lit_stream.argtypes = [_vp, _u64, _p64, _p64]
+        L.or_decode_levels_omp.restype = ctypes.c_int
+        L.or_decode_levels_omp.argtypes = [_u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _vp]
         L.or_exec_tokens.restype = ctypes.c_int
         L.or_exec_tokens.argtypes = [_u64, _u64, _vp, _vp, _vp, _vp, _u64, _vp]
         _LIB = L
@@ -189,6 +193,36 @@ def levels(arc):
     if rc:
         raise OracleError(rc, "levels")
     return lv[:T], int(mx.value)
+
+
+def levels_prepare(arc):
+    """Inputs of the level-parallel CPU decode: the tokens, the literal
+    stream, and the token indices grouped by dependency depth."""
+    a = _u8(arc)
+    inf = info(a)
+    tk = tokens(a)
+    lv, mx = levels(a)
+    order = np.argsort(lv, kind="stable").astype(np.uint64)
+    start = np.zeros(mx + 2, dtype=np.uint64)
+    start[1:] = np.cumsum(np.bincount(lv, minlength=mx + 1))
+    off, nl = _u64(), _u64()
+    rc = lib().or_lit_stream(a.ctypes.data, a.size, ctypes.byref(off), ctypes.byref(nl))
+    if rc:
+        raise OracleError(rc, "lit_stream")
+    lit = np.zeros(max(nl.value, 1), dtype=np.uint8)
+    lit[:nl.value] = a[off.value:off.value + nl.value]
+    return {"n": inf["n"], "tok": tk, "lit": lit, "order": order, "start": start, "max_depth": mx}
+
+
+def decode_levels_omp(prep, out):
+    """Level-parallel decode of prepared tokens into out (uint8[n]) on all
+    host cores (OMP_NUM_THREADS); returns the number of threads used."""
+    tk = prep["tok"]
+    T = len(tk["dst"])
+    return int(lib().or_decode_levels_omp(T, tk["dst"].ctypes.data, tk["lit_len"].ctypes.data,
+                                          tk["lit_off"].ctypes.data, tk["mlen"].ctypes.data, tk["src"].ctypes.data,
+                                          prep["lit"].ctypes.data, prep["order"].ctypes.data,
+                                          prep["start"].ctypes.data, prep["max_depth"], out.ctypes.data))
 
 
 def entropy_size(arc):

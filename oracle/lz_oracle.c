@@ -439,6 +439,16 @@ static int open_view(const uint8_t* a, uint64_t size, view_t* v) {
   return OR_OK;
 }
 
+/* Offset and length of the literal stream inside a valid archive. */
+int or_lit_stream(const uint8_t* arc, uint64_t size, uint64_t* off, uint64_t* n_lit) {
+  view_t v;
+  int rc = open_view(arc, size, &v);
+  if (rc) return rc;
+  *off = (uint64_t)(v.lit - arc);
+  *n_lit = v.n_lit;
+  return OR_OK;
+}
+
 /* Walks every token of every block, checking the container rules; calls
  * `visit` (if given) with the decoded token.  Returns 0 or OR_E_CORRUPT. */
 typedef void (*visit_fn)(void* ctx, uint64_t block, uint64_t t, uint64_t dst, uint64_t lit_len,

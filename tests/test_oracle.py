@@ -311,6 +311,24 @@ def test_depth_replay_equals_decode():
     assert np.array_equal(replay_by_depth(arc, lv), oracle.exec_tokens(n, ll, ml, sr, lit))
 
 
+def test_levels_omp_decode_equals_sequential():
+    """The level-parallel CPU baseline (every depth one parallel loop) gives the
+    sequential decode, with self-overlapping matches and deep chains."""
+    cases = []
+    x = synth.zipf_text(20_000, seed=6)
+    ll, ml, sr, lit = oracle.encode(x, 10, (4, 6, 8, 10), (256, 1024, 4096))
+    cases.append(oracle.write_archive(x.size, 10, ll, ml, sr, lit))
+    n = 200_000
+    ll, ml, sr, lit = synth.geo_tokens(n, 32, seed=10, lit_prefix=512, min_back=1)
+    cases.append(oracle.write_archive(n, 12, ll, ml, sr, lit))
+    for arc in cases:
+        prep = oracle.levels_prepare(arc)
+        assert prep["max_depth"] >= 2
+        out = np.zeros(prep["n"], np.uint8)
+        assert oracle.decode_levels_omp(prep, out) >= 1
+        assert np.array_equal(out, oracle.decode(arc))
+
+
 def test_depth_hand_built():
     """Literals 'abcd'; A copies [0,4) -> depth 1; B copies A's bytes -> 2;
     C copies literals again -> 1; D reads B and C -> 3; E overlaps itself
