@@ -479,6 +479,7 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
   }
   uint64_t t_next = 0, t_end = 0, blk_t_end = 0, pos = 0, bend = 0, litc = 0, xc = 0, yc = 0;
   uint64_t sp0 = 0, sp1 = 0;  // parse: output span of the current G tokens
+  bool span_mode = false;     // parse: the span is written whole (dense literals)
   // this lane's buffered token
   uint64_t l_dst = 0, l_src = 0, m_dst = 0, m_src = 0;
   uint32_t l_len = 0, m_len = 0, m_done = 0;
@@ -684,6 +685,9 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
             pos += span_tot;
             // the span ends at the block's end when it holds the block's last token
             sp1 = (min(t_next + G, t_end) == blk_t_end) ? bend : pos;
+            // whole-span blocks pay when literals fill a good part of the span;
+            // sparse literal runs are copied run by run
+            span_mode = 4 * lit_tot >= sp1 - sp0;
             // record the match in plan order; only literal runs are copied here
             if (valid && mlen > 0) {
               const uint64_t md = tdst + lit_len;
@@ -713,10 +717,10 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
           const uint64_t cnt = min((uint64_t)G, t_end - t_next);
           t_next += cnt;
           m_done = m_done_init;
-          l_pend = (MODE == kModeParse) ? (sp1 > sp0) : (l_len > 0);
+          l_pend = (MODE == kModeParse && span_mode) ? (sp1 > sp0) : (l_len > 0);
           progressed = true;
         }
-      } else if (MODE == kModeParse) {
+      } else if (MODE == kModeParse && span_mode) {
         // ------------------------------------------------ the span's aligned 16-byte blocks
         parse_span<G, kSpanUnroll>(sp0, sp1, l_dst, l_len, (uintptr_t)D.lit + l_src, D.lit_lo, D.lit_hi, out_b, gl, gslot,
                          s_base, s_desc);
