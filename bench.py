@@ -606,12 +606,78 @@ def run_sweep(args, torch, lz):
             "best_frac_m_ge_256": best_frac, "rows": rows}
 
 
+# distance classes named in Sec. 4.2 (d < 128, < 16384, < 2 Mi, else)
+PAPER_BANDS = (128, 16384, 2097152)
+
+
+def run_ablate(args, torch, lz):
+    """Threshold and distance-band variants and schedule mechanisms on the
+    FASTQ-like workload: the tuple the paper rejects (16/24/32/48), the paper's
+    own distance bands with both headline tuples, and, on 12/16/24/32, the
+    decode without the one-workgroup tail, with G = 32, and with schedule 0."""
+    import synth
+    dev = torch.device("cuda:0")
+    x = synth.fastq(args.size, seed=3)
+    n = int(x.size)
+    xt = torch.from_numpy(x).to(dev)
+    rows = []
+    variants = [("6/8/10/12", lz.BASE_THR, lz.BOUNDS_CFG, "cfg"), ("12/16/24/32", lz.TUNED_THR, lz.BOUNDS_CFG, "cfg"),
+                ("16/24/32/48", (16, 24, 32, 48), lz.BOUNDS_CFG, "cfg"),
+                ("6/8/10/12", lz.BASE_THR, PAPER_BANDS, "paper"), ("12/16/24/32", lz.TUNED_THR, PAPER_BANDS, "paper")]
+    tuned_gbps = None
+    for name, thr, bounds, bname in variants:
+        log("encoding %s, %s bands" % (name, bname))
+        arc = lz.encode(x, args.log2_bs, thr, bounds, max_chain=args.max_chain)
+        info = lz.archive_info(arc)
+        ent, _ = lz.entropy_size(arc)
+        da = lz.DeviceArchive(arc, device=dev)
+        out = torch.empty(n, dtype=torch.uint8, device=dev)
+        mechs = [("G64 U2 schedule 1", 64, 2, 1, 0)]
+        if name == "12/16/24/32" and bname == "cfg":
+            mechs += [("no tail", 64, 2, 1, lz.TAIL_OFF), ("G32", 32, 2, 1, 0), ("schedule 0", 64, 2, 0, 0)]
+        for mname, G, U, S, T in mechs:
+            da.decode(out, G=G, unroll=U, schedule=S, tail=T)
+            torch.cuda.synchronize()
+            if not bool(torch.equal(out, xt)):
+                raise SystemExit("ablation %s %s %s: decode differs from the input" % (name, bname, mname))
+            steps = max(3, args.steps // (4 if S == 0 else 1))
+            st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(steps):
+                da.decode_async(out, G=G, unroll=U, schedule=S, tail=T)
+            e1.record(st)
+            e1.synchronize()
+            da.check()
+            ms = e0.elapsed_time(e1) / steps
+            row = {"thr": name, "bands": bname, "mechanism": mname, "ms": round(ms, 4),
+                   "gbps": round(n / ms / 1e6, 2), "depths": da.levels, "ratio_raw": round(n / arc.size, 4),
+                   "ratio_entropy": round(n / ent, 4), "mean_match": round(info["mean_match"], 2),
+                   "coverage": round(info["coverage"], 4)}
+            log(json.dumps(row))
+            rows.append(row)
+            if name == "12/16/24/32" and bname == "cfg" and mname.startswith("G64"):
+                tuned_gbps = row["gbps"]
+        da.close()
+        del out
+        torch.cuda.empty_cache()
+    return {
+        "metric": "decode GB/s and ratio under threshold, band and schedule variants (FASTQ-like)",
+        "value": tuned_gbps, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "FASTQ-like reads %d B, 64 KiB blocks; bands cfg = 4 Ki/64 Ki/1 Mi, "
+                               "paper = 128/16 Ki/2 Mi" % n},
+        "rows": rows,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fastq", choices=["fastq", "sweep", "batch", "serve"])
+    ap.add_argument("--workload", default="fastq", choices=["fastq", "sweep", "batch", "serve", "ablate"])
     ap.add_argument("--count", type=int, default=4096, help="batch: archives")
     ap.add_argument("--requests", type=int, default=300, help="serve: requests")
     ap.add_argument("--load", default="1,4,16", help="serve: offered rate / one-at-a-time rate (comma list)")
@@ -654,6 +720,8 @@ def main():
         line = run_batch(args, torch, lz)
     elif args.workload == "serve":
         line = run_serve(args, torch, lz)
+    elif args.workload == "ablate":
+        line = run_ablate(args, torch, lz)
     else:
         line = run_fastq(args, torch, lz)
     print(json.dumps(line), flush=True)
