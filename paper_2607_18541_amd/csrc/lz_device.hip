@@ -322,8 +322,9 @@ __device__ __forceinline__ void shift_up(uint64_t lo, uint64_t hi, uint32_t s, u
 // 16-byte load covers a block: run j's bytes sit at their block position minus
 // the match bytes between the block's first run and run j.
 // Blocks per lane and pass of the span copy (the U loads of a lane are in
-// flight together; measured best at 4 on gfx950 for FASTQ-like literals).
-constexpr int kSpanUnroll = 4;
+// flight together; measured best at 3 on gfx950 for FASTQ-like literals:
+// 2 and 4 are 5 % slower, the latter at occupancy 4).
+constexpr int kSpanUnroll = 3;
 
 template <int G, int U>
 __device__ __forceinline__ void parse_span(uint64_t sp0, uint64_t sp1, uint64_t l_dst, uint32_t l_len, uintptr_t l_src,
@@ -341,61 +342,80 @@ __device__ __forceinline__ void parse_span(uint64_t sp0, uint64_t sp1, uint64_t 
   s_desc[gslot + gl].a_src = l_src;
   compiler_barrier();
   constexpr uint32_t kAny = 1u << 8, kSlow = 1u << 9;
-  // window address of a block whose first literal byte is in run k
-  auto window = [&](uint32_t A, uint32_t k) -> uintptr_t {
-    return s_desc[gslot + k].a_src + (uintptr_t)((int64_t)A - (int64_t)s_base[gslot + k]);
-  };
-  // blocks r..r + G * U: per block its first literal run (| kAny, kSlow), and its window loaded
+  // The U blocks of a lane advance together, so their LDS reads overlap.
+  // Blocks r..r + G * U: per block its first literal run (| kAny, kSlow), and its window loaded.
   auto issue = [&](uint32_t r, uint32_t (&f)[U], u32x4 (&v)[U]) {
     if (r >= C) return;
+    uint32_t A[U], k[U], bk[U], lk[U];
 #pragma unroll
     for (int i = 0; i < U; ++i) {
-      const uint32_t A = 16u * (r + i * G + gl);
-      // the last run starting at or before the block (run 0 when none does)
-      uint32_t own = 0;
+      A[i] = 16u * (r + i * G + gl);
+      k[i] = 0;
+    }
+    // the last run starting at or before the block (run 0 when none does)
 #pragma unroll
-      for (int step = G / 2; step >= 1; step >>= 1)
-        if (s_base[gslot + own + step] <= A) own += step;
-      // the block's first literal byte: in run `own`, or a later run starting inside the block
-      uint32_t k = own;
-      for (;;) {
-        const uint32_t lk = s_desc[gslot + k].a_len;
-        const bool none = lk == 0 || s_base[gslot + k] + lk <= A;  // no literal at or after A
-        if (!none || k + 1 >= (uint32_t)G || s_base[gslot + k + 1] >= A + 16u) break;
-        ++k;
+    for (int step = G / 2; step >= 1; step >>= 1) {
+#pragma unroll
+      for (int i = 0; i < U; ++i)
+        if (s_base[gslot + k[i] + step] <= A[i]) k[i] += step;
+    }
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      bk[i] = s_base[gslot + k[i]];
+      lk[i] = s_desc[gslot + k[i]].a_len;
+    }
+    // the block's first literal byte: in run k, or a later run starting inside the block
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      while ((lk[i] == 0 || bk[i] + lk[i] <= A[i]) && k[i] + 1 < (uint32_t)G) {
+        const uint32_t bn = s_base[gslot + k[i] + 1];
+        if (bn >= A[i] + 16u) break;
+        ++k[i];
+        bk[i] = bn;
+        lk[i] = s_desc[gslot + k[i]].a_len;
       }
-      const uint32_t bk = s_base[gslot + k], lk = s_desc[gslot + k].a_len;
-      const bool any = (r + i * G + gl < C) && lk > 0 && bk < A + 16u && bk + lk > A;
-      const uintptr_t W = window(A, k);
+    }
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      const bool any = (r + i * G + gl < C) && lk[i] > 0 && bk[i] < A[i] + 16u && bk[i] + lk[i] > A[i];
+      const uintptr_t W = s_desc[gslot + k[i]].a_src + (uintptr_t)((int64_t)A[i] - (int64_t)bk[i]);
       const bool slow = any && (W < lit_lo || W + 16u > lit_hi);
-      f[i] = k | (any ? kAny : 0u) | (slow ? kSlow : 0u);
-      v[i] = *gptr<const u32x4_a1>((any && !slow) ? W : (uintptr_t)g_pad16);
+      f[i] = k[i] | (any ? kAny : 0u) | (slow ? kSlow : 0u);
+      // lanes without a window read the first 16 bytes of the readable range
+      v[i] = *gptr<const u32x4_a1>((any && !slow) ? W : lit_lo);
     }
   };
   auto finish = [&](uint32_t r, const uint32_t (&f)[U], u32x4 (&v)[U]) {
     if (r >= C) return;
+    uint32_t bk[U], bn[U];
+    uintptr_t sk[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      const uint32_t k0 = f[i] & 0xFFu;
+      bk[i] = s_base[gslot + k0];
+      sk[i] = s_desc[gslot + k0].a_src;
+      bn[i] = (k0 + 1 < (uint32_t)G) ? s_base[gslot + k0 + 1] : 0xFFFFFFFFu;
+    }
 #pragma unroll
     for (int i = 0; i < U; ++i) {
       if (r + i * G + gl >= C) continue;
       const uint32_t A = 16u * (r + i * G + gl);
       const uint32_t k0 = f[i] & 0xFFu;
       if (f[i] & kSlow) {
-        const uintptr_t W = window(A, k0);
+        const uintptr_t W = sk[i] + (uintptr_t)((int64_t)A - (int64_t)bk[i]);
         const int lo = W < lit_lo ? (int)(lit_lo - W) : 0;
         const int hi = W + 16u > lit_hi ? (int)(lit_hi - W) : 16;
         v[i] = load_bytes(W, lo, hi);
       }
       uint64_t lo = (uint64_t)v[i].x | ((uint64_t)v[i].y << 32), hi = (uint64_t)v[i].z | ((uint64_t)v[i].w << 32);
-      if (f[i] & kAny) {
+      if ((f[i] & kAny) && bn[i] < A + 16u) {
         // later runs starting inside the block: their bytes from v, moved up
         const uint64_t vlo = lo, vhi = hi;
-        const uint32_t bk = s_base[gslot + k0];
-        const uintptr_t sk = s_desc[gslot + k0].a_src;
         for (uint32_t j = k0 + 1; j < (uint32_t)G && s_base[gslot + j] < A + 16u; ++j) {
           const uint32_t bj = s_base[gslot + j];
           if (s_desc[gslot + j].a_len == 0) continue;
-          const uint32_t st = bj - A;                                                // first block byte of run j
-          const uint32_t sh = (bj - bk) - (uint32_t)(s_desc[gslot + j].a_src - sk);  // match bytes skipped
+          const uint32_t st = bj - A;                                                    // first block byte of run j
+          const uint32_t sh = (bj - bk[i]) - (uint32_t)(s_desc[gslot + j].a_src - sk[i]);  // match bytes skipped
           uint64_t rlo, rhi;
           shift_up(vlo, vhi, sh, rlo, rhi);
           const uint64_t mlo = st >= 8u ? 0ull : (~0ull << (8u * st));
