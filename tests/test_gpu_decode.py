@@ -252,3 +252,21 @@ def test_unaligned_output_address(off):
         assert torch.equal(got, exp_t)
         assert bool((buf[:off] == 0x5A).all().item()) and bool((buf[off + da.n:] == 0x5A).all().item())
     da.close()
+
+
+def test_dense_short_runs_many_per_block():
+    """Literal runs and matches of 1-3 bytes (literals about half the bytes):
+    the whole-span parse path with up to eight runs inside one 16-byte block,
+    and near sources (overlapping matches)."""
+    rng = np.random.default_rng(7)
+    toks, lits, pos = [(64, 0, 0)], list(rng.integers(0, 256, 64)), 64
+    while pos < 300_000:
+        L = int(rng.integers(1, 4))
+        lits += list(rng.integers(0, 256, L))
+        pos += L
+        M = int(rng.integers(1, 4))
+        back = int(rng.integers(1, min(pos, 300) + 1))
+        toks.append((L, M, pos - back))
+        pos += M
+    arc, exp = _tokens_to_arc(pos, toks, lits, 14)
+    _check(arc, exp, [(64, 2, 1), (64, 1, 0), (32, 4, 1), (8, 2, 1)], "dense-short")
