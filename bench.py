@@ -606,6 +606,64 @@ def run_sweep(args, torch, lz):
             "best_frac_m_ge_256": best_frac, "rows": rows}
 
 
+def run_seek(args, torch, lz):
+    """Latency of one range decode (a seek) on the device-resident
+    12/16/24/32 FASTQ-like archive, by offset and length: host plan time,
+    device time (events on the launching stream) and their sum, with the plan
+    mode (token closure, or a device prefix decode when the closure exceeds
+    its budget)."""
+    import synth
+    dev = torch.device("cuda:0")
+    x = synth.fastq(args.size, seed=3)
+    n = int(x.size)
+    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain)
+    da = lz.DeviceArchive(arc, device=dev)
+    rows = []
+    st = torch.cuda.current_stream()
+    for length in (16384, 1 << 20):
+        for frac in (0.0001, 0.001, 0.01, 0.1, 0.5, 0.99):
+            off = min(int(frac * n), n - length)
+            best = None
+            for rep in range(args.steps):
+                t0 = time.perf_counter()
+                plan = da.range_plan([off], [length])
+                t_plan = time.perf_counter() - t0
+                out = torch.empty(length, dtype=torch.uint8, device=dev)
+                scratch = torch.empty(max(plan.scratch_bytes, 1), dtype=torch.uint8, device=dev)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                t1 = time.perf_counter()
+                e0.record(st)
+                plan.run(out, [0], scratch)
+                e1.record(st)
+                e1.synchronize()
+                t_run = time.perf_counter() - t1
+                dev_ms = e0.elapsed_time(e1)
+                if rep == 0 and not np.array_equal(out.cpu().numpy(), x[off:off + length]):
+                    raise SystemExit("seek off=%d len=%d differs from the input" % (off, length))
+                row = {"len": length, "off": off, "frac": frac, "plan_ms": round(t_plan * 1e3, 3),
+                       "device_ms": round(dev_ms, 3), "total_ms": round((t_plan + t_run) * 1e3, 3),
+                       "mode": "prefix" if plan.prefix_bytes else "closure",
+                       "closure_bytes": plan.closure_bytes, "prefix_bytes": plan.prefix_bytes,
+                       "depths": plan.levels}
+                if best is None or row["total_ms"] < best["total_ms"]:
+                    best = row
+                plan.free()
+                del scratch, out
+            log(json.dumps(best))
+            rows.append(best)
+    small = [r["total_ms"] for r in rows if r["len"] == 16384]
+    return {
+        "metric": "range seek latency, 16 KiB (device-resident, FASTQ-like)",
+        "value": round(float(np.median(small)), 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "FASTQ-like reads %d B, 12/16/24/32, 64 KiB blocks; best of %d seeks per point"
+                               % (n, args.steps)},
+        "rows": rows,
+    }
+
+
 # distance classes named in Sec. 4.2 (d < 128, < 16384, < 2 Mi, else)
 PAPER_BANDS = (128, 16384, 2097152)
 
@@ -677,7 +735,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fastq", choices=["fastq", "sweep", "batch", "serve", "ablate"])
+    ap.add_argument("--workload", default="fastq", choices=["fastq", "sweep", "batch", "serve", "ablate", "seek"])
     ap.add_argument("--count", type=int, default=4096, help="batch: archives")
     ap.add_argument("--requests", type=int, default=300, help="serve: requests")
     ap.add_argument("--load", default="1,4,16", help="serve: offered rate / one-at-a-time rate (comma list)")
@@ -722,6 +780,8 @@ def main():
         line = run_serve(args, torch, lz)
     elif args.workload == "ablate":
         line = run_ablate(args, torch, lz)
+    elif args.workload == "seek":
+        line = run_seek(args, torch, lz)
     else:
         line = run_fastq(args, torch, lz)
     print(json.dumps(line), flush=True)
