@@ -78,10 +78,10 @@ constexpr int kModeParse = 3;   // parse blocks, copy literals, fill the match t
 constexpr int kModeTail = 4;    // the last, small levels in one workgroup, a barrier between levels
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint64_t kSegTok = 256;    // tokens per parse segment
-constexpr uint32_t kWinBytes = 2048;  // a match window holds at most this many bytes ...
+constexpr uint32_t kWinBytes = 3072;  // a match window holds at most this many bytes ...
 constexpr uint32_t kWinMatches = 64;  // ... and at most this many matches
 constexpr uint64_t kWinSpan = 1ull << 20;  // and its matches start within this many output bytes
-constexpr uint64_t kClosureMin = 1ull << 20;  // range closures of up to max(1 MiB, prefix / 256) bytes;
+constexpr uint64_t kClosureMin = 1ull << 20;  // range closures of up to max(1 MiB, prefix / 4096) bytes;
 constexpr uint64_t kClosureRatio = 4096;      // beyond that the prefix is decoded instead
 constexpr uint64_t kGatherPiece = 64ull << 10;  // ranges are gathered into the output in pieces of this size
 
