@@ -146,14 +146,15 @@ const char* lz_last_error(void);
 typedef struct lz_dev lz_dev; /* opaque handle of a device-resident archive */
 
 /* Decode configuration.  A decode is a parse launch (one group of G lanes per
- * 256-token segment of a block: token headers, literal runs, match table)
+ * 256-token segment of a block: token headers, literal bytes, match table)
  * followed by the matches in order of their depth (lz_plan), cut into windows
- * of G matches; the G lanes of a group cooperate on a window (Sec. 2, G in
- * {8,16,32,64}); unroll = 16-byte chunks per lane per step (1, 2, 4).
- * schedule 0 = every depth in one launch, a window starting once all windows
- * of the depth below have finished (per-depth counters); schedule 1 = one
- * launch per depth, except that the deepest depths that each have at most
- * `tail` windows of 64 matches run in a single one-workgroup launch with a
+ * of at most 64 matches and 3 KiB of match output (a longer match is split
+ * over windows); the G lanes of a group cooperate on 64 / G parts of a window
+ * (Sec. 2, G in {8,16,32,64}); unroll = 16-byte chunks per lane per step
+ * (1, 2, 4).  schedule 0 = every depth in one launch, a window starting once
+ * all windows of the depth below have finished (per-depth counters);
+ * schedule 1 = one launch per depth, except that the deepest depths that each
+ * have at most `tail` windows run in a single one-workgroup launch with a
  * barrier between depths (0 = 32 windows; 0xFFFFFFFF = no such launch).
  * NULL config = G 64, unroll 2, schedule 1, tail 0. */
 typedef struct lz_decode_cfg {
