@@ -1857,7 +1857,6 @@ struct BatchGroup {
   std::vector<uint32_t> arcs;  // archive indices
 };
 
-// windows of G match-table slots over every level of the group's archives
 // windows over every depth of the group's archives
 uint64_t group_windows(const std::vector<lz_dev*>& H, const BatchGroup& g, uint64_t* nl_out) {
   uint64_t nw = 0, nl = 0;
