@@ -1,41 +1,42 @@
 // lz_device.hip -- gfx950 match-phase decoder of absolute-offset LZ77.
 //
 // Work is done by groups of G lanes of a 64-lane wave (Sec. 2: cooperation
-// width G; Sec. 3.1: lanes = G x N_blocks).  A decode is two launches:
+// width G; Sec. 3.1: lanes = G x N_blocks).  A decode is a parse launch
+// followed by the match passes:
 //
-//  parse  One group per LZ block walks the block's token stream: each lane
-//         reads one token header (cmd byte, length extensions, absolute
-//         source) and group prefix sums give every token's output position
-//         and literal offset, so G tokens are parsed per step.  The group
-//         copies all literal runs of the block and writes every match as a
-//         16-byte record {offset in block, length, source} into a match table
-//         laid out in plan order (below).
+//  parse  One group per segment of 256 tokens of one block: each lane reads
+//         one token header (cmd byte, source, plan slot), a group prefix count
+//         locates the length extensions, and prefix sums give every token's
+//         output position and literal offset, so G tokens are parsed per
+//         step.  Each match is stored as a 16-byte record {dst, length, src}
+//         at its slot of the match table, which is in plan order (below).
+//         The literals of the G tokens are written as the aligned 16-byte
+//         blocks of their whole output span when literals are dense (match
+//         bytes get arbitrary values there and are rewritten by the match
+//         passes), else run by run.
 //  match  The plan (computed on the host when the archive is opened) gives
-//         each match a dependency level: literals are level 0, a match takes
-//         the largest level among the writers of its source bytes, plus one
-//         for writers in another block.  Matches of one block at one level
-//         form a unit; units are ordered by (level, block).  Schedule 0 runs
-//         all units in one launch: groups take units in order from an atomic
-//         ticket; a unit of level p of block b starts once every block it
-//         reads (and b itself) has published done_level >= p, i.e. has
-//         finished all its units below p; finishing a unit publishes the
-//         block's next level.  Every unit waits only on units taken earlier,
-//         so the earliest unfinished unit can always run.  Output bytes in
-//         this launch are read and written with agent-scope (sc1) accesses,
-//         so publishing needs only the store acknowledgements, no L2 write-
-//         back.  Schedule 1 launches each level's units separately (kernel
-//         boundaries order the levels) with ordinary cached accesses.
+//         each match a dependency depth: literal bytes have depth 0, a match
+//         has one more than the deepest token that wrote any of its source
+//         bytes (its own bytes excluded), so matches of one depth never read
+//         each other's output.  Slots are ordered by (depth, token) and cut
+//         into windows of at most 64 matches and 3 KiB (a longer match is
+//         split over windows).  Schedule 1 launches each depth's windows
+//         separately (kernel boundaries order the depths) with ordinary cached
+//         accesses, and runs the deepest, smallest depths in one workgroup
+//         with a barrier between them.  Schedule 0 runs every depth in one
+//         launch: groups take windows depth by depth from per-depth tickets,
+//         wait until the depth below has counted all its windows done, and
+//         read and write output bytes with agent-scope (sc1) accesses.
 //
-// Copy engine (both launches): the group's pending segments (literal runs or
-// match pieces) are cut into batches whose sources lie entirely before the
-// batch's first output byte, so a batch has no read-after-write inside it; a
-// match whose source overlaps its own output (period d = dst - src < length)
-// runs as pieces of length d, 2d, 4d, ... each reading the already final
-// prefix.  A batch's output is covered by 16-byte aligned chunks spread over
-// the group's lanes (`unroll` chunks per lane per step): one unaligned 16-byte
-// load of the source window and one aligned 16-byte store per full chunk; the
-// chunks at segment edges are written with exact byte/short/dword/qword
-// stores so neighbouring segments never race on a byte.
+// Copy engine: a lane's pending segment (literal run or match piece) is cut
+// into 16-byte chunks [16q, 16q + 16), the last one moved back to end at the
+// segment end, so every chunk of a segment of 16 bytes or more is one
+// unaligned 16-byte load and store inside the segment; shorter segments are
+// written with two overlapping power-of-two stores.  Chunks are dealt over the
+// group's lanes (`unroll` per lane per step, all loads of a step in flight
+// before the first store).  A match whose source overlaps its own output
+// (period d = dst - src < length) runs as pieces d, 2d, 4d, ... each reading
+// the already final prefix.
 //
 // Mode 2 executes pre-decoded tokens whose match sources are in a separate
 // buffer (the pure-copy control of Sec. 3.3).
@@ -1835,8 +1836,9 @@ int lz_decode_range(lz_dev* h, uint64_t off, uint64_t len, uint8_t* d_out, void*
 //
 // Thousands of archives in one replayable launch sequence: archives that share
 // a configuration form a group; a group is one parse launch over the parse
-// segments of all its archives and one launch per dependency level over the
-// level-p units of all its archives (or one launch for schedule 0).  Every
+// segments of all its archives and one launch per dependency depth over the
+// depth-p windows of all its archives, with the small deepest depths in one
+// workgroup (or one launch for schedule 0).  Every
 // work item carries its archive index; the kernels read that archive's
 // streams, plan and output from a descriptor table.  All groups are recorded
 // in one graph.
