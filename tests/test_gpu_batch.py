@@ -69,6 +69,31 @@ def test_batch_equals_solo(mix):
     b.destroy()
 
 
+def test_batch_packed_unaligned_outputs():
+    """Outputs packed back to back in one buffer at odd offsets, 3 guard bytes
+    between them: whole-span literal blocks of one archive never touch its
+    neighbours' bytes."""
+    dev = _dev()
+    arcs, inputs = _mixed_archives(24, 11)
+    das = [lz.DeviceArchive(a, device=dev) for a in arcs]
+    offs, pos = [], 5
+    for d in das:
+        offs.append(pos)
+        pos += max(d.n, 1) + 3
+    buf = torch.full((pos + 16,), 0xEE, dtype=torch.uint8, device=dev)
+    outs = [buf[o:o + max(d.n, 1)] for o, d in zip(offs, das)]
+    print(f"[batch packed] {len(das)} archives, {pos} bytes", flush=True)
+    b = lz.Batch(das, outs, None)
+    b.launch()
+    torch.cuda.synchronize()
+    host = buf.cpu().numpy()
+    for o, d, x in zip(offs, das, inputs):
+        assert np.array_equal(host[o:o + d.n], x), (o, d.n)
+        assert np.all(host[o + d.n:o + d.n + 3] == 0xEE)
+    assert np.all(host[:5] == 0xEE)
+    b.destroy()
+
+
 def test_autotune_choices_decode_exactly():
     dev = _dev()
     arcs, inputs = _mixed_archives(24, 11)
