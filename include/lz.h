@@ -170,8 +170,9 @@ typedef struct lz_decode_cfg {
 int lz_device_bytes(const uint8_t* arc, uint64_t arc_size, uint64_t* bytes);
 
 /* Validates the archive on the host, copies it into the caller's device buffer
- * d_buf (>= lz_device_bytes) on `stream`, and returns a handle.  The host
- * archive may be freed after the stream has completed the copy. */
+ * d_buf (>= lz_device_bytes, 256-byte aligned as hipMalloc and torch
+ * allocations are; LZ_E_INVAL otherwise) on `stream`, and returns a handle.
+ * The host archive may be freed after the stream has completed the copy. */
 int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t d_cap, void* stream, lz_dev** h);
 
 /* Decodes the whole archive into d_out[0, n) (Sec. 2: match phase, device
@@ -241,9 +242,9 @@ int lz_decode_range(lz_dev* h, uint64_t off, uint64_t len, uint8_t* d_out, void*
  * schedule 0).  This is how small archives -- starved alone, Sec. 3.1/3.2 --
  * fill the GPU.  Archive i decodes into d_out[i] (capacity out_cap[i]);
  * cfgs[i] (NULL = defaults) selects its configuration.  d_scratch holds the
- * merged work lists (lz_batch_scratch_bytes).  The batch records the handles'
- * device buffers: an archive must not be decoded elsewhere while the batch
- * runs. */
+ * merged work lists (lz_batch_scratch_bytes; 256-byte aligned, else
+ * LZ_E_INVAL).  The batch records the handles' device buffers: an archive must
+ * not be decoded elsewhere while the batch runs. */
 typedef struct lz_batch lz_batch;
 int lz_batch_scratch_bytes(uint32_t count, lz_dev* const* handles, const lz_decode_cfg* cfgs, uint64_t* bytes);
 int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_out, const uint64_t* out_cap,

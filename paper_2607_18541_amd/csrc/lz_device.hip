@@ -1208,6 +1208,8 @@ int lz_device_bytes(const uint8_t* arc, uint64_t arc_size, uint64_t* bytes) {
 int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t d_cap, void* stream, lz_dev** out) {
   if (!out || !d_buf) return lz::fail(LZ_E_INVAL, "null argument");
   *out = nullptr;
+  // the buffer holds words that kernels update atomically (error flags, counters)
+  if ((uintptr_t)d_buf & 255u) return lz::fail(LZ_E_INVAL, "d_buf must be 256-byte aligned");
   lz::ArcView v;
   int rc = lz::view_archive(arc, arc_size, &v);
   if (rc) return rc;
@@ -1918,6 +1920,8 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
                     const lz_decode_cfg* cfgs, void* d_scratch, uint64_t scratch_cap, void* stream, lz_batch** out) {
   if (!out || (count && (!handles || !d_out || !out_cap)) || !d_scratch) return lz::fail(LZ_E_INVAL, "null argument");
   *out = nullptr;
+  // the scratch holds words that kernels update atomically (error flag, counters)
+  if ((uintptr_t)d_scratch & 255u) return lz::fail(LZ_E_INVAL, "d_scratch must be 256-byte aligned");
   if (count >= (1u << 24)) return lz::fail(LZ_E_INVAL, "at most 2^24 - 1 archives per batch");
   std::vector<lz_dev*> H(handles, handles + count);
   for (uint32_t i = 0; i < count; ++i) {

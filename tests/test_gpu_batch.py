@@ -94,6 +94,28 @@ def test_batch_packed_unaligned_outputs():
     b.destroy()
 
 
+def test_batch_scratch_alignment_rejected():
+    """A batch scratch that is not 256-byte aligned (it holds atomically
+    updated words) is refused before anything is recorded or launched."""
+    import ctypes
+    dev = _dev()
+    arcs, _ = _mixed_archives(3, 13)
+    das = [lz.DeviceArchive(a, device=dev) for a in arcs]
+    outs = [torch.empty(max(d.n, 1), dtype=torch.uint8, device=dev) for d in das]
+    hs = (ctypes.c_void_p * len(das))(*[d.h.value for d in das])
+    sb = ctypes.c_uint64()
+    assert lz.lib().lz_batch_scratch_bytes(len(das), hs, None, ctypes.byref(sb)) == 0
+    scratch = torch.empty(sb.value + 512, dtype=torch.uint8, device=dev)
+    op = (ctypes.c_void_p * len(das))(*[o.data_ptr() for o in outs])
+    caps = np.array([o.numel() for o in outs], dtype=np.uint64)
+    b = ctypes.c_void_p()
+    rc = lz.lib().lz_batch_create(len(das), hs, op, caps.ctypes.data, None,
+                                  ctypes.c_void_p(scratch.data_ptr() + 8), sb.value, None, ctypes.byref(b))
+    assert rc == lz.LZ_E_INVAL and not b.value
+    for d in das:
+        d.close()
+
+
 def test_autotune_choices_decode_exactly():
     dev = _dev()
     arcs, inputs = _mixed_archives(24, 11)

@@ -205,3 +205,17 @@ def test_blockwise_encoder_uniform_equals_plain():
         for k in ta:
             assert np.array_equal(ta[k], tb[k])
         assert np.array_equal(oracle.decode(a), x)
+
+
+def test_device_buffer_alignment_rejected_before_any_device_call():
+    """lz_device_open refuses a device buffer that is not 256-byte aligned
+    (kernels update words in it atomically); the check runs before the
+    archive is validated or any HIP call is made."""
+    import ctypes
+    x = synth.zipf_text(4096, seed=2)
+    arc = lz.encode(x, 12, (4, 4, 4, 4))
+    h = ctypes.c_void_p()
+    rc = lz.lib().lz_device_open(arc.ctypes.data, arc.size, ctypes.c_void_p(0x10001), 1 << 30, None,
+                                 ctypes.byref(h))
+    assert rc == lz.LZ_E_INVAL and not h.value
+    assert b"256-byte aligned" in lz.lib().lz_last_error()
