@@ -476,11 +476,10 @@ def run_serve(args, torch, lz):
         da.decode_range(int(offs[i]), int(lens[i]))
     torch.cuda.synchronize()
     per_req = (time.perf_counter() - t1) / 8
-    rows = []
-    for load in [float(v) for v in str(args.load).split(",")]:
-        rate = load / per_req  # requests per second offered
-        gaps = -np.log(1.0 - synth.uniform(k, 53)) / rate
-        arrive = np.cumsum(gaps)
+    tot = int(lens.sum())
+
+    def serve(arrive, label):
+        """Requests i arrive at arrive[i] seconds; returns the level's row."""
         srv = lz.Server(da, args.arena << 20, slots=args.slots)
         lat = np.zeros(k)
         pending = {}
@@ -504,19 +503,38 @@ def run_serve(args, torch, lz):
                     done += 1
             if time.perf_counter() - last_log > 10:
                 last_log = time.perf_counter()
-                log("load %.1f: served %d/%d requests" % (load, done, k))
+                log("%s: served %d/%d requests" % (label, done, k))
             if nxt < k and not pending:
                 time.sleep(max(0.0, min(0.001, arrive[nxt] - (time.perf_counter() - T0))))
         wall = time.perf_counter() - T0
         hw = srv.stats()["arena_high_water"]
         srv.destroy()
-        tot = int(lens.sum())
-        rows.append({"load": load, "offered_req_per_s": round(rate, 2), "gbps": round(tot / wall / 1e9, 3),
-                     "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
-                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-                     "mean_ms": round(float(lat.mean()) * 1e3, 2), "wall_s": round(wall, 2),
-                     "arena_high_water": int(hw)})
-        log("load %.1f: %s" % (load, json.dumps(rows[-1])))
+        row = {"level": label, "served_req_per_s": round(k / wall, 2), "gbps": round(tot / wall / 1e9, 3),
+               "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+               "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+               "mean_ms": round(float(lat.mean()) * 1e3, 2), "wall_s": round(wall, 2), "arena_high_water": int(hw)}
+        log("%s: %s" % (label, json.dumps(row)))
+        return row
+
+    def poisson(rate):
+        return np.cumsum(-np.log(1.0 - synth.uniform(k, 53)) / rate)
+
+    rows = []
+    # saturated capacity: every request queued at once
+    sat = serve(np.zeros(k), "saturated")
+    cap = k / sat["wall_s"]
+    sat["offered_req_per_s"] = None
+    rows.append(sat)
+    # offered loads as fractions of the saturated capacity
+    for f in [float(v) for v in str(args.capacity).split(",") if v]:
+        r = serve(poisson(f * cap), "%.2f of capacity" % f)
+        r["offered_req_per_s"] = round(f * cap, 2)
+        rows.append(r)
+    # offered loads as multiples of the one-at-a-time service rate
+    for load in [float(v) for v in str(args.load).split(",") if v]:
+        r = serve(poisson(load / per_req), "%.1f x one-at-a-time" % load)
+        r["offered_req_per_s"] = round(load / per_req, 2)
+        rows.append(r)
     # every tenth request checked against the input
     for i in range(0, k, 10):
         got = da.decode_range(int(offs[i]), int(lens[i]))
@@ -526,11 +544,12 @@ def run_serve(args, torch, lz):
     return {"metric": "range-serving GB/s and latency", "value": best["gbps"], "unit": "GB/s",
             "n_gpus": 1, "steps": k, "warmup": 8, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-            "config": {"workload": "FASTQ-like %d B (12/16/24/32, %s), %d Poisson range requests of 16 KiB-64 MiB "
-                                   "per load level" % (n, "1 GiB segments" if seg else "one segment", k),
+            "config": {"workload": "FASTQ-like %d B (12/16/24/32, %s), %d range requests of 16 KiB-64 MiB per "
+                                   "level: all at once (saturated), then Poisson at fractions of that capacity"
+                                   % (n, "1 GiB segments" if seg else "one segment", k),
                        "arena_mib": args.arena, "slots": args.slots},
             "detail": {"alone_ms": round(per_req * 1e3, 2), "mean_request_bytes": int(lens.mean()),
-                       "loads": rows, "best": best}}
+                       "capacity_req_per_s": round(cap, 2), "loads": rows, "best": best}}
 
 
 def run_sweep(args, torch, lz):
@@ -738,7 +757,9 @@ def main():
     ap.add_argument("--workload", default="fastq", choices=["fastq", "sweep", "batch", "serve", "ablate", "seek"])
     ap.add_argument("--count", type=int, default=4096, help="batch: archives")
     ap.add_argument("--requests", type=int, default=300, help="serve: requests")
-    ap.add_argument("--load", default="1,4,16", help="serve: offered rate / one-at-a-time rate (comma list)")
+    ap.add_argument("--capacity", default="0.5,0.8,0.95",
+                    help="serve: offered rates as fractions of the saturated capacity (comma list)")
+    ap.add_argument("--load", default="", help="serve: offered rate / one-at-a-time rate (comma list)")
     ap.add_argument("--arena", type=int, default=4096, help="serve: arena MiB")
     ap.add_argument("--slots", type=int, default=64, help="serve: request slots")
     ap.add_argument("--size", type=int, default=1 << 30)
