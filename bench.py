@@ -201,6 +201,57 @@ def copy_ceiling(torch, n, steps):
     return 2 * n / (ms * 1e-3) / 1e9
 
 
+ENTROPY_PART_NAMES = ("cmd", "x16", "x32", "src_lo_planes", "lit", "header_and_table", "src_hi_plane")
+
+
+def entropy_parts(parts):
+    return {k: int(round(float(v))) for k, v in zip(ENTROPY_PART_NAMES, parts)}
+
+
+def sweep_points(args, torch, lz, ms=(256, 1024), log2_bs=14):
+    """Generated streams of the granularity sweep (Table II method) at the
+    mean match lengths where the bandwidth target is set: 256 MiB, 16 KiB
+    blocks, G = 64.  Each point's cpu_baseline is the oracle's sequential
+    execution of the same tokens on one host core, whose output is also the
+    reference the GPU decode is compared with, byte by byte."""
+    import synth
+    import oracle
+    dev = torch.device("cuda:0")
+    n = 1 << 28
+    pts = []
+    for i, m in enumerate((32, 64, 128, 256, 512, 1024)):
+        if m not in ms:
+            continue
+        ll, ml, sr, lit = synth.geo_tokens(n, m, seed=2 + i)
+        t0 = time.perf_counter()
+        ref = oracle.exec_tokens(n, ll, ml, sr, lit)
+        cpu_s = time.perf_counter() - t0
+        arc = lz.build_archive(n, log2_bs, ll, ml, sr, lit)
+        info = lz.archive_info(arc)
+        alg, _ = algorithmic_bytes(arc, info)
+        da = lz.DeviceArchive(arc, device=dev)
+        out = torch.empty(n, dtype=torch.uint8, device=dev)
+        mean_ms, _, _ = time_decode(torch, da, out, 64, args.unroll, args.schedule, args.warmup, args.steps)
+        if not bool(torch.equal(out, torch.from_numpy(ref).to(dev))):
+            raise SystemExit("generated stream m=%d: GPU decode differs from the oracle" % m)
+        parse_ms, match_ms = time_stages(torch, da, out, 64, args.unroll, args.schedule, args.steps)
+        match_alg = 2 * info["match_bytes"]
+        pt = {"m": m, "n_bytes": n, "log2_bs": log2_bs, "G": 64, "realized_m": round(info["mean_match"], 1),
+              "depths": da.levels, "ms": round(mean_ms, 4), "gbps": round(n / mean_ms / 1e6, 2),
+              "alg_gbps": round(alg / mean_ms / 1e6, 2), "frac": round(alg / mean_ms / 1e6 / HBM_PEAK_GBS, 4),
+              "match_stage": {"ms": round(match_ms, 4), "alg_gbps": round(match_alg / match_ms / 1e6, 2),
+                              "frac": round(match_alg / match_ms / 1e6 / HBM_PEAK_GBS, 4)},
+              "parse_ms": round(parse_ms, 4), "oracle_checked": True,
+              "cpu_baseline": {"value": round(n / cpu_s / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                               "sample": "sequential execution of the whole stream's tokens, one run"}}
+        log("sweep point: %s" % json.dumps(pt))
+        pts.append(pt)
+        da.close()
+        del out
+        torch.cuda.empty_cache()
+    return pts
+
+
 def achieved_all(t):
     return t["alg_bytes"] / (t["mean_ms"] * 1e-3) / 1e9
 
@@ -222,7 +273,7 @@ def run_fastq(args, torch, lz):
         enc_s = time.perf_counter() - t0
         log("encoded %s: %d B archive in %.1fs" % (name, arc.size, enc_s))
         info = lz.archive_info(arc)
-        ent, _ = lz.entropy_size(arc)
+        ent, parts = lz.entropy_size(arc)
         t0 = time.perf_counter()
         da = lz.DeviceArchive(arc, device=dev)
         open_s = time.perf_counter() - t0
@@ -240,11 +291,19 @@ def run_fastq(args, torch, lz):
         if not bool(torch.equal(out, torch.from_numpy(x).to(dev))):
             raise SystemExit(f"{name}: staged GPU decode differs from the input")
         log("stages %s: parse %.3f ms, match passes %.3f ms" % (name, parse_ms, match_ms))
+        g32_ms = None
+        if name == "tuned" and args.G != 32:
+            # the configuration's own cooperation width, beside the default
+            g32_ms, _, _ = time_decode(torch, da, out, 32, args.unroll, args.schedule, args.warmup, args.steps)
+            if not bool(torch.equal(out, torch.from_numpy(x).to(dev))):
+                raise SystemExit("tuned, G=32: GPU decode differs from the input")
+            log("decoded tuned at G=32: %.3f ms, %.2f GB/s" % (g32_ms, n / g32_ms / 1e6))
         res[name] = {
             "arc": arc, "info": info, "mean_ms": mean_ms, "median_ms": med_ms, "wall_s": wall,
             "gbps": n / (mean_ms * 1e-3) / 1e9, "alg_bytes": alg, "tok_bytes": tok_bytes,
             "ratio_raw": n / arc.size, "ratio_entropy": n / ent, "enc_s": enc_s, "open_s": open_s,
-            "levels": da.levels, "parse_ms": parse_ms, "match_ms": match_ms,
+            "levels": da.levels, "parse_ms": parse_ms, "match_ms": match_ms, "device_bytes": da.device_bytes,
+            "entropy_parts": entropy_parts(parts), "g32_ms": g32_ms,
         }
         da.close()
         del out
@@ -295,6 +354,15 @@ def run_fastq(args, torch, lz):
             "tuned_levels": t["levels"], "base_levels": b["levels"],
             "base_ms": round(b["mean_ms"], 4), "encode_s": [round(b["enc_s"], 2), round(t["enc_s"], 2)],
             "bit_exact": True, **gen,
+            "tuned_G32": {"G": 32, "ms": round(t["g32_ms"], 4), "gbps": round(n / t["g32_ms"] / 1e6, 3)}
+            if t["g32_ms"] else None,
+            # everything resident on the device per archive: the archive, the
+            # depth plan and parse segments computed at open, and the match table
+            "residency": {k: {"archive_bytes": int(res[k]["arc"].size), "device_bytes": int(res[k]["device_bytes"]),
+                              "plan_and_table_bytes": int(res[k]["device_bytes"] - res[k]["arc"].size),
+                              "ratio_raw": round(res[k]["ratio_raw"], 4),
+                              "ratio_resident": round(n / res[k]["device_bytes"], 4)} for k in ("base", "tuned")},
+            "entropy_bound_bytes_by_stream": {k: res[k]["entropy_parts"] for k in ("base", "tuned")},
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -310,6 +378,8 @@ def run_fastq(args, torch, lz):
             "whole_decode_alg_gbps": round(achieved_all(t), 2),
         },
     }
+    if not args.no_sweep_points:
+        line["sweep_points"] = sweep_points(args, torch, lz)
     if not args.no_cpu:
         log("timing the CPU oracle decode")
         dt, reps, out = cpu_oracle_time(t["arc"], n)
@@ -460,7 +530,7 @@ def run_serve(args, torch, lz):
     x = synth.fastq(n, seed=5)
     n = int(x.size)
     log("generated %d B in %.0fs" % (n, time.perf_counter() - t0))
-    seg = (1 << 30) if n > (3 << 30) else 0
+    seg = args.segment_mib << 20 if args.segment_mib >= 0 else ((1 << 30) if n > (3 << 30) else 0)
     arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain, segment=seg,
                     progress=lambda d, t: log("encoded %d of %d input bytes" % (d, t)))
     log("encoded: %d B archive (ratio %.3f) in %.0fs" % (arc.size, n / arc.size, time.perf_counter() - t0))
@@ -508,11 +578,13 @@ def run_serve(args, torch, lz):
                 time.sleep(max(0.0, min(0.001, arrive[nxt] - (time.perf_counter() - T0))))
         wall = time.perf_counter() - T0
         hw = srv.stats()["arena_high_water"]
+        max_groups = srv.stats()["max_running_groups"]
         srv.destroy()
         row = {"level": label, "served_req_per_s": round(k / wall, 2), "gbps": round(tot / wall / 1e9, 3),
                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-               "mean_ms": round(float(lat.mean()) * 1e3, 2), "wall_s": round(wall, 2), "arena_high_water": int(hw)}
+               "mean_ms": round(float(lat.mean()) * 1e3, 2), "wall_s": round(wall, 2), "arena_high_water": int(hw),
+               "max_groups_in_flight": int(max_groups)}
         log("%s: %s" % (label, json.dumps(row)))
         return row
 
@@ -559,12 +631,19 @@ def run_sweep(args, torch, lz):
     for each block size and G, and the pure-copy control (every token
     independent, sources in a reference copy of the output) for each G."""
     import synth
+    import oracle
     dev = torch.device("cuda:0")
     n = args.size
     rows = []
+    cpu = []
     for i, m in enumerate((32, 64, 128, 256, 512, 1024)):
         ll, ml, sr, lit = synth.geo_tokens(n, m, seed=2 + i)
-        ref = None  # the first decode; every other decode and the pure copy must equal it
+        # cpu_baseline leg: the oracle executes the same tokens sequentially on
+        # one host core; its output is what every decode is compared with
+        t0 = time.perf_counter()
+        expect = torch.from_numpy(oracle.exec_tokens(n, ll, ml, sr, lit)).to(dev)
+        cpu.append({"m": m, "gbps": round(n / (time.perf_counter() - t0) / 1e9, 4)})
+        ref = None  # the first GPU decode (equal to the oracle's): the pure copy's source buffer
         for lb in (14, 16, 18, 20):
             arc = lz.build_archive(n, lb, ll, ml, sr, lit)
             info = lz.archive_info(arc)
@@ -573,10 +652,10 @@ def run_sweep(args, torch, lz):
             alg, _ = algorithmic_bytes(arc, info)
             for G in (8, 16, 32, 64):
                 mean_ms, med_ms, wall = time_decode(torch, da, out, G, args.unroll, args.schedule, 2, args.steps)
+                if not bool(torch.equal(out, expect)):
+                    raise SystemExit("decode differs from the oracle (m=%d log2_bs=%d G=%d)" % (m, lb, G))
                 if ref is None:
                     ref = out.clone()
-                elif not bool(torch.equal(out, ref)):
-                    raise SystemExit("decodes disagree (m=%d log2_bs=%d G=%d)" % (m, lb, G))
                 rows.append({"mode": "decode", "m": m, "log2_bs": lb, "G": G, "lanes": G * info["n_blocks"],
                              "gbps": round(n / mean_ms / 1e6, 2), "alg_gbps": round(alg / mean_ms / 1e6, 2),
                              "frac": round(alg / mean_ms / 1e6 / HBM_PEAK_GBS, 4), "depths": da.levels,
@@ -600,8 +679,8 @@ def run_sweep(args, torch, lz):
             us = g(copy_units(llv + mlv, G, 2048), np.uint64)
             lz.purecopy(tdst, tlo, tll, tsrc, tml, us, tlit, ref, out, G=G, unroll=args.unroll)
             torch.cuda.synchronize()
-            if not bool(torch.equal(out, ref)):
-                raise SystemExit("pure copy differs from the decode (m=%d G=%d)" % (m, G))
+            if not bool(torch.equal(out, expect)):
+                raise SystemExit("pure copy differs from the oracle (m=%d G=%d)" % (m, G))
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
@@ -613,7 +692,7 @@ def run_sweep(args, torch, lz):
             rows.append({"mode": "purecopy", "m": m, "G": G, "gbps": round(n / ms / 1e6, 2),
                          "alg_gbps": round(pc_alg / ms / 1e6, 2), "frac": round(pc_alg / ms / 1e6 / HBM_PEAK_GBS, 4)})
             log(json.dumps(rows[-1]))
-        del out, ref
+        del out, ref, expect
         torch.cuda.empty_cache()
     best = max(r["gbps"] for r in rows if r["mode"] == "decode" and r["m"] >= 256)
     best_frac = max(r["frac"] for r in rows if r["mode"] == "decode" and r["m"] >= 256)
@@ -622,7 +701,10 @@ def run_sweep(args, torch, lz):
             "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
             "config": {"workload": "match-length sweep, %d B streams, m in 32..1024, 16 KiB-1 MiB blocks, "
                                    "G in 8..64" % n},
-            "best_frac_m_ge_256": best_frac, "rows": rows}
+            "best_frac_m_ge_256": best_frac, "rows": rows,
+            "cpu_baseline": {"value": min(c["gbps"] for c in cpu), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                             "sample": "sequential execution of each m's whole %d-byte token stream, one run per m "
+                                       "(per m: %s)" % (n, json.dumps(cpu))}}
 
 
 def run_seek(args, torch, lz):
@@ -635,7 +717,8 @@ def run_seek(args, torch, lz):
     dev = torch.device("cuda:0")
     x = synth.fastq(args.size, seed=3)
     n = int(x.size)
-    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain)
+    seg = max(args.segment_mib, 0) << 20
+    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain, segment=seg)
     da = lz.DeviceArchive(arc, device=dev)
     rows = []
     st = torch.cuda.current_stream()
@@ -664,6 +747,7 @@ def run_seek(args, torch, lz):
                        "device_ms": round(dev_ms, 3), "total_ms": round((t_plan + t_run) * 1e3, 3),
                        "mode": "prefix" if plan.prefix_bytes else "closure",
                        "closure_bytes": plan.closure_bytes, "prefix_bytes": plan.prefix_bytes,
+                       "horizon": plan.horizon,
                        "depths": plan.levels}
                 if best is None or row["total_ms"] < best["total_ms"]:
                     best = row
@@ -677,8 +761,8 @@ def run_seek(args, torch, lz):
         "value": round(float(np.median(small)), 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 0,
         "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8", "data": "synthetic",
-        "config": {"workload": "FASTQ-like reads %d B, 12/16/24/32, 64 KiB blocks; best of %d seeks per point"
-                               % (n, args.steps)},
+        "config": {"workload": "FASTQ-like reads %d B, 12/16/24/32, 64 KiB blocks%s; best of %d seeks per point"
+                               % (n, ", encoded in %d MiB segments" % (seg >> 20) if seg else "", args.steps)},
         "rows": rows,
     }
 
@@ -762,6 +846,9 @@ def main():
     ap.add_argument("--load", default="", help="serve: offered rate / one-at-a-time rate (comma list)")
     ap.add_argument("--arena", type=int, default=4096, help="serve: arena MiB")
     ap.add_argument("--slots", type=int, default=64, help="serve: request slots")
+    ap.add_argument("--segment-mib", dest="segment_mib", type=int, default=-1,
+                    help="serve/seek: encode in segments of this many MiB (serve default: 1024 above 3 GiB, else "
+                         "none; seek default: none)")
     ap.add_argument("--size", type=int, default=1 << 30)
     ap.add_argument("--log2-bs", dest="log2_bs", type=int, default=16)
     ap.add_argument("--G", type=int, default=64)
@@ -769,6 +856,8 @@ def main():
     ap.add_argument("--schedule", type=int, default=1)
     ap.add_argument("--max-chain", dest="max_chain", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sweep-points", action="store_true",
+                    help="fastq: skip the generated-stream points at mean match length 256 and 1024")
     ap.add_argument("--profile-run", action="store_true",
                     help="decode the 12/16/24/32 archive `steps` times plus a calibration kernel (counter runs)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

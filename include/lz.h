@@ -208,18 +208,24 @@ void lz_device_close(lz_dev* h);
  * computes the token closure of each range (every token the range's bytes
  * depend on through match sources), lays it out in output order in device
  * scratch and orders its copies by dependency depth.  Closures cost host work
- * per byte, so once they exceed max(1 MiB, E/256) bytes, E = the largest range
- * end, the plan instead decodes every token before E on the device (parse
- * segments and depth windows of that prefix) into scratch and gathers the
- * ranges from it.  LZ_E_RANGE if a range leaves [0, n).  Plans are host
- * objects; free with lz_range_plan_free after the stream that ran them has
+ * per byte, so once they exceed max(1 MiB, (E - H)/4096) bytes, E = the
+ * largest range end, the plan instead decodes every token of [H, E) on the
+ * device (parse segments and depth windows of that stretch) into scratch and
+ * gathers the ranges from it.  H, the decode horizon, is the largest start of
+ * an output grain (2^20 bytes or the block size if larger) at or below the
+ * first range such that no match written between H and the grain holding
+ * E - 1 reads below H; archives encoded in segments (lz_params.segment) get
+ * their segment starts, so such a decode and its scratch are bounded by one
+ * segment.  LZ_E_RANGE if a range leaves [0, n).  Plans are host objects;
+ * free with lz_range_plan_free after the stream that ran them has
  * completed. */
 typedef struct lz_range_plan lz_range_plan;
 int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const uint64_t* len, lz_range_plan** plan);
 uint64_t lz_range_plan_scratch_bytes(const lz_range_plan* plan); /* device scratch lz_range_run needs */
 uint64_t lz_range_plan_levels(const lz_range_plan* plan);        /* match depths (launches) */
 uint64_t lz_range_plan_closure_bytes(const lz_range_plan* plan); /* closure bytes (0 for a prefix plan) */
-uint64_t lz_range_plan_prefix_bytes(const lz_range_plan* plan);  /* prefix decoded (0 for a closure plan) */
+uint64_t lz_range_plan_prefix_bytes(const lz_range_plan* plan);  /* E - H decoded (0 for a closure plan) */
+uint64_t lz_range_plan_horizon(const lz_range_plan* plan);       /* H (0 for a closure plan) */
 void lz_range_plan_free(lz_range_plan* plan);
 
 /* Runs a plan on `stream`: range i is written to d_out[out_off[i], +len[i]),
@@ -277,17 +283,23 @@ int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* const* d_out, c
  * `slots` is free and the arena has room for the output and the scratch of
  * the group, and launches all requests admitted in that tick as one merged
  * range plan, alternating two streams so new groups overlap running ones.
- * Outputs live in the arena until lz_serve_release.  Single-threaded use. */
+ * A tick allocates no device or pinned memory (plan staging comes from a
+ * pinned pool the server owns, which grows only while no group is in flight).
+ * Outputs live in the arena until lz_serve_release.  A request that can never
+ * fit (its output plus its plan scratch exceed the arena) makes the tick that
+ * meets it return LZ_E_NOMEM and is marked failed (state 4); its slot is held
+ * until lz_serve_release.  Single-threaded use. */
 typedef struct lz_server lz_server;
 int lz_serve_create(lz_dev* h, void* d_arena, uint64_t arena_bytes, uint32_t slots, const lz_decode_cfg* cfg,
                     lz_server** server);
 int lz_serve_submit(lz_server* server, uint64_t off, uint64_t len, uint64_t* id);
 int lz_serve_tick(lz_server* server, uint64_t* n_done, uint64_t* n_admitted);
-int lz_serve_status(lz_server* server, uint64_t id, int* state /* 0 waiting, 1 running, 2 done, 3 released */,
-                    uint8_t** d_ptr);
+int lz_serve_status(lz_server* server, uint64_t id,
+                    int* state /* 0 waiting, 1 running, 2 done, 3 released, 4 failed */, uint8_t** d_ptr);
 int lz_serve_release(lz_server* server, uint64_t id);
 void lz_serve_stats(const lz_server* server, uint64_t* waiting, uint64_t* running_groups, uint64_t* arena_used,
                     uint64_t* arena_high_water);
+uint64_t lz_serve_max_running(const lz_server* server); /* most groups in flight after any tick so far */
 int lz_serve_destroy(lz_server* server);
 
 /* ------------------------------------------------------ learned thresholds */

@@ -81,7 +81,7 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint64_t kSegTok = 256;    // tokens per parse segment
 constexpr uint32_t kWinBytes = 3072;  // a match window holds at most this many bytes ...
 constexpr uint32_t kWinMatches = 64;  // ... and at most this many matches
-constexpr uint64_t kWinSpan = 1ull << 20;  // and its matches start within this many output bytes
+constexpr uint32_t kLog2Grain = 20;  // and its matches lie in one aligned grain of max(2^20, block) bytes
 constexpr uint64_t kClosureMin = 1ull << 20;  // range closures of up to max(1 MiB, prefix / 4096) bytes;
 constexpr uint64_t kClosureRatio = 4096;      // beyond that the prefix is decoded instead
 constexpr uint64_t kGatherPiece = 64ull << 10;  // ranges are gathered into the output in pieces of this size
@@ -109,6 +109,7 @@ struct ArcDesc {
   uintptr_t msrc_lo, msrc_hi;
   const uint32_t* slot;  // per token: match-table index, or kNone
   u32x4* mtab;           // per match: {dst lo, length, src lo, dst hi | src hi << 16}
+  uint64_t out_lo;       // lowest output position a match may read or write (range plans)
 };
 
 struct KArgs {
@@ -727,7 +728,7 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
             m_len = r.y;
             m_src = (uint64_t)r.z | ((uint64_t)(r.w >> 16) << 32);
             l_len = 0;
-            if (valid && (m_src >= m_dst || m_dst + m_len > D.n)) {  // not a record of this archive
+            if (valid && (m_src >= m_dst || m_dst + m_len > D.n || m_src < D.out_lo)) {  // not a record of this output
               m_len = 0;
               atomicOr(A.err, 4u);
             }
@@ -813,10 +814,16 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
               cs.len[i] = valid ? 16 : 0;
             } else {
               // short segment: the window starts at its source, or ends at its
-              // end near the top of the readable range
+              // end near the top of the readable range.  An empty segment (a
+              // lane past the group's last chunk whose owner has nothing to
+              // copy) never touches its source, which need not be an address
+              // inside the buffer (range plans place the output base below it).
               cs.dst[i] = Dd;
               cs.len[i] = valid ? (int)L : 0;
-              if (S + 16 <= hb) {
+              if (L == 0) {
+                cs.win[i] = S;
+                cs.slow[i] = true;
+              } else if (S + 16 <= hb) {
                 cs.win[i] = S;
               } else if (S + L >= lb + 16) {
                 cs.win[i] = S + L - 16;
@@ -910,6 +917,8 @@ struct lz_dev {
   std::vector<uint64_t> h_seg;      // host copies of the parse segments and windows (batch decodes merge them)
   std::vector<uint32_t> h_win;
   std::vector<uint64_t> h_wdst;  // per window: output position of its first byte
+  uint32_t log2_grain = 20;      // output grains: see Plan
+  std::vector<uint64_t> grain_low;
   int cu_count = 0;
   // replayable launch sequences, one per (output, config)
   struct GraphKey {
@@ -992,6 +1001,13 @@ struct Plan {
   std::vector<uint64_t> seg;  // parse segments, 8 words each
   std::vector<uint64_t> lvl_start;
   uint64_t n_match = 0;
+  // Output grains of 2^log2_grain bytes (aligned; a multiple of the block
+  // size): no window holds matches of two grains, and grain_low[g] is the
+  // lowest source of a match written in grain g (its start when lower ones
+  // do not exist).  A range plan can start decoding at any grain start h whose
+  // grains up to the range end read nothing below h.
+  uint32_t log2_grain = kLog2Grain;
+  std::vector<uint64_t> grain_low;
 };
 
 int build_plan(const lz::ArcView& v, Plan& P) {
@@ -1020,6 +1036,7 @@ int build_plan(const lz::ArcView& v, Plan& P) {
   std::vector<uint32_t> tok_of(M + 1, 0), len_of(M + 1, 0);
   std::vector<uint64_t> dst_of(M + 1, 0);
   std::vector<uint8_t> periodic(M + 1, 0);
+  std::vector<uint64_t> blk_low(v.nb, UINT64_MAX);  // lowest match source of each block
   for (uint64_t t = 0; t < T; ++t)
     if (hasm[t]) {
       P.slot[t] = (uint32_t)cursor[depth[t] - 1]++;
@@ -1035,13 +1052,24 @@ int build_plan(const lz::ArcView& v, Plan& P) {
         len_of[sl] = (uint32_t)k.mlen;
         dst_of[sl] = k.dst + k.lit_len;
         periodic[sl] = (k.dst + k.lit_len - k.src < k.mlen) ? 1 : 0;
+        blk_low[b] = std::min(blk_low[b], k.src);
       });
       if (r) bad.store(r);
     });
     if (bad.load()) return lz::fail(LZ_E_CORRUPT, "archive fails validation");
   }
-  // windows of each depth: at most kWinMatches matches and kWinBytes bytes; a
-  // longer match that does not overlap itself is split into kWinBytes pieces
+  P.log2_grain = std::max<uint32_t>(kLog2Grain, v.log2_bs);
+  const uint32_t lg = P.log2_grain;
+  const uint64_t n_grain = v.n ? ((v.n - 1) >> lg) + 1 : 0;
+  P.grain_low.resize(n_grain);
+  for (uint64_t g = 0; g < n_grain; ++g) P.grain_low[g] = g << lg;
+  for (uint64_t b = 0; b < v.nb; ++b) {
+    const uint64_t g = (b << v.log2_bs) >> lg;
+    P.grain_low[g] = std::min(P.grain_low[g], blk_low[b]);
+  }
+  // windows of each depth: at most kWinMatches matches and kWinBytes bytes, all
+  // in one grain; a longer match that does not overlap itself is split into
+  // kWinBytes pieces
   P.lvl_start.assign(NL + 1, 0);
   for (uint64_t p = 0; p < NL; ++p) {
     P.lvl_start[p] = P.win.size() / 4;
@@ -1064,7 +1092,7 @@ int build_plan(const lz::ArcView& v, Plan& P) {
         }
         continue;
       }
-      if (wc && (wc == kWinMatches || wb + L > kWinBytes || dst_of[sl] >= dst_of[w0] + kWinSpan)) flush();
+      if (wc && (wc == kWinMatches || wb + L > kWinBytes || (dst_of[sl] >> lg) != (dst_of[w0] >> lg))) flush();
       if (!wc) w0 = sl;
       ++wc;
       wb += L;
@@ -1254,6 +1282,8 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
   h->h_seg = P.seg;
   h->h_win = P.win;
   h->h_wdst = P.wdst;
+  h->log2_grain = P.log2_grain;
+  h->grain_low = P.grain_low;
   hipStream_t s = (hipStream_t)stream;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -1473,11 +1503,12 @@ int lz_purecopy_device(uint64_t ntok, const uint64_t* d_dst, const uint64_t* d_l
 
 struct lz_range_plan {
   uint64_t count = 0;
-  // prefix mode: every token before prefix_end is decoded into the scratch
-  // data (parse segments [0, nseg), depth p windows [first, win_hi[p]))
+  // prefix mode: every token in [horizon, prefix_end) is decoded into the
+  // scratch data, which holds output positions [horizon, data_end) (parse
+  // segments [seg_lo, seg_hi), depth p windows [win_lo[p], win_hi[p]))
   bool prefix = false;
-  uint64_t prefix_end = 0, nseg = 0;
-  std::vector<uint64_t> win_hi;
+  uint64_t prefix_end = 0, horizon = 0, data_end = 0, seg_lo = 0, seg_hi = 0;
+  std::vector<uint64_t> win_lo, win_hi;
   std::vector<uint64_t> range_src;   // per range: scratch-data offset of byte off
   std::vector<uint64_t> range_len;
   uint64_t data_bytes = 0;           // scratch-data bytes
@@ -1489,8 +1520,9 @@ struct lz_range_plan {
   uint64_t scratch_bytes = 0;        // total device scratch for lz_range_run
   uint8_t* staging = nullptr;        // pinned copy of the piece arrays
   uint64_t staging_bytes = 0;
+  bool staging_owned = true;         // false: lent by a server's pinned pool
   ~lz_range_plan() {
-    if (staging) (void)hipHostFree(staging);
+    if (staging && staging_owned) (void)hipHostFree(staging);
   }
 };
 
@@ -1561,6 +1593,26 @@ size_t find_need(const std::vector<NeedTok>& need, uint64_t x) {
   return i - 1;
 }
 
+// Decode horizon of the output prefix [0, end) as seen from position off: the
+// largest grain start h <= off such that no match written in the grains from
+// h's through the one holding end - 1 reads below h.  Decoding those grains
+// alone (from h) then reproduces every byte of [h, end).  h = 0 always
+// qualifies; segment-encoded archives give their segment starts.
+uint64_t decode_horizon(const lz_dev* h, uint64_t off, uint64_t end) {
+  if (end == 0 || h->grain_low.empty()) return 0;
+  const uint32_t lg = h->log2_grain;
+  const uint64_t g_last = (end - 1) >> lg;
+  uint64_t g = std::min(off >> lg, g_last);
+  uint64_t low = UINT64_MAX;
+  for (uint64_t q = g; q <= g_last; ++q) low = std::min(low, h->grain_low[q]);
+  while (low < (g << lg)) {
+    const uint64_t g2 = low >> lg;
+    for (uint64_t q = g2; q < g; ++q) low = std::min(low, h->grain_low[q]);
+    g = g2;
+  }
+  return g << lg;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1583,9 +1635,13 @@ int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const u
     // A closure costs host work per byte, a prefix decode runs on the device at
     // HBM speed: closures are tried while they stay within a budget that grows
     // with the prefix the ranges would need.
-    uint64_t end = 0;
-    for (uint64_t r = 0; r < count; ++r) end = std::max(end, off[r] + len[r]);
-    uint64_t budget = std::max<uint64_t>(kClosureMin, end / kClosureRatio);
+    uint64_t end = 0, first = h->v.n;
+    for (uint64_t r = 0; r < count; ++r) {
+      end = std::max(end, off[r] + len[r]);
+      if (len[r]) first = std::min(first, off[r]);
+    }
+    const uint64_t horizon = (end > 0 && first < end) ? decode_horizon(h, first, end) : 0;
+    uint64_t budget = std::max<uint64_t>(kClosureMin, (end - horizon) / kClosureRatio);
     for (uint64_t r = 0; r < count && !P->prefix; ++r) {
       P->range_len.push_back(len[r]);
       if (len[r] == 0) {
@@ -1628,29 +1684,41 @@ int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const u
       base += acc;
     }
     if (P->prefix) {
-      // decode every token before `end` into the scratch data, then gather
+      // decode every token of [horizon, end) into the scratch data, then gather
       by_lvl.assign(1, {});
       P->range_len.assign(len, len + count);
-      P->range_src.assign(off, off + count);
       P->prefix_end = end;
-      base = h->v.n;
-      // windows starting before `end` have all their matches before
-      // end + kWinSpan: their records come from the parse of those blocks
-      const uint64_t last_blk = end ? (std::min(h->v.n, end + kWinSpan) - 1) >> h->v.log2_bs : 0;
-      // parse segments are in block order: those of blocks <= last_blk come first
-      uint64_t lo = 0, hi = h->h_seg.size() / 8;
-      while (lo < hi) {
-        const uint64_t mid = (lo + hi) / 2;
-        if ((h->h_seg[8 * mid + 7] & 0xFFFFFFFFull) <= last_blk) lo = mid + 1;
-        else hi = mid;
+      P->horizon = horizon;
+      // windows starting in [horizon, end) have all their matches in the grains
+      // up to the one holding end - 1: the parse of those grains' blocks writes
+      // their records, and the scratch data covers them
+      const uint32_t lg = h->log2_grain;
+      P->data_end = end ? std::min(h->v.n, (((end - 1) >> lg) + 1) << lg) : horizon;
+      P->range_src.assign(count, 0);  // replaces the entries of ranges served by closures so far
+      for (uint64_t r = 0; r < count; ++r) P->range_src[r] = len[r] ? off[r] - horizon : 0;
+      base = P->data_end - horizon;
+      // parse segments are in block order
+      auto seg_bound = [&](uint64_t blk) {  // first segment of a block >= blk
+        uint64_t lo = 0, hi = h->h_seg.size() / 8;
+        while (lo < hi) {
+          const uint64_t mid = (lo + hi) / 2;
+          if ((h->h_seg[8 * mid + 7] & 0xFFFFFFFFull) < blk) lo = mid + 1;
+          else hi = mid;
+        }
+        return lo;
+      };
+      if (P->data_end > horizon) {
+        P->seg_lo = seg_bound(horizon >> h->v.log2_bs);
+        P->seg_hi = seg_bound(((P->data_end - 1) >> h->v.log2_bs) + 1);
       }
-      P->nseg = end ? lo : 0;
       const size_t NL = h->lvl_start.size() ? h->lvl_start.size() - 1 : 0;
+      P->win_lo.assign(NL, 0);
       P->win_hi.assign(NL, 0);
       for (size_t p = 0; p < NL; ++p) {
-        // windows of depth p whose first byte lies before `end`
+        // windows of depth p whose first byte lies in [horizon, end)
         auto b0 = h->h_wdst.begin() + h->lvl_start[p], b1 = h->h_wdst.begin() + h->lvl_start[p + 1];
-        P->win_hi[p] = (uint64_t)(std::lower_bound(b0, b1, end) - h->h_wdst.begin());
+        P->win_lo[p] = (uint64_t)(std::lower_bound(b0, b1, horizon) - h->h_wdst.begin());
+        P->win_hi[p] = std::max(P->win_lo[p], (uint64_t)(std::lower_bound(b0, b1, end) - h->h_wdst.begin()));
       }
     }
     P->data_bytes = base;
@@ -1685,7 +1753,7 @@ int lz_range_plan_create(lz_dev* h, uint64_t count, const uint64_t* off, const u
   // staging layout: dst | lit_off | src (u64) | lit_len | mlen (u32) | unit starts (u64, one unit per piece)
   const uint64_t np = P->p_dst.size();
   auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
-  P->staging_bytes = a256(8 * np) * 3 + a256(4 * np) * 2 + a256(4 * P->win_hi.size());
+  P->staging_bytes = a256(8 * np) * 3 + a256(4 * np) * 2 + 2 * a256(4 * P->win_hi.size());
   P->scratch_bytes = P->staging_bytes + a256(P->data_bytes + 16);
   *out = P;
   return 0;
@@ -1698,7 +1766,8 @@ uint64_t lz_range_plan_levels(const lz_range_plan* P) {
   return P->lvl_piece.size() > 2 ? P->lvl_piece.size() - 3 : 0;
 }
 uint64_t lz_range_plan_closure_bytes(const lz_range_plan* P) { return P ? (P->prefix ? 0 : P->data_bytes) : 0; }
-uint64_t lz_range_plan_prefix_bytes(const lz_range_plan* P) { return P && P->prefix ? P->prefix_end : 0; }
+uint64_t lz_range_plan_prefix_bytes(const lz_range_plan* P) { return P && P->prefix ? P->prefix_end - P->horizon : 0; }
+uint64_t lz_range_plan_horizon(const lz_range_plan* P) { return P && P->prefix ? P->horizon : 0; }
 void lz_range_plan_free(lz_range_plan* P) { delete P; }
 
 int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, const uint64_t* out_off,
@@ -1730,6 +1799,9 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
   const uint64_t o_src = o; memcpy(st + o, P->p_src.data(), 8 * np); o += a256(8 * np);
   const uint64_t o_llen = o; memcpy(st + o, P->p_lit_len.data(), 4 * np); o += a256(4 * np);
   const uint64_t o_mlen = o; memcpy(st + o, P->p_mlen.data(), 4 * np); o += a256(4 * np);
+  const uint64_t o_lo = o;
+  for (size_t p = 0; p < P->win_lo.size(); ++p) ((uint32_t*)(st + o))[p] = (uint32_t)P->win_lo[p];
+  o += a256(4 * P->win_lo.size());
   const uint64_t o_hi = o;
   for (size_t p = 0; p < P->win_hi.size(); ++p) ((uint32_t*)(st + o))[p] = (uint32_t)P->win_hi[p];
   o += a256(4 * P->win_hi.size());
@@ -1744,13 +1816,20 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
   A.p_lit_len = (const uint32_t*)(D + o_llen);
   A.p_mlen = (const uint32_t*)(D + o_mlen);
   if (P->prefix) {
-    // every token before the prefix end, decoded into the scratch data
+    // every token of [horizon, data_end), decoded into the scratch data: the
+    // output base is placed `horizon` bytes before it, so absolute positions
+    // index it directly, and no match may touch a position below the horizon
     KArgs A = base_args(h);
-    A.one = arc_desc(h, data, h->v.n);
-    A.nseg = P->nseg;
-    if (P->nseg) {
+    A.one = arc_desc(h, data - P->horizon, P->data_end);
+    A.one.msrc_lo = (uintptr_t)data;
+    A.one.msrc_hi = (uintptr_t)data + P->data_bytes;
+    A.one.n = P->data_end;
+    A.one.out_lo = P->horizon;
+    A.seg = h->d_seg + 8 * P->seg_lo;
+    A.nseg = P->seg_hi - P->seg_lo;
+    if (A.nseg) {
       kfn_t kp = pick_kernel<kModeParse>(G, U);
-      hipLaunchKernelGGL(kp, dim3((unsigned)grid_for(P->nseg, resident_groups(kp, h->cu_count, G), G)), dim3(kWG), 0,
+      hipLaunchKernelGGL(kp, dim3((unsigned)grid_for(A.nseg, resident_groups(kp, h->cu_count, G), G)), dim3(kWG), 0,
                          s, A);
       HIPCHK(hipGetLastError());
     }
@@ -1758,11 +1837,11 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
     const uint64_t rl = resident_groups(kl, h->cu_count, G);
     const uint64_t NL = P->win_hi.size();
     std::vector<uint64_t> cnt(NL);
-    for (uint64_t p = 0; p < NL; ++p) cnt[p] = P->win_hi[p] - h->lvl_start[p];
+    for (uint64_t p = 0; p < NL; ++p) cnt[p] = P->win_hi[p] - P->win_lo[p];
     const uint64_t pt = tail_start(cnt, kTailWindows);
     for (uint64_t p = 0; p < pt; ++p) {
       KArgs a = A;
-      a.lo = h->lvl_start[p];
+      a.lo = P->win_lo[p];
       a.hi = P->win_hi[p];
       if (a.hi <= a.lo) continue;
       hipLaunchKernelGGL(kl, dim3((unsigned)grid_for((a.hi - a.lo) * (64 / G), rl, G)), dim3(kWG), 0, s, a);
@@ -1772,6 +1851,7 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
       KArgs a = A;
       a.lo = pt;
       a.hi = NL;
+      a.lvl_start = (const uint32_t*)(D + o_lo);
       a.lvl_hi = (const uint32_t*)(D + o_hi);
       hipLaunchKernelGGL(pick_tail(U, false), dim3(1), dim3(kWGTail), 0, s, a);
       HIPCHK(hipGetLastError());
@@ -2194,41 +2274,29 @@ extern "C" int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* cons
 //
 // Continuous batching of range requests against one device-resident archive.
 // Requests wait in a FIFO; a tick first retires every launched group whose
-// completion event has fired (their requests become done, their scratch is
-// freed), then admits waiting requests in arrival order while a request slot
-// is free and the device arena has room for its output plus its share of
-// scratch, and launches everything admitted in this tick as one merged range
-// plan on the next of two streams, so a new group runs while earlier ones are
-// still on the device.  Outputs stay in the arena until released.
+// completion event has fired (their requests become done, their scratch and
+// staging are freed), then admits waiting requests in arrival order while a
+// request slot is free and the device arena has room for its output plus its
+// share of scratch, and launches everything admitted in this tick as one
+// merged range plan on the next of two streams, so a new group runs while
+// earlier ones are still on the device.  Outputs stay in the arena until
+// released.  A tick allocates and frees no device or pinned memory and creates
+// no events: plan staging comes from a pinned pool and completion events from
+// a pool, both owned by the server (freeing pinned memory waits for the whole
+// device, which would serialise the groups).
 
-struct lz_server {
-  lz_dev* h = nullptr;
-  uint8_t* arena = nullptr;
-  uint64_t arena_bytes = 0;
-  uint32_t slots = 0;
-  lz_decode_cfg cfg{64, 2, 1, 0};
-  hipStream_t streams[2] = {nullptr, nullptr};
-  uint32_t next_stream = 0;
-  struct Req {
-    uint64_t id, off, len;
-    uint64_t out_at = 0;          // arena offset of the output
-    int state = 0;                // 0 waiting, 1 running, 2 done
-  };
-  std::vector<Req> reqs;          // indexed by id
-  std::vector<uint64_t> fifo;     // waiting ids, arrival order
-  size_t fifo_head = 0;
-  uint32_t active = 0;            // admitted, not yet released
-  struct Group {
-    hipEvent_t ev;
-    lz_range_plan* plan;
-    uint64_t scratch_at, scratch_len;
-    std::vector<uint64_t> ids;
-  };
-  std::vector<Group> running;
-  // first-fit allocator over the arena: free extents by offset
+namespace {
+
+// First-fit allocator over [0, bytes) in 256-byte units: free extents by offset.
+struct Extents {
   std::map<uint64_t, uint64_t> free_ext;
   uint64_t used = 0, high_water = 0;
   static uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+  void reset(uint64_t bytes) {
+    free_ext.clear();
+    if (bytes) free_ext[0] = bytes;
+    used = 0;
+  }
   bool alloc(uint64_t len, uint64_t* at) {
     len = a256(std::max<uint64_t>(len, 1));
     for (auto it = free_ext.begin(); it != free_ext.end(); ++it)
@@ -2262,6 +2330,65 @@ struct lz_server {
   }
 };
 
+constexpr uint64_t kPinPoolMin = 16ull << 20;  // initial pinned staging pool of a server
+
+}  // namespace
+
+struct lz_server {
+  lz_dev* h = nullptr;
+  uint8_t* arena = nullptr;
+  uint64_t arena_bytes = 0;
+  uint32_t slots = 0;
+  lz_decode_cfg cfg{64, 2, 1, 0};
+  hipStream_t streams[2] = {nullptr, nullptr};
+  uint32_t next_stream = 0;
+  struct Req {
+    uint64_t id, off, len;
+    uint64_t out_at = 0;          // arena offset of the output
+    int state = 0;                // 0 waiting, 1 running, 2 done, 3 released, 4 failed
+  };
+  std::vector<Req> reqs;          // indexed by id
+  std::vector<uint64_t> fifo;     // waiting ids, arrival order
+  size_t fifo_head = 0;
+  uint32_t active = 0;            // admitted (or failed), not yet released
+  struct Group {
+    hipEvent_t ev;
+    lz_range_plan* plan;
+    uint64_t scratch_at, scratch_len, pin_at, pin_len;
+    std::vector<uint64_t> ids;
+  };
+  std::vector<Group> running;
+  uint64_t max_running = 0;       // most groups in flight after any tick
+  Extents mem;                    // device arena
+  Extents pin;                    // pinned staging pool
+  uint8_t* pin_base = nullptr;
+  uint64_t pin_bytes = 0;
+  std::vector<hipEvent_t> ev_free;
+  ~lz_server() {
+    for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
+    if (pin_base) (void)hipHostFree(pin_base);
+    for (auto& st : streams)
+      if (st) (void)hipStreamDestroy(st);
+  }
+  void finish_group(Group& G, int state) {
+    for (uint64_t id : G.ids) reqs[id].state = state;
+    mem.release(G.scratch_at, G.scratch_len);
+    pin.release(G.pin_at, G.pin_len);
+    ev_free.push_back(G.ev);
+    lz_range_plan_free(G.plan);
+  }
+  // the newest admission goes back to the head of the queue
+  void unadmit(std::vector<uint64_t>& ids, std::vector<uint64_t>& offs, std::vector<uint64_t>& lens) {
+    auto& r = reqs[ids.back()];
+    mem.release(r.out_at, r.len);
+    --active;
+    --fifo_head;
+    ids.pop_back();
+    offs.pop_back();
+    lens.pop_back();
+  }
+};
+
 extern "C" {
 
 int lz_serve_create(lz_dev* h, void* d_arena, uint64_t arena_bytes, uint32_t slots, const lz_decode_cfg* cfg,
@@ -2273,12 +2400,20 @@ int lz_serve_create(lz_dev* h, void* d_arena, uint64_t arena_bytes, uint32_t slo
   S->arena_bytes = arena_bytes & ~uint64_t(255);
   S->slots = slots;
   if (cfg) S->cfg = *cfg;
-  S->free_ext[0] = S->arena_bytes;
+  S->mem.reset(S->arena_bytes);
   for (auto& st : S->streams)
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      st = nullptr;
       delete S;
       return lz::fail(LZ_E_HIP, "stream creation failed");
     }
+  if (hipHostMalloc((void**)&S->pin_base, kPinPoolMin, 0) != hipSuccess) {
+    S->pin_base = nullptr;
+    delete S;
+    return lz::fail(LZ_E_NOMEM, "pinned staging pool allocation failed");
+  }
+  S->pin_bytes = kPinPoolMin;
+  S->pin.reset(S->pin_bytes);
   *out = S;
   return 0;
 }
@@ -2286,7 +2421,7 @@ int lz_serve_create(lz_dev* h, void* d_arena, uint64_t arena_bytes, uint32_t slo
 int lz_serve_submit(lz_server* S, uint64_t off, uint64_t len, uint64_t* id) {
   if (!S || !id) return lz::fail(LZ_E_INVAL, "null argument");
   if (off > S->h->v.n || len > S->h->v.n - off) return lz::fail(LZ_E_RANGE, "range outside the archive");
-  if (lz_server::a256(std::max<uint64_t>(len, 1)) > S->arena_bytes)
+  if (Extents::a256(std::max<uint64_t>(len, 1)) > S->arena_bytes)
     return lz::fail(LZ_E_NOMEM, "request of %llu bytes exceeds the arena", (unsigned long long)len);
   lz_server::Req r;
   r.id = S->reqs.size();
@@ -2302,29 +2437,30 @@ int lz_serve_submit(lz_server* S, uint64_t off, uint64_t len, uint64_t* id) {
 int lz_serve_tick(lz_server* S, uint64_t* n_done, uint64_t* n_admitted) {
   if (!S) return lz::fail(LZ_E_INVAL, "null server");
   uint64_t done = 0, admitted = 0;
+  if (n_done) *n_done = 0;
+  if (n_admitted) *n_admitted = 0;
   // 1. retire finished groups
+  int rc_retire = 0;
   for (size_t g = 0; g < S->running.size();) {
     hipError_t q = hipEventQuery(S->running[g].ev);
     if (q == hipErrorNotReady) {
       ++g;
       continue;
     }
-    if (q != hipSuccess) return lz::fail(LZ_E_HIP, "group failed: %s", hipGetErrorString(q));
     auto& G = S->running[g];
-    for (uint64_t id : G.ids) S->reqs[id].state = 2;
-    done += G.ids.size();
-    S->release(G.scratch_at, G.scratch_len);
-    (void)hipEventDestroy(G.ev);
-    lz_range_plan_free(G.plan);
+    if (q != hipSuccess) rc_retire = lz::fail(LZ_E_HIP, "group failed: %s", hipGetErrorString(q));
+    else done += G.ids.size();
+    S->finish_group(G, q == hipSuccess ? 2 : 4);
     S->running.erase(S->running.begin() + g);
   }
+  if (n_done) *n_done = done;
+  if (rc_retire) return rc_retire;
   // 2. admit in arrival order
   std::vector<uint64_t> ids, offs, lens;
-  std::vector<uint64_t> out_at;
   while (S->fifo_head < S->fifo.size() && S->active < S->slots) {
     auto& r = S->reqs[S->fifo[S->fifo_head]];
     uint64_t at;
-    if (!S->alloc(r.len, &at)) break;  // head waits for memory: FIFO order
+    if (!S->mem.alloc(r.len, &at)) break;  // head waits for memory: FIFO order
     r.out_at = at;
     ids.push_back(r.id);
     offs.push_back(r.off);
@@ -2336,52 +2472,95 @@ int lz_serve_tick(lz_server* S, uint64_t* n_done, uint64_t* n_admitted) {
     // 3. one merged plan for everything admitted now; shrink if scratch does not fit
     lz_range_plan* P = nullptr;
     int rc = lz_range_plan_create(S->h, ids.size(), offs.data(), lens.data(), &P);
-    if (rc) return rc;
-    uint64_t sat;
-    if (!S->alloc(P->scratch_bytes, &sat)) {
-      const uint64_t need = lz_server::a256(std::max<uint64_t>(lens.back(), 1)) + lz_server::a256(P->scratch_bytes);
+    if (rc) {
+      while (!ids.empty()) S->unadmit(ids, offs, lens);
+      return rc;
+    }
+    uint64_t sat = 0, pat = 0;
+    const bool got_mem = S->mem.alloc(P->scratch_bytes, &sat);
+    bool got_pin = got_mem && S->pin.alloc(P->staging_bytes, &pat);
+    if (got_mem && !got_pin && S->running.empty() && Extents::a256(P->staging_bytes) > S->pin_bytes) {
+      // the pool is too small for this plan and nothing is in flight: grow it
+      // (freeing pinned memory waits for the device, which is idle here)
+      (void)hipHostFree(S->pin_base);
+      S->pin_base = nullptr;
+      const uint64_t nb = std::max(2 * S->pin_bytes, Extents::a256(P->staging_bytes));
+      if (hipHostMalloc((void**)&S->pin_base, nb, 0) != hipSuccess) {
+        S->pin_base = nullptr;
+        S->pin_bytes = 0;
+        S->pin.reset(0);
+      } else {
+        S->pin_bytes = nb;
+        S->pin.reset(nb);
+      }
+      got_pin = S->pin.alloc(P->staging_bytes, &pat);
+    }
+    if (!got_pin) {
+      if (got_mem) S->mem.release(sat, P->scratch_bytes);
+      const uint64_t need = Extents::a256(std::max<uint64_t>(lens.back(), 1)) + Extents::a256(P->scratch_bytes);
+      // a lone request whose output and scratch exceed the whole arena, or
+      // whose staging the pool could not grow to, can never be served
+      const bool never = ids.size() == 1 && S->running.empty() && (need > S->arena_bytes || got_mem);
       lz_range_plan_free(P);
-      if (ids.size() == 1 && S->running.empty() && need > S->arena_bytes)
-        return lz::fail(LZ_E_NOMEM, "request %llu needs %llu bytes, more than the arena", (unsigned long long)ids[0],
-                        (unsigned long long)need);
-      // give back the newest admission; it waits at the head of the queue
-      auto& r = S->reqs[ids.back()];
-      S->release(r.out_at, r.len);
-      --S->active;
-      --S->fifo_head;
-      ids.pop_back();
-      offs.pop_back();
-      lens.pop_back();
+      if (never) {
+        // nothing else holds memory: this request can never be served
+        auto& r = S->reqs[ids[0]];
+        S->mem.release(r.out_at, r.len);
+        r.state = 4;  // failed; its slot is held until released
+        return lz::fail(LZ_E_NOMEM, "request %llu needs %llu bytes of arena (or its staging the pinned pool), "
+                        "more than there is", (unsigned long long)ids[0], (unsigned long long)need);
+      }
+      S->unadmit(ids, offs, lens);
       continue;
     }
+    P->staging = S->pin_base + pat;
+    P->staging_owned = false;
     std::vector<uint64_t> oo;
     for (uint64_t id : ids) oo.push_back(S->reqs[id].out_at);
     hipStream_t st = S->streams[S->next_stream];
     S->next_stream ^= 1;
-    rc = lz_range_run(S->h, P, S->arena, S->arena_bytes, oo.data(), S->arena + sat, P->scratch_bytes, &S->cfg, st);
-    if (rc) {
-      S->release(sat, P->scratch_bytes);
-      lz_range_plan_free(P);
+    hipEvent_t ev = nullptr;
+    if (!S->ev_free.empty()) {
+      ev = S->ev_free.back();
+      S->ev_free.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      ev = nullptr;
+    }
+    rc = ev ? lz_range_run(S->h, P, S->arena, S->arena_bytes, oo.data(), S->arena + sat, P->scratch_bytes, &S->cfg, st)
+            : lz::fail(LZ_E_HIP, "event creation failed");
+    if (rc == 0 && hipEventRecord(ev, st) != hipSuccess) {
+      // the work is enqueued but cannot be tracked: wait for it here
+      rc = (hipStreamSynchronize(st) == hipSuccess) ? 0 : lz::fail(LZ_E_HIP, "event record and stream sync failed");
+      lz_server::Group G{ev, P, sat, P->scratch_bytes, pat, P->staging_bytes, ids};
+      for (uint64_t id : ids) S->reqs[id].state = 1;
+      S->finish_group(G, rc == 0 ? 2 : 4);
+      if (n_admitted) *n_admitted = ids.size();
       return rc;
     }
-    lz_server::Group G;
-    if (hipEventCreateWithFlags(&G.ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(G.ev, st) != hipSuccess)
-      return lz::fail(LZ_E_HIP, "event failed");
-    G.plan = P;
-    G.scratch_at = sat;
-    G.scratch_len = P->scratch_bytes;
-    G.ids = ids;
+    if (rc) {
+      // nothing of this group reached the device after a failed launch call;
+      // wait for what did, then give everything back
+      (void)hipStreamSynchronize(st);
+      if (ev) S->ev_free.push_back(ev);
+      S->mem.release(sat, P->scratch_bytes);
+      S->pin.release(pat, P->staging_bytes);
+      lz_range_plan_free(P);
+      while (!ids.empty()) S->unadmit(ids, offs, lens);
+      return rc;
+    }
+    lz_server::Group G{ev, P, sat, P->scratch_bytes, pat, P->staging_bytes, ids};
     for (uint64_t id : ids) S->reqs[id].state = 1;
     S->running.push_back(std::move(G));
     admitted += ids.size();
     break;
   }
-  if (n_done) *n_done = done;
+  S->max_running = std::max<uint64_t>(S->max_running, S->running.size());
   if (n_admitted) *n_admitted = admitted;
   return 0;
 }
 
-// State of a request: 0 waiting, 1 running, 2 done; *d_ptr its output when done.
+// State of a request: 0 waiting, 1 running, 2 done, 3 released, 4 failed;
+// *d_ptr its output when done.
 int lz_serve_status(lz_server* S, uint64_t id, int* state, uint8_t** d_ptr) {
   if (!S || id >= S->reqs.size() || !state) return lz::fail(LZ_E_INVAL, "bad request id");
   *state = S->reqs[id].state;
@@ -2389,10 +2568,11 @@ int lz_serve_status(lz_server* S, uint64_t id, int* state, uint8_t** d_ptr) {
   return 0;
 }
 
-// Frees a done request's output.
+// Frees a done request's output (or the slot of a failed one).
 int lz_serve_release(lz_server* S, uint64_t id) {
-  if (!S || id >= S->reqs.size() || S->reqs[id].state != 2) return lz::fail(LZ_E_INVAL, "request not done");
-  S->release(S->reqs[id].out_at, S->reqs[id].len);
+  if (!S || id >= S->reqs.size() || (S->reqs[id].state != 2 && S->reqs[id].state != 4))
+    return lz::fail(LZ_E_INVAL, "request not done");
+  if (S->reqs[id].state == 2) S->mem.release(S->reqs[id].out_at, S->reqs[id].len);
   S->reqs[id].state = 3;
   --S->active;
   return 0;
@@ -2403,19 +2583,20 @@ void lz_serve_stats(const lz_server* S, uint64_t* waiting, uint64_t* running_gro
   if (!S) return;
   if (waiting) *waiting = S->fifo.size() - S->fifo_head;
   if (running_groups) *running_groups = S->running.size();
-  if (arena_used) *arena_used = S->used;
-  if (arena_high_water) *arena_high_water = S->high_water;
+  if (arena_used) *arena_used = S->mem.used;
+  if (arena_high_water) *arena_high_water = S->mem.high_water;
 }
+
+uint64_t lz_serve_max_running(const lz_server* S) { return S ? S->max_running : 0; }
 
 int lz_serve_destroy(lz_server* S) {
   if (!S) return 0;
   for (auto& G : S->running) {
     (void)hipEventSynchronize(G.ev);
-    (void)hipEventDestroy(G.ev);
+    S->ev_free.push_back(G.ev);
     lz_range_plan_free(G.plan);
   }
-  for (auto& st : S->streams)
-    if (st) (void)hipStreamDestroy(st);
+  S->running.clear();
   delete S;
   return 0;
 }

@@ -90,6 +90,7 @@ def lib():
             "lz_range_plan_levels": (_u64, [_vp]),
             "lz_range_plan_closure_bytes": (_u64, [_vp]),
             "lz_range_plan_prefix_bytes": (_u64, [_vp]),
+            "lz_range_plan_horizon": (_u64, [_vp]),
             "lz_range_plan_free": (None, [_vp]),
             "lz_range_run": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
             "lz_range_scratch_bytes": (ctypes.c_int, [_vp, _u64, _u64, _p64]),
@@ -107,6 +108,7 @@ def lib():
             "lz_serve_status": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_vp)]),
             "lz_serve_release": (ctypes.c_int, [_vp, _u64]),
             "lz_serve_stats": (None, [_vp, _p64, _p64, _p64, _p64]),
+            "lz_serve_max_running": (_u64, [_vp]),
             "lz_serve_destroy": (ctypes.c_int, [_vp]),
             "lz_block_features": (ctypes.c_int, [_vp, _u64, _vp, _vp]),
             "lz_block_stats": (ctypes.c_int, [_vp, _u64, _vp, _vp, _vp, _vp]),
@@ -392,6 +394,7 @@ class RangePlan:
         self.levels = int(lib().lz_range_plan_levels(p))
         self.closure_bytes = int(lib().lz_range_plan_closure_bytes(p))
         self.prefix_bytes = int(lib().lz_range_plan_prefix_bytes(p))
+        self.horizon = int(lib().lz_range_plan_horizon(p))
 
     def run(self, out, out_offs, scratch, G=64, unroll=2, stream=None):
         """Enqueues the plan; range i lands at out[out_offs[i]:+lens[i]]."""
@@ -555,7 +558,8 @@ class Server:
     def stats(self):
         w, r, u, hw = _u64(), _u64(), _u64(), _u64()
         lib().lz_serve_stats(self.s, ctypes.byref(w), ctypes.byref(r), ctypes.byref(u), ctypes.byref(hw))
-        return {"waiting": w.value, "running_groups": r.value, "arena_used": u.value, "arena_high_water": hw.value}
+        return {"waiting": w.value, "running_groups": r.value, "arena_used": u.value, "arena_high_water": hw.value,
+                "max_running_groups": int(lib().lz_serve_max_running(self.s))}
 
     def destroy(self):
         if getattr(self, "s", None):

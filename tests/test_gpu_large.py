@@ -1,0 +1,95 @@
+"""Outputs above 4 GiB: the high byte plane of the sources, the 16-bit high
+fields of the device match records and gathers past 2^32 are compared with
+the oracle.  A 4.38 GB token stream (geometric match lengths of mean 256,
+sources uniform over everything at least 64 KiB back, so most matches past
+2^32 read below it) gets a few planted matches: sources whose span straddles
+2^32 and a period-3 self-overlapping match cut at 2^32.  The whole decode,
+ranges around and across 2^32 and a served request are checked byte by byte
+and by FNV-1a 64 against the oracle's execution of the same tokens."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2607_18541_amd import lz
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+B32 = 1 << 32
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _stream():
+    n = B32 + (384 << 20)
+    ll, ml, sr, lit = synth.geo_tokens(n, 256, seed=41)
+    ml = ml.copy()
+    sr = sr.copy()
+    mstart = np.concatenate([[0], np.cumsum(ll.astype(np.int64) + ml)[:-1]]) + ll
+    # sources straddling 2^32, for matches written well above it
+    far = np.nonzero((mstart > B32 + (64 << 20)) & (ml >= 32))[0][:16:2]
+    for t in far:
+        sr[t] = B32 - int(ml[t]) // 2
+    # a self-overlapping match (period 3) whose output crosses 2^32
+    t = int(np.nonzero(mstart + ml > B32)[0][0])
+    if mstart[t] >= B32 - 8:  # make it start below 2^32
+        t -= 1
+    assert mstart[t] < B32 < mstart[t] + ml[t] or mstart[t] + ml[t] <= B32
+    sr[t] = mstart[t] - 3
+    return n, ll, ml, sr, lit, far, int(mstart[t])
+
+
+def test_decode_above_4gib_matches_oracle():
+    dev = _dev()
+    n, ll, ml, sr, lit, far, per_at = _stream()
+    print("building the 4.38 GB stream and its oracle output", flush=True)
+    x = oracle.exec_tokens(n, ll, ml, sr, lit)
+    arc = lz.build_archive(n, 16, ll, ml, sr, lit)
+    assert lz.archive_info(arc)["n"] == n
+    assert np.array_equal(oracle.decode(arc), x), "the oracle's reader disagrees with its token execution"
+    x_fnv = oracle.fnv1a64(x)
+    da = lz.DeviceArchive(arc, device=dev)
+    print("device archive: %d depths" % da.levels, flush=True)
+    exp = torch.from_numpy(x).to(dev)
+    out = da.decode()
+    torch.cuda.synchronize()
+    assert torch.equal(out, exp), "whole decode differs from the oracle"
+    host = out.cpu().numpy()
+    assert lz.fnv1a64(host) == x_fnv
+    del host, out
+    torch.cuda.empty_cache()
+    # ranges around and across 2^32, near the planted matches, and random ones
+    rng = np.random.default_rng(42)
+    cases = [(B32 - 1, 2), (B32 - 5000, 10000), (B32, 1), (B32 - (1 << 20), 2 << 20), (n - 1, 1), (n - (3 << 20), 3 << 20),
+             (per_at - 4, 64), (B32 - 17, 33), (0, 4096)]
+    for t in far[:4]:
+        a = int(np.concatenate([[0], np.cumsum(ll[:t].astype(np.int64) + ml[:t])])[-1] + ll[t])
+        cases.append((a - 10, int(ml[t]) + 20))
+    for _ in range(30):
+        L = int(np.exp(rng.uniform(np.log(16), np.log(4 << 20))))
+        o = int(rng.integers(B32 - (512 << 20), n - L))
+        cases.append((o, L))
+    for o, L in cases:
+        print("range %d +%d" % (o, L), flush=True)
+        got = da.decode_range(o, L)
+        torch.cuda.synchronize()
+        assert torch.equal(got, exp[o:o + L]), (o, L)
+    # one request through the server, across 2^32
+    srv = lz.Server(da, 6 << 30, slots=4)
+    o, L = B32 - (3 << 20), 5 << 20
+    rid = srv.submit(o, L)
+    for _ in range(100000):
+        srv.tick()
+        if srv.status(rid)[0] == 2:
+            break
+    got = srv.result(rid, L)
+    assert torch.equal(got, exp[o:o + L])
+    assert lz.fnv1a64(got.cpu().numpy()) == oracle.fnv1a64(x[o:o + L])
+    srv.release(rid)
+    srv.destroy()
+    da.close()

@@ -17,6 +17,25 @@ def _dev():
     return torch.device("cuda:0")
 
 
+def horizon_by_definition(tk, first, end, log2_grain=20):
+    """The decode horizon of output [first, end), straight from its definition:
+    the largest multiple h of the grain (2^20 bytes) at or below `first` such
+    that no match written in [h, end of the grain holding end - 1) reads a
+    byte below h; searched one grain at a time from the top."""
+    grain = 1 << log2_grain
+    g_end = ((end - 1) // grain + 1) * grain
+    m = tk["mlen"] > 0
+    mdst = (tk["dst"] + tk["lit_len"])[m].astype(np.int64)
+    msrc = tk["src"][m].astype(np.int64)
+    h = (first // grain) * grain
+    while h > 0:
+        sel = (mdst >= h) & (mdst < g_end)
+        if not sel.any() or msrc[sel].min() >= h:
+            return h
+        h -= grain
+    return 0
+
+
 def _ranges(n, bs, rng, k=40):
     r = [(0, 1), (0, n), (n - 1, 1), (n - 7, 7), (bs - 3, 9), (2 * bs - 1, bs + 2), (n // 2, 0)]
     for _ in range(k):
@@ -105,12 +124,70 @@ def test_range_plan_modes():
     x = synth.fastq(8 << 20, seed=5)
     da = lz.DeviceArchive(lz.encode(x, 16, lz.TUNED_THR), device=dev)
     p = da.range_plan([6 << 20, 1 << 20], [16 << 10, 1 << 20])
-    assert p.prefix_bytes == (6 << 20) + (16 << 10) and p.closure_bytes == 0
+    assert p.closure_bytes == 0 and p.prefix_bytes == (6 << 20) + (16 << 10) - p.horizon
+    assert p.horizon == horizon_by_definition(oracle.tokens(da.arc), 1 << 20, (6 << 20) + (16 << 10))
     out = torch.zeros((17 << 16) + (1 << 20), dtype=torch.uint8, device=dev)
     scratch = torch.empty(p.scratch_bytes, dtype=torch.uint8, device=dev)
     p.run(out, np.array([0, 16 << 10], np.uint64), scratch)
     torch.cuda.synchronize()
     assert bytes(out[:16 << 10].cpu().numpy()) == bytes(x[6 << 20:(6 << 20) + (16 << 10)])
     assert bytes(out[16 << 10:(16 << 10) + (1 << 20)].cpu().numpy()) == bytes(x[1 << 20:2 << 20])
+    p.free()
+    da.close()
+
+
+@pytest.mark.parametrize("segment_mib", [0, 4])
+def test_range_prefix_horizon(segment_mib):
+    """Prefix plans start at the decode horizon: on an archive encoded in
+    4 MiB segments that is the segment start, so a seek decodes at most the
+    segment up to its range; without segments it is what the sources allow.
+    The horizon equals its definition computed from the oracle's tokens, and
+    every range equals the oracle's decode, alone and merged."""
+    dev = _dev()
+    x = synth.fastq(24 << 20, seed=11)
+    arc = lz.encode(x, 16, lz.TUNED_THR, segment=segment_mib << 20)
+    expect = oracle.decode(arc)
+    assert np.array_equal(expect, x)
+    tk = oracle.tokens(arc)
+    da = lz.DeviceArchive(arc, device=dev)
+    n = da.n
+    exp_t = torch.from_numpy(expect).to(dev)
+    rng = np.random.default_rng(7)
+    cases = [((4 << 20) - 5, 10), ((4 << 20), 3 << 20), ((13 << 20) + 12345, 2 << 20), (n - (2 << 20), 2 << 20),
+             ((8 << 20) + 1, 1 << 20)]
+    cases += [(int(rng.integers(0, n - (3 << 20))), int(rng.integers(1 << 20, 3 << 20))) for _ in range(8)]
+    prefix_plans = 0
+    for o, L in cases:
+        print(f"[horizon seg={segment_mib}] range {o} +{L}", flush=True)
+        p = da.range_plan([o], [L])
+        if p.prefix_bytes:
+            prefix_plans += 1
+            h = horizon_by_definition(tk, o, o + L)
+            assert p.horizon == h, (o, L, p.horizon, h)
+            assert p.prefix_bytes == o + L - h
+            if segment_mib:
+                assert h >= (o // (segment_mib << 20)) * (segment_mib << 20)
+                assert p.scratch_bytes < (segment_mib << 21)
+        out = torch.full((L + 16,), 0xA5, dtype=torch.uint8, device=dev)
+        scratch = torch.empty(p.scratch_bytes, dtype=torch.uint8, device=dev)
+        p.run(out, np.zeros(1, np.uint64), scratch)
+        torch.cuda.synchronize()
+        assert torch.equal(out[:L], exp_t[o:o + L]), (o, L)
+        assert bool((out[L:] == 0xA5).all().item())
+        p.free()
+    assert prefix_plans >= 5
+    # merged: the horizon of the lowest range start serves every range
+    offs = [o for o, L in cases[:6]]
+    lens = [L for o, L in cases[:6]]
+    p = da.range_plan(offs, lens)
+    oo = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
+    out = torch.empty(int(sum(lens)), dtype=torch.uint8, device=dev)
+    scratch = torch.empty(p.scratch_bytes, dtype=torch.uint8, device=dev)
+    p.run(out, oo, scratch)
+    torch.cuda.synchronize()
+    if p.prefix_bytes:
+        assert p.horizon == horizon_by_definition(tk, min(offs), max(o + L for o, L in zip(offs, lens)))
+    for (o, L), q in zip(zip(offs, lens), oo):
+        assert torch.equal(out[int(q):int(q) + L], exp_t[o:o + L]), ("merged", o, L)
     p.free()
     da.close()

@@ -75,3 +75,72 @@ def test_serve_rejects_oversized_and_out_of_range():
     assert bytes(srv.result(rid, 1000).cpu().numpy()) == bytes(x[100:1100])
     srv.release(rid)
     srv.destroy()
+
+
+def test_serve_groups_overlap_on_device():
+    """Requests arriving one per tick each become a group; with horizon-bounded
+    prefix decodes (an archive encoded in 8 MiB segments) the scratch of a
+    group is at most a segment, so several groups fit the arena at once and
+    a new one is launched while earlier ones still run: at least two groups
+    are in flight at some tick.  Every result equals the range decoded alone
+    and the input bytes."""
+    dev = _dev()
+    x = synth.fastq(64 << 20, seed=8)
+    da = lz.DeviceArchive(lz.encode(x, 16, lz.TUNED_THR, segment=8 << 20), device=dev)
+    n = da.n
+    k = 48
+    lens = synth.loguniform(k, 2 << 20, 8 << 20, 19).astype(np.int64)
+    offs = (synth.uniform(k, 20) * (n - lens)).astype(np.int64)
+    srv = lz.Server(da, 512 << 20, slots=64)
+    seen_running = 0
+    rids = []
+    for i in range(k):
+        rids.append(srv.submit(int(offs[i]), int(lens[i])))
+        srv.tick()
+        seen_running = max(seen_running, srv.stats()["running_groups"])
+    t_end = time.time() + 60
+    while time.time() < t_end and any(srv.status(r)[0] != 2 for r in rids):
+        srv.tick()
+    st = srv.stats()
+    print("max groups in flight: seen %d, server %d; arena high water %d" %
+          (seen_running, st["max_running_groups"], st["arena_high_water"]), flush=True)
+    assert seen_running >= 2 and st["max_running_groups"] >= 2
+    for i, r in enumerate(rids):
+        assert srv.status(r)[0] == 2, i
+        got = srv.result(r, int(lens[i])).clone()
+        assert bytes(got.cpu().numpy()) == bytes(x[int(offs[i]):int(offs[i]) + int(lens[i])]), i
+        alone = da.decode_range(int(offs[i]), int(lens[i]))
+        assert torch.equal(got, alone), i
+        srv.release(r)
+    assert srv.stats()["arena_used"] == 0
+    srv.destroy()
+
+
+def test_serve_never_fitting_request_fails_cleanly():
+    """A request whose output plus plan scratch exceeds the arena is marked
+    failed (state 4) by the tick that meets it, which reports LZ_E_NOMEM; its
+    memory is returned at once and its slot on release, and later requests
+    are served normally."""
+    dev = _dev()
+    x = synth.fastq(6 << 20, seed=9)
+    da = lz.DeviceArchive(lz.encode(x, 16, lz.TUNED_THR), device=dev)
+    n = da.n
+    srv = lz.Server(da, 3 << 20, slots=2)
+    big = srv.submit(n - (2 << 20), 2 << 20)  # a prefix decode of ~n bytes of scratch cannot fit 3 MiB
+    with pytest.raises(lz.LzError) as e:
+        for _ in range(10):
+            srv.tick()
+    assert e.value.rc == lz.LZ_E_NOMEM
+    assert srv.status(big)[0] == 4
+    assert srv.stats()["arena_used"] == 0
+    srv.release(big)
+    assert srv.status(big)[0] == 3
+    rid = srv.submit(100, 1000)
+    for _ in range(1000):
+        srv.tick()
+        if srv.status(rid)[0] == 2:
+            break
+    assert bytes(srv.result(rid, 1000).cpu().numpy()) == bytes(x[100:1100])
+    srv.release(rid)
+    assert srv.stats()["arena_used"] == 0
+    srv.destroy()
