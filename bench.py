@@ -87,7 +87,7 @@ def time_stages(torch, da, out, G, U, sched, steps):
 def source_digest():
     import hashlib
     h = hashlib.sha256()
-    for f in ("lz_device.hip", "lz_internal.h"):
+    for f in ("lz_device.hip", "lz_internal.h", "lz_host.cpp"):
         with open(os.path.join(ROOT, "paper_2607_18541_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -112,7 +112,7 @@ def measured_traffic(kernels):
     return int(sum(k["traffic_bytes_per_decode"] for k in got if k))
 
 
-def traffic_from_counters(fetch_csv, write_csv, steps, n, command):
+def traffic_from_counters(fetch_csv, write_csv, steps, n, command, depth_passes=1):
     """Writes the traffic summary from two rocprofv3 --pmc runs of
     `bench.py --profile-run` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).
     Each counter is scaled by what it reads for the calibration kernel of the
@@ -143,7 +143,8 @@ def traffic_from_counters(fetch_csv, write_csv, steps, n, command):
                       "fetch_bytes_per_decode": round(fetch[k][1] * fs / steps),
                       "write_bytes_per_decode": round(write[k][1] * ws / steps),
                       "traffic_bytes_per_decode": round((fetch[k][1] * fs + write[k][1] * ws) / steps)}
-    out = {"source_sha256": source_digest(), "workload": "FASTQ-like 1 GiB, 12/16/24/32", "steps": steps,
+    out = {"source_sha256": source_digest(),
+           "workload": "FASTQ-like 1 GiB, 12/16/24/32, %d depth-aware encoder passes" % depth_passes, "steps": steps,
            "fetch_scale": round(fs, 4), "write_scale": round(ws, 4), "command": command, "kernels": kernels}
     with open(TRAFFIC_JSON, "w") as fh:
         json.dump(out, fh, indent=1)
@@ -269,7 +270,7 @@ def run_fastq(args, torch, lz):
     for name, thr in (("base", lz.BASE_THR), ("tuned", lz.TUNED_THR)):
         t0 = time.perf_counter()
         log("encoding %s %s" % (name, thr))
-        arc = lz.encode(x, args.log2_bs, thr, lz.BOUNDS_CFG, max_chain=args.max_chain)
+        arc = lz.encode(x, args.log2_bs, thr, lz.BOUNDS_CFG, max_chain=args.max_chain, depth_passes=args.depth_passes)
         enc_s = time.perf_counter() - t0
         log("encoded %s: %d B archive in %.1fs" % (name, arc.size, enc_s))
         info = lz.archive_info(arc)
@@ -344,6 +345,7 @@ def run_fastq(args, torch, lz):
                         % (n, args.G),
             "n_bytes": n, "log2_bs": args.log2_bs, "G": args.G, "unroll": args.unroll,
             "schedule": args.schedule, "bounds": list(lz.BOUNDS_CFG), "max_chain": args.max_chain,
+            "depth_passes": args.depth_passes,
         },
         "detail": {
             "tuned_gbps": round(t["gbps"], 3), "base_gbps": round(b["gbps"], 3),
@@ -405,7 +407,7 @@ def run_profile(args, torch, lz):
     x = synth.fastq(args.size, seed=3)
     n = int(x.size)
     log("encoding")
-    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain)
+    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain, depth_passes=args.depth_passes)
     da = lz.DeviceArchive(arc, device=dev)
     out = torch.empty(n, dtype=torch.uint8, device=dev)
     for i in range(args.steps):
@@ -454,7 +456,7 @@ def run_batch(args, torch, lz):
         sz = int(sz)
         x = synth.zipf_text(sz, seed=4000 + i) if i % 2 == 0 else synth.fastq(sz, seed=4000 + i)
         thr = (lz.BASE_THR, lz.TUNED_THR)[(i // 2) % 2]
-        arc = lz.encode(x, args.log2_bs, thr, lz.BOUNDS_CFG, max_chain=args.max_chain)
+        arc = lz.encode(x, args.log2_bs, thr, lz.BOUNDS_CFG, max_chain=args.max_chain, depth_passes=args.depth_passes)
         da = lz.DeviceArchive(arc, device=dev)
         das.append(da)
         outs.append(torch.empty(max(da.n, 1), dtype=torch.uint8, device=dev))
@@ -531,7 +533,7 @@ def run_serve(args, torch, lz):
     n = int(x.size)
     log("generated %d B in %.0fs" % (n, time.perf_counter() - t0))
     seg = args.segment_mib << 20 if args.segment_mib >= 0 else ((1 << 30) if n > (3 << 30) else 0)
-    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain, segment=seg,
+    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain, depth_passes=args.depth_passes, segment=seg,
                     progress=lambda d, t: log("encoded %d of %d input bytes" % (d, t)))
     log("encoded: %d B archive (ratio %.3f) in %.0fs" % (arc.size, n / arc.size, time.perf_counter() - t0))
     da = lz.DeviceArchive(arc, device=dev)
@@ -718,7 +720,7 @@ def run_seek(args, torch, lz):
     x = synth.fastq(args.size, seed=3)
     n = int(x.size)
     seg = max(args.segment_mib, 0) << 20
-    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain, segment=seg)
+    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain, depth_passes=args.depth_passes, segment=seg)
     da = lz.DeviceArchive(arc, device=dev)
     rows = []
     st = torch.cuda.current_stream()
@@ -788,7 +790,7 @@ def run_ablate(args, torch, lz):
     tuned_gbps = None
     for name, thr, bounds, bname in variants:
         log("encoding %s, %s bands" % (name, bname))
-        arc = lz.encode(x, args.log2_bs, thr, bounds, max_chain=args.max_chain)
+        arc = lz.encode(x, args.log2_bs, thr, bounds, max_chain=args.max_chain, depth_passes=args.depth_passes)
         info = lz.archive_info(arc)
         ent, _ = lz.entropy_size(arc)
         da = lz.DeviceArchive(arc, device=dev)
@@ -855,6 +857,8 @@ def main():
     ap.add_argument("--unroll", type=int, default=2)
     ap.add_argument("--schedule", type=int, default=1)
     ap.add_argument("--max-chain", dest="max_chain", type=int, default=32)
+    ap.add_argument("--depth-passes", dest="depth_passes", type=int, default=1,
+                    help="encoder: depth-aware tie-break passes (0 = nearest source on ties)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep-points", action="store_true",
                     help="fastq: skip the generated-stream points at mean match length 256 and 1024")
@@ -867,7 +871,7 @@ def main():
     if args.traffic_from:
         n = len(__import__("synth").fastq(args.size, seed=3))
         print(json.dumps(traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.steps, n,
-                                               args.command)))
+                                               args.command, args.depth_passes)))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; multi-GPU runs are not part of this build", file=sys.stderr)

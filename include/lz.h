@@ -75,10 +75,18 @@ typedef struct lz_params {
    * the input bytes done so far and the total; user is passed through */
   void (*progress)(uint64_t done, uint64_t total, void* user);
   void* progress_user;
+  /* Tie-break among equally long valid candidates (lengths never change):
+   * 0 = the nearest source; k = 1..8 = k further parses in which the source
+   * with the lowest resulting dependency depth (1 + the deepest byte it reads,
+   * as in lz_plan) wins, then the nearest.  Blocks are parsed in parallel, so
+   * a pass takes the depths of earlier blocks from the parse before it and
+   * those of its own block from itself. */
+  uint32_t depth_passes;
 } lz_params;
 
 /* Fills the defaults: 64 KiB blocks, thresholds 6/8/10/12, bounds 4 KiB /
- * 64 KiB / 1 MiB, max_chain 32, all threads, whole-prefix window. */
+ * 64 KiB / 1 MiB, max_chain 32, all threads, whole-prefix window, one
+ * depth-aware parse (depth_passes 1). */
 int lz_params_default(lz_params* p);
 
 /* Greedy LZ77 parse of in[0,n) with per-class thresholds (Sec. 4.2) into a

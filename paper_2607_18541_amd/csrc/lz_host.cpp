@@ -438,7 +438,12 @@ struct EncCtx {
   const uint32_t* thr_block;  // per block tuple or null
   HashIndex near_idx, far_idx;
   uint64_t seg;  // unused: positions are segment-relative
+  // Depth-aware ties: dependency depth of every segment position as the
+  // previous parse left it (null = ties go to the nearest source).
+  const uint16_t* dep = nullptr;
 };
+
+constexpr uint32_t kDepthMax = 0xFFFF;
 
 // Greedy parse of one block into tokens + its literal bytes.
 static void parse_block(const EncCtx& c, uint64_t b, std::vector<BTok>& toks, std::vector<uint8_t>& lit) {
@@ -455,8 +460,48 @@ static void parse_block(const EncCtx& c, uint64_t b, std::vector<BTok>& toks, st
   toks.clear();
   lit.clear();
   lit.reserve(end - start);
+  // Depth-aware ties (reading 4 of the tie-break among equal lengths): the
+  // resulting depth of a candidate is 1 + the deepest byte it reads (its own
+  // output excluded); bytes of this block take the depths of this parse,
+  // earlier bytes those of the previous parse.  Lower depth wins, then the
+  // nearer source; lengths are unchanged.
+  const bool deep = c.dep != nullptr;
+  std::vector<uint16_t> dl;
+  if (deep) dl.assign(end - start, 0);
+  auto cand_depth = [&](uint64_t src, uint64_t L, uint64_t at) -> uint32_t {
+    const uint64_t e = std::min(src + L, at);
+    uint32_t m = 0;
+    uint64_t q = src;
+    for (const uint64_t e1 = std::min(e, start); q < e1; ++q) m = std::max<uint32_t>(m, c.dep[q]);
+    for (; q < e; ++q) m = std::max<uint32_t>(m, dl[q - start]);
+    return std::min<uint32_t>(m + 1, kDepthMax);
+  };
   while (pos < end) {
     uint64_t best_len = 0, best_src = 0;
+    uint32_t best_dep = 0;
+    // a candidate of cl's class matching L bytes from src: keep the longest,
+    // then (depth-aware) the shallowest, then the nearest
+    auto consider = [&](uint64_t src, uint64_t L) {
+      if (L > best_len) {
+        best_len = L;
+        best_src = src;
+        if (deep) best_dep = cand_depth(src, L, pos);
+      } else if (L == best_len && L) {
+        if (deep) {
+          const uint32_t d = cand_depth(src, L, pos);
+          if (d < best_dep || (d == best_dep && src > best_src)) {
+            best_src = src;
+            best_dep = d;
+          }
+        } else if (src > best_src) {
+          best_src = src;
+        }
+      }
+    };
+    // the walk can stop once nothing better is possible: the longest match
+    // reaches the block end or is long enough, and (depth-aware) reads only
+    // literals
+    auto done = [&]() { return (pos + best_len == end || best_len >= nice) && (!deep || best_dep <= 1); };
     if (pos + 4 < end) {
       __builtin_prefetch(&c.near_idx.prev[pos + 4]);
       __builtin_prefetch(&c.far_idx.prev[pos + 4]);
@@ -480,17 +525,16 @@ static void parse_block(const EncCtx& c, uint64_t b, std::vector<BTok>& toks, st
         }
         uint64_t L = match_len(x, src, pos, end);
         int cl = dclass(d, bound);
-        if (L >= thr[cl] && (L > best_len || (L == best_len && src > best_src))) {
-          best_len = L;
-          best_src = src;
-          if (pos + L == end || L >= nice) break;
+        if (L >= thr[cl]) {
+          consider(src, L);
+          if (done()) break;
         }
         if (maxc && ++steps >= maxc) break;
         link = uint32_t(e);
       }
     }
     // far chain: any distance
-    if (pos + kf <= end && best_len < end - pos && best_len < nice) {
+    if (pos + kf <= end && !done()) {
       const uint64_t e0 = c.far_idx.prev[pos];
       const uint64_t fp = e0 & 0xFFFFFFFF00000000ull;
       uint32_t link = uint32_t(e0);
@@ -506,10 +550,9 @@ static void parse_block(const EncCtx& c, uint64_t b, std::vector<BTok>& toks, st
         }
         uint64_t L = match_len(x, src, pos, end);
         int cl = dclass(d, bound);
-        if (L >= thr[cl] && (L > best_len || (L == best_len && src > best_src))) {
-          best_len = L;
-          best_src = src;
-          if (pos + L == end || L >= nice) break;
+        if (L >= thr[cl]) {
+          consider(src, L);
+          if (done()) break;
         }
         if (maxc && ++steps >= maxc) break;
         link = uint32_t(e);
@@ -518,6 +561,7 @@ static void parse_block(const EncCtx& c, uint64_t b, std::vector<BTok>& toks, st
     if (best_len) {
       toks.push_back(BTok{run, best_len, best_src});
       run = 0;
+      if (deep) std::fill(dl.begin() + (pos - start), dl.begin() + (pos - start + best_len), (uint16_t)best_dep);
       pos += best_len;
     } else {
       lit.push_back(x[pos]);
@@ -539,6 +583,7 @@ static int check_params(const lz_params* p, uint64_t n) {
   if (p->segment && (p->segment % bs)) return fail(LZ_E_INVAL, "segment must be a multiple of the block size");
   if (p->segment > 0xFFFFFFFFull - 16) return fail(LZ_E_INVAL, "segment must be below 4 GiB");
   if (!p->segment && n > 0xFFFFFFFFull - 16) return fail(LZ_E_INVAL, "inputs of 4 GiB or more need a segment");
+  if (p->depth_passes > 8) return fail(LZ_E_INVAL, "depth_passes must be at most 8");
   return 0;
 }
 
@@ -583,16 +628,41 @@ static int encode_impl(const uint8_t* in, uint64_t n, const lz_params* p, const 
       build_index(c.x, 0, c.n, kn, idx_threads, c.near_idx, bits);
       build_index(c.x, 0, c.n, kf, idx_threads, c.far_idx, bits);
       uint64_t b0 = s0 / bs, b1 = (s1 + bs - 1) / bs;
-      parallel_for(b1 - b0, threads, [&](uint64_t i, unsigned) {
-        std::vector<BTok> toks;
-        BlockEnc& e = blocks[b0 + i];
-        parse_block(c, i, toks, e.lit);
-        for (auto& t : toks)
-          if (t.mlen) t.src += s0;
-        // tokens are parked in e.slo until min_match is known
-        e.slo.resize(toks.size() * sizeof(BTok));
-        memcpy(e.slo.data(), toks.data(), toks.size() * sizeof(BTok));
-      });
+      HugeArray<uint16_t> dep;  // byte depths of the previous parse (depth-aware passes)
+      for (uint32_t pass = 0; pass <= p->depth_passes; ++pass) {
+        if (pass > 0) {
+          // dependency depth of every segment byte under the last parse, in
+          // output order: literals 0, a match 1 + the deepest byte it reads
+          if (!dep.p) dep.assign_zero(s1 - s0);
+          for (uint64_t i = 0; i < b1 - b0; ++i) {
+            const BlockEnc& e = blocks[b0 + i];
+            const BTok* tk = (const BTok*)e.slo.data();
+            uint64_t q = i * bs;
+            for (size_t j = 0; j < e.slo.size() / sizeof(BTok); ++j) {
+              for (uint64_t r = 0; r < tk[j].lit_len; ++r) dep[q + r] = 0;
+              q += tk[j].lit_len;
+              if (!tk[j].mlen) continue;
+              const uint64_t a = tk[j].src - s0, z = std::min(a + tk[j].mlen, q);
+              uint32_t m = 0;
+              for (uint64_t r = a; r < z; ++r) m = std::max<uint32_t>(m, dep[r]);
+              const uint16_t d = (uint16_t)std::min<uint32_t>(m + 1, kDepthMax);
+              for (uint64_t r = 0; r < tk[j].mlen; ++r) dep[q + r] = d;
+              q += tk[j].mlen;
+            }
+          }
+          c.dep = dep.p;
+        }
+        parallel_for(b1 - b0, threads, [&](uint64_t i, unsigned) {
+          std::vector<BTok> toks;
+          BlockEnc& e = blocks[b0 + i];
+          parse_block(c, i, toks, e.lit);
+          for (auto& t : toks)
+            if (t.mlen) t.src += s0;
+          // tokens are parked in e.slo until min_match is known
+          e.slo.resize(toks.size() * sizeof(BTok));
+          memcpy(e.slo.data(), toks.data(), toks.size() * sizeof(BTok));
+        });
+      }
       if (p->progress) p->progress(s1, n, p->progress_user);
     }
   } catch (const std::bad_alloc&) {
@@ -632,6 +702,7 @@ int lz_params_default(lz_params* p) {
   p->max_chain = 32;
   p->n_threads = 0;
   p->segment = 0;
+  p->depth_passes = 1;
   return 0;
 }
 

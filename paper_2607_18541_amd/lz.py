@@ -38,7 +38,8 @@ PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_
 
 class Params(ctypes.Structure):
     _fields_ = [("log2_bs", _u32), ("thr", _u32 * 4), ("bound", _u64 * 3), ("max_chain", _u32),
-                ("n_threads", _u32), ("segment", _u64), ("progress", PROGRESS_FN), ("progress_user", ctypes.c_void_p)]
+                ("n_threads", _u32), ("segment", _u64), ("progress", PROGRESS_FN), ("progress_user", ctypes.c_void_p),
+                ("depth_passes", _u32)]
 
 
 class Info(ctypes.Structure):
@@ -149,7 +150,7 @@ def default_threads():
     return min(os.cpu_count() or 1, 16)
 
 
-def params(log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0):
+def params(log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0, depth_passes=1):
     if not n_threads:
         n_threads = default_threads()
     p = Params()
@@ -162,14 +163,18 @@ def params(log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=
     p.max_chain = max_chain
     p.n_threads = n_threads
     p.segment = segment
+    p.depth_passes = depth_passes
     return p
 
 
-def encode(x, log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0, progress=None):
+def encode(x, log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0, progress=None,
+           depth_passes=1):
     """Greedy parse with per-distance-class thresholds into a container.
-    progress(done, total), if given, is called after each segment."""
+    progress(done, total), if given, is called after each segment;
+    depth_passes (default 1) re-parses that many times breaking length ties
+    by the lowest resulting dependency depth (0: nearest source)."""
     x = _u8(x)
-    p = params(log2_bs, thr, bounds, max_chain, n_threads, segment)
+    p = params(log2_bs, thr, bounds, max_chain, n_threads, segment, depth_passes)
     if progress is not None:
         cb = PROGRESS_FN(lambda d, t, u: progress(int(d), int(t)))
         p.progress = cb

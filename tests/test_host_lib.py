@@ -35,7 +35,7 @@ def test_exact_encoder_equals_oracle(thr):
     parse: the archive is byte-identical to the oracle's."""
     x = synth.zipf_text(24000, seed=21)
     bounds = (512, 4096, 16384)
-    a = lz.encode(x, 12, thr, bounds, max_chain=0)
+    a = lz.encode(x, 12, thr, bounds, max_chain=0, depth_passes=0)
     ll, ml, sr, lit = oracle.encode(x, 12, thr, bounds)
     b = oracle.write_archive(x.size, 12, ll, ml, sr, lit, min_match=min(thr), thr=thr, bounds=bounds)
     assert np.array_equal(a, b)
@@ -45,11 +45,93 @@ def test_exact_encoder_fastq_and_binary():
     for x in (synth.fastq(30000, seed=7), synth.random_bytes(5000, 3),
               np.zeros(7000, np.uint8), np.tile(np.arange(7, dtype=np.uint8), 900)):
         for lb in (8, 12):
-            a = lz.encode(x, lb, (4, 5, 6, 7), (64, 1024, 4096), max_chain=0)
+            a = lz.encode(x, lb, (4, 5, 6, 7), (64, 1024, 4096), max_chain=0, depth_passes=0)
             ll, ml, sr, lit = oracle.encode(x, lb, (4, 5, 6, 7), (64, 1024, 4096))
             b = oracle.write_archive(x.size, lb, ll, ml, sr, lit, min_match=4, thr=(4, 5, 6, 7),
                                      bounds=(64, 1024, 4096))
             assert np.array_equal(a, b)
+
+
+def _lcp_table(x):
+    """lcp[i, j] = length of the longest common prefix of x[i:] and x[j:]."""
+    n = x.size
+    L = np.zeros((n + 1, n + 1), dtype=np.int32)
+    for i in range(n - 1, -1, -1):
+        L[i, :n] = np.where(x[i] == x, L[i + 1, 1:n + 1] + 1, 0)
+    return L
+
+
+def _byte_depths(arc):
+    """Dependency depth of every output byte from the oracle: literal bytes
+    0, match bytes their match's depth."""
+    T = oracle.tokens(arc)
+    lv, _ = oracle.levels(arc)
+    n = int(oracle.info(arc)["n"])
+    d = np.zeros(n, dtype=np.int64)
+    for t in range(T["dst"].size):
+        m0 = int(T["dst"][t] + T["lit_len"][t])
+        d[m0:m0 + int(T["mlen"][t])] = int(lv[t])
+    return T, d
+
+
+@pytest.mark.parametrize("kind", ["fastq", "zipf", "runs"])
+def test_depth_aware_ties_choose_shallowest_then_nearest(kind):
+    """One block, exhaustive chains: match lengths equal the oracle's
+    exhaustive greedy parse, and every match's source is, among all valid
+    candidates of its length (brute force over every earlier position), one
+    of lowest resulting depth (1 + the deepest byte it reads, its own output
+    excluded), and the nearest of those."""
+    if kind == "fastq":
+        x = synth.fastq(4096, seed=31)
+    elif kind == "zipf":
+        x = synth.zipf_text(4096, seed=32, vocab=64)
+    else:
+        x = np.frombuffer(b"".join(b"@R.%d %d/1\nACGTTGCAAC\n+\nIIIIIIII\n" % (i, i) for i in range(90)),
+                          np.uint8)[:4096].copy()
+    n = x.size
+    thr, bounds = (4, 5, 6, 8), (64, 512, 2048)
+    arc = lz.encode(x, 12, thr, bounds, max_chain=0, depth_passes=1)
+    assert np.array_equal(oracle.decode(arc), x)
+    ll, ml, sr, lit = oracle.encode(x, 12, thr, bounds)
+    T, dep = _byte_depths(arc)
+    assert T["lit_len"].tolist() == [int(v) for v in ll] and T["mlen"].tolist() == [int(v) for v in ml]
+    lcp = _lcp_table(x)
+    ties = 0
+    for t in range(T["dst"].size):
+        L = int(T["mlen"][t])
+        if L == 0:
+            continue
+        pos = int(T["dst"][t] + T["lit_len"][t])
+        s = np.arange(pos)
+        cap = np.minimum(lcp[s, pos], n - pos)
+        d = pos - s
+        cls = np.where(d < bounds[0], 0, np.where(d < bounds[1], 1, np.where(d < bounds[2], 2, 3)))
+        valid = cap >= np.array(thr)[cls]
+        assert cap[valid].max() == L
+        cands = s[valid & (cap == L)]
+        cdep = np.array([1 + dep[c:min(c + L, pos)].max() for c in cands])
+        best = cands[cdep == cdep.min()].max()
+        ties += int(cands.size > 1)
+        assert int(T["src"][t]) == best, (t, pos, L, int(T["src"][t]), best)
+    assert ties > 5
+
+
+def test_depth_aware_passes_keep_lengths_and_cut_depth():
+    """Several blocks, exhaustive chains: 1 and 2 depth-aware passes keep the
+    exhaustive parse's lengths (equal to the oracle's), round-trip, and do not
+    deepen the plan of header-heavy records."""
+    x = synth.fastq(64_000, seed=33)
+    thr, bounds = (5, 6, 8, 10), (4096, 65536, 1 << 20)
+    ll, ml, sr, lit = oracle.encode(x, 12, thr, bounds)
+    depths = []
+    for dp in (0, 1, 2):
+        arc = lz.encode(x, 12, thr, bounds, max_chain=0, depth_passes=dp)
+        assert np.array_equal(oracle.decode(arc), x)
+        T = oracle.tokens(arc)
+        assert T["lit_len"].tolist() == [int(v) for v in ll] and T["mlen"].tolist() == [int(v) for v in ml]
+        depths.append(oracle.levels(arc)[1])
+    assert depths[1] <= depths[0] and depths[2] <= depths[0]
+    assert depths[1] < depths[0]
 
 
 def test_chain_limited_encoder_roundtrips_and_keeps_invariants():
