@@ -336,6 +336,17 @@ int lz_mlp_forward(const float* d_params, uint32_t batch, const float* d_x, floa
 int lz_mlp_backward(const float* d_params, uint32_t batch, const float* d_x, const float* d_h1, const float* d_h2,
                     const float* d_logits, const int32_t* d_labels, float* d_grads, float* d_work, float* d_loss,
                     void* stream);
+/* lz_mlp_backward for callers that cannot allocate (code under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid hipMalloc):
+ * the work buffer is the library's own per-GPU device array of 4096 x 272
+ * floats (4.25 MiB, held by each GPU the library runs on until the process
+ * ends), so the call allocates nothing.  batch > 4096 gives LZ_E_INVAL.  All
+ * calls on one GPU share that array (every element is written before it is
+ * read, so nothing carries over between calls): calls that overlap on one GPU,
+ * e.g. on two streams, race.  Other arguments as lz_mlp_backward. */
+int lz_mlp_backward_noalloc(const float* d_params, uint32_t batch, const float* d_x, const float* d_h1,
+                            const float* d_h2, const float* d_logits, const int32_t* d_labels, float* d_grads,
+                            float* d_loss, void* stream);
 /* One bias-corrected Adam step (Kingma and Ba); step counts from 1. */
 int lz_mlp_adam(float* d_params, const float* d_grads, float* d_m, float* d_v, uint64_t n, float lr, float beta1,
                 float beta2, float eps, uint32_t step, void* stream);

@@ -15,6 +15,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "lz_internal.h"
 
 namespace {
@@ -101,6 +103,68 @@ void gemm(hipStream_t s, int M, int N, int K, const float* A, int lda, const flo
   hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(T * T), 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias, epi, R);
 }
 
+// Backward pass with its per-row work buffer `work` (batch x 272 floats:
+// dlogits, then the two hidden-layer gradients; every element is written
+// before it is read, so the buffer needs no clearing).
+int backward(const float* d_params, uint32_t batch, const float* d_x, const float* d_h1, const float* d_h2,
+             const float* d_logits, const int32_t* d_labels, float* d_grads, float* work, float* d_loss,
+             hipStream_t s) {
+  const float* P = d_params;
+  float* d3 = work;                          // batch x 16
+  float* dh2 = d3 + (size_t)batch * OUT;     // batch x 128
+  float* dh1 = dh2 + (size_t)batch * H;      // batch x 128
+  hipLaunchKernelGGL(k_softmax_ce, dim3((batch + 255) / 256), dim3(256), 0, s, (int)batch, d_logits, d_labels, d3,
+                     d_loss);
+  // layer 3
+  gemm<true, false>(s, H, OUT, batch, d_h2, H, d3, OUT, d_grads + OW3, OUT, nullptr, 0, nullptr);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, s, (int)batch, OUT, d3, d_grads + OB3);
+  gemm<false, true>(s, batch, H, OUT, d3, OUT, P + OW3, OUT, dh2, H, nullptr, 2, d_h2);
+  // layer 2
+  gemm<true, false>(s, H, H, batch, d_h1, H, dh2, H, d_grads + OW2, H, nullptr, 0, nullptr);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, s, (int)batch, H, dh2, d_grads + OB2);
+  gemm<false, true>(s, batch, H, H, dh2, H, P + OW2, H, dh1, H, nullptr, 2, d_h1);
+  // layer 1
+  gemm<true, false>(s, IN, H, batch, d_x, IN, dh1, H, d_grads + OW1, H, nullptr, 0, nullptr);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, s, (int)batch, H, dh1, d_grads + OB1);
+  if (hipGetLastError() != hipSuccess) return lz::fail(LZ_E_HIP, "backward launch failed");
+  return 0;
+}
+
+constexpr uint32_t kNoAllocMaxBatch = 4096;
+constexpr uint64_t kWorkPerRow = OUT + 2 * H;  // 272 floats
+
+}  // namespace
+
+// Work buffer of the allocation-free backward pass: a file-scope device array
+// (4096 x 272 floats = 4.25 MiB; one copy per GPU, alive until the process
+// ends).  In host code its name is a host-side stand-in, not a device
+// address; kernels get the address hipGetSymbolAddress returns for the
+// current device.
+static __device__ __align__(256) float scratch[(uint64_t)kNoAllocMaxBatch * kWorkPerRow];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, resolved once per device.
+int scratch_for_current_device(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return lz::fail(LZ_E_HIP, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxDevices) return lz::fail(LZ_E_INVAL, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return lz::fail(LZ_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = (float*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -131,26 +195,24 @@ int lz_mlp_backward(const float* d_params, uint32_t batch, const float* d_x, con
   if (!d_params || !d_x || !d_h1 || !d_h2 || !d_logits || !d_labels || !d_grads || !d_work)
     return lz::fail(LZ_E_INVAL, "null argument");
   if (batch == 0) return 0;
-  hipStream_t s = (hipStream_t)stream;
-  const float* P = d_params;
-  float* d3 = d_work;                        // batch x 16
-  float* dh2 = d3 + (size_t)batch * OUT;     // batch x 128
-  float* dh1 = dh2 + (size_t)batch * H;      // batch x 128
-  hipLaunchKernelGGL(k_softmax_ce, dim3((batch + 255) / 256), dim3(256), 0, s, (int)batch, d_logits, d_labels, d3,
-                     d_loss);
-  // layer 3
-  gemm<true, false>(s, H, OUT, batch, d_h2, H, d3, OUT, d_grads + OW3, OUT, nullptr, 0, nullptr);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, s, (int)batch, OUT, d3, d_grads + OB3);
-  gemm<false, true>(s, batch, H, OUT, d3, OUT, P + OW3, OUT, dh2, H, nullptr, 2, d_h2);
-  // layer 2
-  gemm<true, false>(s, H, H, batch, d_h1, H, dh2, H, d_grads + OW2, H, nullptr, 0, nullptr);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, s, (int)batch, H, dh2, d_grads + OB2);
-  gemm<false, true>(s, batch, H, H, dh2, H, P + OW2, H, dh1, H, nullptr, 2, d_h1);
-  // layer 1
-  gemm<true, false>(s, IN, H, batch, d_x, IN, dh1, H, d_grads + OW1, H, nullptr, 0, nullptr);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, s, (int)batch, H, dh1, d_grads + OB1);
-  if (hipGetLastError() != hipSuccess) return lz::fail(LZ_E_HIP, "backward launch failed");
-  return 0;
+  return backward(d_params, batch, d_x, d_h1, d_h2, d_logits, d_labels, d_grads, d_work, d_loss, (hipStream_t)stream);
+}
+
+// lz_mlp_backward with its work buffer in the library's per-device `scratch`
+// array: no allocation of any kind.  Calls on one GPU share that array, so
+// calls that overlap on one GPU (e.g. on two streams) race.
+int lz_mlp_backward_noalloc(const float* d_params, uint32_t batch, const float* d_x, const float* d_h1,
+                            const float* d_h2, const float* d_logits, const int32_t* d_labels, float* d_grads,
+                            float* d_loss, void* stream) {
+  if (!d_params || !d_x || !d_h1 || !d_h2 || !d_logits || !d_labels || !d_grads)
+    return lz::fail(LZ_E_INVAL, "null argument");
+  if (batch > kNoAllocMaxBatch)
+    return lz::fail(LZ_E_INVAL, "batch %u exceeds the allocation-free maximum of %u rows", batch, kNoAllocMaxBatch);
+  float* work = nullptr;
+  const int rc = scratch_for_current_device(&work);
+  if (rc) return rc;
+  if (batch == 0) return 0;
+  return backward(d_params, batch, d_x, d_h1, d_h2, d_logits, d_labels, d_grads, work, d_loss, (hipStream_t)stream);
 }
 
 // One Adam step (Kingma & Ba), bias-corrected; `step` counts from 1.

@@ -116,6 +116,7 @@ def lib():
             "lz_mlp_param_count": (_u64, []),
             "lz_mlp_forward": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _vp, _vp]),
             "lz_mlp_backward": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "lz_mlp_backward_noalloc": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "lz_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                            ctypes.c_float, _u32, _vp]),
             "lz_purecopy_device": (ctypes.c_int, [_u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp,
@@ -616,6 +617,14 @@ def mlp_backward(params, x, h1, h2, logits, labels, grads, work, loss=None, stre
                                _p(work), None if loss is None else _p(loss), _stream(stream))
     if rc:
         raise LzError(rc, "lz_mlp_backward")
+
+
+def mlp_backward_noalloc(params, x, h1, h2, logits, labels, grads, loss=None, stream=None):
+    """mlp_backward with the library's per-GPU work array (batch <= 4096)."""
+    rc = lib().lz_mlp_backward_noalloc(_p(params), x.shape[0], _p(x), _p(h1), _p(h2), _p(logits), _p(labels),
+                                       _p(grads), None if loss is None else _p(loss), _stream(stream))
+    if rc:
+        raise LzError(rc, "lz_mlp_backward_noalloc")
 
 
 def mlp_adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
