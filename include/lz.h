@@ -351,6 +351,71 @@ int lz_mlp_backward_noalloc(const float* d_params, uint32_t batch, const float* 
 int lz_mlp_adam(float* d_params, const float* d_grads, float* d_m, float* d_v, uint64_t n, float lr, float beta1,
                 float beta2, float eps, uint32_t step, void* stream);
 
+/* The selector (Sec. 4.3 and Sec. 6: the best threshold tuple is data-dependent
+ * at the margin).  A host object holding 16 candidate tuples (4 thresholds
+ * each), the fixed fallback tuple, the feature normalisation (mu, sd), the
+ * validation cost table of the fallback rule and the network parameters.
+ * File format (little-endian): "LZSEL001", u32 16, u32 fixed, u32 tuples[16][4],
+ * f32 mu[64], f32 sd[64], f32 val_J[16], u32 26896, f32 params[26896]. */
+typedef struct lz_selector lz_selector;
+/* tuples: 16 x 4 thresholds (>= 1); fixed < 16; weights He-initialised from
+ * `seed` (normal, std sqrt(2 / fan-in)), biases 0, mu 0, sd 1, val_J 1. */
+int lz_selector_create(const uint32_t* tuples, uint32_t fixed, uint64_t seed, lz_selector** sel);
+int lz_selector_load(const char* path, lz_selector** sel); /* LZ_E_CORRUPT if not a selector file */
+int lz_selector_save(const lz_selector* sel, const char* path);
+void lz_selector_free(lz_selector* sel);
+/* Copies the 26,896 parameters out (get) and/or in (set); either may be NULL. */
+int lz_selector_params(lz_selector* sel, float* get, const float* set);
+int lz_selector_info(const lz_selector* sel, uint32_t* tuples, uint32_t* fixed, float* mu, float* sd, float* val_J);
+/* Feature normalisation from training rows: per feature the mean and the
+ * population standard deviation + 1e-6. */
+int lz_selector_set_norm(lz_selector* sel, const float* feats, uint64_t n_rows);
+
+/* Labels from the method's own measurements.  Blocks are numbered file by
+ * file (file f has file_blocks[f] blocks); for block k and tuple t,
+ * size[16k + t] is its entropy-bound bytes (lz_block_stats) and
+ * counts[3(16k + t) + {0,1,2}] its tokens, matches and match bytes; per file
+ * and tuple, file_ms[16f + t] is the measured GPU decode time and
+ * file_depths[16f + t] the plan's depth count.  The decode-time model
+ *   ms = c0 tokens + c1 matches + c2 match bytes + c3 depths + c4
+ * is fitted by least squares over every (file, tuple) and clamped at 0
+ * (coef[5]); a block's time is its share: c0 t + c1 m + c2 b + (c3 depths +
+ * c4) / blocks.  J[16k + t] = size / size(fixed) + lambda time / time(fixed),
+ * labels[k] = the t of least J (first on ties). */
+int lz_learn_labels(uint32_t n_files, const uint32_t* file_blocks, uint32_t fixed, const double* size,
+                    const uint64_t* counts, const double* file_ms, const uint32_t* file_depths, double lambda,
+                    double* coef, double* J, int32_t* labels);
+
+/* Trains the network on the GPU with the kernels above (softmax cross-entropy,
+ * Adam with beta 0.9 / 0.999, eps 1e-8): `epochs` passes over a seeded
+ * permutation of the rows (features normalised with the selector's mu / sd),
+ * batches of `batch` rows.  d_work: device workspace of
+ * lz_selector_train_bytes, 256-byte aligned.  loss_hist[epochs] (may be NULL)
+ * receives each epoch's mean loss.  Synchronises `stream`. */
+int lz_selector_train_bytes(uint64_t n_rows, uint32_t batch, uint64_t* bytes);
+int lz_selector_train(lz_selector* sel, const float* feats, const int32_t* labels, uint64_t n_rows, uint32_t epochs,
+                      uint32_t batch, float lr, uint64_t seed, void* d_work, uint64_t work_bytes, float* loss_hist,
+                      void* stream);
+
+/* Validation table of the fallback rule: for each tuple, the mean J of the
+ * validation rows the network predicts it for (argmax), divided by 1 + lambda
+ * (the fixed tuple's J); tuples never predicted get 9, the fixed tuple 1. */
+int lz_selector_calibrate(lz_selector* sel, const float* feats, const double* J, uint64_t n_rows, double lambda);
+
+/* Inference on the host (double precision): per row, the tuple of largest
+ * softmax probability, or the fixed tuple when that probability is below 0.5
+ * or the tuple's validation cost is not below the fixed one's.
+ * top_prob (may be NULL) receives the largest probability. */
+int lz_selector_choose(const lz_selector* sel, const float* feats, uint64_t n_rows, uint8_t* choice, float* top_prob);
+
+/* Learned mode of the encoder: features from a cheap parse of `in`
+ * (thresholds 4/4/4/4, 16 candidates per chain), one tuple per block by
+ * lz_selector_choose, then lz_encode_blockwise with those thresholds (tuple
+ * indices in the per-block info bytes).  choice (n_blocks, may be NULL)
+ * receives the chosen tuple indices.  Other parameters from p. */
+int lz_encode_learned(const uint8_t* in, uint64_t n, const lz_params* p, const lz_selector* sel, uint8_t** arc,
+                      uint64_t* arc_size, uint8_t* choice);
+
 /* Pure-copy mode (Sec. 3.3, first control): executes pre-decoded tokens on the
  * device.  Token t (SoA, device arrays): copy lit_len[t] bytes from
  * d_lit[lit_off[t]..] to d_out[dst[t]..], then mlen[t] bytes from

@@ -59,7 +59,20 @@ int compute_levels(const ArcView& v, uint32_t* levels, uint32_t* max_level, uint
 
 unsigned hw_threads(uint32_t requested);
 
+// Learned threshold selector (host object behind lz_selector).
+constexpr uint32_t kSelIn = 64, kSelHidden = 128, kSelTuples = 16;
+constexpr uint64_t kSelParams = kSelIn * kSelHidden + kSelHidden + kSelHidden * kSelHidden + kSelHidden +
+                                kSelHidden * kSelTuples + kSelTuples;  // 26,896
+
 }  // namespace lz
+
+struct lz_selector {
+  uint32_t tuples[lz::kSelTuples][4];
+  uint32_t fixed = 1;                   // fallback tuple
+  float mu[lz::kSelIn], sd[lz::kSelIn];  // feature normalisation
+  float val_J[lz::kSelTuples];          // mean validation cost per predicted tuple, relative to the fixed one
+  std::vector<float> params;            // kSelParams, row-major W1 b1 W2 b2 W3 b3
+};
 
 // ---------------------------------------------------------------- inline impl
 namespace lz {

@@ -16,6 +16,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <vector>
 
 #include "lz_internal.h"
 
@@ -213,6 +214,106 @@ int lz_mlp_backward_noalloc(const float* d_params, uint32_t batch, const float* 
   if (rc) return rc;
   if (batch == 0) return 0;
   return backward(d_params, batch, d_x, d_h1, d_h2, d_logits, d_labels, d_grads, work, d_loss, (hipStream_t)stream);
+}
+
+// Device workspace of lz_selector_train: parameters, gradients and the two
+// Adam moments, the (shuffled, normalised) training rows and labels, and one
+// batch of activations, work buffer and loss; regions 256-byte aligned.
+static uint64_t train_layout(uint64_t n_rows, uint32_t batch, uint64_t off[11]) {
+  auto a256 = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  const uint64_t sizes[11] = {4 * NP, 4 * NP, 4 * NP, 4 * NP, 4 * n_rows * IN, 4 * n_rows, 4ull * batch * H,
+                              4ull * batch * H, 4ull * batch * OUT, 4ull * batch * (OUT + 2 * H), 4};
+  uint64_t o = 0;
+  for (int i = 0; i < 11; ++i) {
+    off[i] = o;
+    o += a256(sizes[i]);
+  }
+  return o;
+}
+
+int lz_selector_train_bytes(uint64_t n_rows, uint32_t batch, uint64_t* bytes) {
+  if (!bytes || batch == 0) return lz::fail(LZ_E_INVAL, "bad argument");
+  uint64_t off[11];
+  *bytes = train_layout(n_rows, batch, off);
+  return 0;
+}
+
+// Mini-batch training of the selector's network with the kernels above:
+// per epoch a seeded permutation of the rows (features normalised with the
+// selector's mu / sd), then per batch forward, backward and one Adam step.
+// loss_hist[e] (may be null) receives epoch e's mean loss.  Synchronises
+// `stream` once per epoch (to read the loss) and at the end.
+int lz_selector_train(lz_selector* sel, const float* feats, const int32_t* labels, uint64_t n_rows, uint32_t epochs,
+                      uint32_t batch, float lr, uint64_t seed, void* d_work, uint64_t work_bytes, float* loss_hist,
+                      void* stream) {
+  if (!sel || (n_rows && (!feats || !labels)) || !d_work || batch == 0) return lz::fail(LZ_E_INVAL, "bad argument");
+  if ((uintptr_t)d_work & 255u) return lz::fail(LZ_E_INVAL, "d_work must be 256-byte aligned");
+  for (uint64_t r = 0; r < n_rows; ++r)
+    if (labels[r] < 0 || labels[r] >= OUT) return lz::fail(LZ_E_INVAL, "label %d of row %llu out of range",
+                                                           labels[r], (unsigned long long)r);
+  uint64_t off[11];
+  if (work_bytes < train_layout(n_rows, batch, off)) return lz::fail(LZ_E_NOMEM, "training workspace too small");
+  if (n_rows == 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* W = (uint8_t*)d_work;
+  float* P = (float*)(W + off[0]);
+  float* G = (float*)(W + off[1]);
+  float* M = (float*)(W + off[2]);
+  float* V = (float*)(W + off[3]);
+  float* X = (float*)(W + off[4]);
+  int32_t* Y = (int32_t*)(W + off[5]);
+  float* h1 = (float*)(W + off[6]);
+  float* h2 = (float*)(W + off[7]);
+  float* lg = (float*)(W + off[8]);
+  float* work = (float*)(W + off[9]);
+  float* loss = (float*)(W + off[10]);
+  std::vector<float> zeros(NP, 0.f), hx(n_rows * IN);
+  std::vector<int32_t> hy(n_rows);
+  std::vector<uint64_t> perm(n_rows);
+  if (hipMemcpyAsync(P, sel->params.data(), 4 * NP, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(M, zeros.data(), 4 * NP, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(V, zeros.data(), 4 * NP, hipMemcpyHostToDevice, s) != hipSuccess)
+    return lz::fail(LZ_E_HIP, "parameter upload failed");
+  uint64_t st = seed;
+  uint32_t step = 0;
+  for (uint32_t ep = 0; ep < epochs; ++ep) {
+    // Fisher-Yates over SplitMix64 draws
+    for (uint64_t r = 0; r < n_rows; ++r) perm[r] = r;
+    for (uint64_t r = n_rows - 1; r > 0; --r) {
+      st += 0x9E3779B97F4A7C15ull;
+      uint64_t z = st;
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+      z ^= z >> 31;
+      std::swap(perm[r], perm[z % (r + 1)]);
+    }
+    for (uint64_t r = 0; r < n_rows; ++r) {
+      const float* f = feats + perm[r] * IN;
+      for (int i = 0; i < IN; ++i) hx[r * IN + i] = (f[i] - sel->mu[i]) / sel->sd[i];
+      hy[r] = labels[perm[r]];
+    }
+    const float zero = 0.f;
+    float ep_loss = 0.f;
+    if (hipMemcpyAsync(X, hx.data(), 4 * n_rows * IN, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(Y, hy.data(), 4 * n_rows, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(loss, &zero, 4, hipMemcpyHostToDevice, s) != hipSuccess)
+      return lz::fail(LZ_E_HIP, "training rows upload failed");
+    uint64_t nb = 0;
+    for (uint64_t r0 = 0; r0 < n_rows; r0 += batch, ++nb) {
+      const uint32_t B = (uint32_t)std::min<uint64_t>(batch, n_rows - r0);
+      int rc = lz_mlp_forward(P, B, X + r0 * IN, h1, h2, lg, stream);
+      if (!rc) rc = backward(P, B, X + r0 * IN, h1, h2, lg, Y + r0, G, work, loss, s);
+      if (!rc) rc = lz_mlp_adam(P, G, M, V, NP, lr, 0.9f, 0.999f, 1e-8f, ++step, stream);
+      if (rc) return rc;
+    }
+    if (hipMemcpyAsync(&ep_loss, loss, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      return lz::fail(LZ_E_HIP, "training epoch %u failed", ep);
+    if (loss_hist) loss_hist[ep] = ep_loss / (float)nb;
+  }
+  if (hipMemcpyAsync(sel->params.data(), P, 4 * NP, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return lz::fail(LZ_E_HIP, "parameter download failed");
+  return 0;
 }
 
 // One Adam step (Kingma & Ba), bias-corrected; `step` counts from 1.

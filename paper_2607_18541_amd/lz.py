@@ -119,6 +119,21 @@ def lib():
             "lz_mlp_backward_noalloc": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "lz_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                            ctypes.c_float, _u32, _vp]),
+            "lz_selector_create": (ctypes.c_int, [_vp, _u32, _u64, ctypes.POINTER(_vp)]),
+            "lz_selector_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
+            "lz_selector_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+            "lz_selector_free": (None, [_vp]),
+            "lz_selector_params": (ctypes.c_int, [_vp, _vp, _vp]),
+            "lz_selector_info": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+            "lz_selector_set_norm": (ctypes.c_int, [_vp, _vp, _u64]),
+            "lz_learn_labels": (ctypes.c_int, [_u32, _vp, _u32, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
+            "lz_selector_train_bytes": (ctypes.c_int, [_u64, _u32, _p64]),
+            "lz_selector_train": (ctypes.c_int, [_vp, _vp, _vp, _u64, _u32, _u32, ctypes.c_float, _u64, _vp, _u64, _vp,
+                                                 _vp]),
+            "lz_selector_calibrate": (ctypes.c_int, [_vp, _vp, _vp, _u64, ctypes.c_double]),
+            "lz_selector_choose": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp]),
+            "lz_encode_learned": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp), _p64,
+                                                 _vp]),
             "lz_purecopy_device": (ctypes.c_int, [_u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp,
                                                   _u64, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
         }
@@ -632,3 +647,133 @@ def mlp_adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-
                            _stream(stream))
     if rc:
         raise LzError(rc, "lz_mlp_adam")
+
+
+# ------------------------------------------------------------ learned thresholds
+
+class Selector:
+    """The learned per-block threshold selector (a liblz host object): 16
+    candidate tuples, the fixed fallback, feature normalisation, the fallback
+    rule's validation table and the network parameters."""
+
+    def __init__(self, tuples=None, fixed=1, seed=1, path=None):
+        h = _vp()
+        if path is not None:
+            rc = lib().lz_selector_load(os.fsencode(path), ctypes.byref(h))
+            what = "lz_selector_load"
+        else:
+            t = np.ascontiguousarray(tuples, dtype=np.uint32).reshape(16, 4)
+            rc = lib().lz_selector_create(t.ctypes.data, fixed, seed, ctypes.byref(h))
+            what = "lz_selector_create"
+        if rc:
+            raise LzError(rc, what)
+        self.h = h
+
+    def save(self, path):
+        rc = lib().lz_selector_save(self.h, os.fsencode(path))
+        if rc:
+            raise LzError(rc, "lz_selector_save")
+
+    def params(self, new=None):
+        """The 26,896 parameters (a copy); with `new`, sets them first."""
+        out = np.zeros(26896, dtype=np.float32)
+        src = None if new is None else np.ascontiguousarray(new, dtype=np.float32)
+        rc = lib().lz_selector_params(self.h, out.ctypes.data, None if src is None else src.ctypes.data)
+        if rc:
+            raise LzError(rc, "lz_selector_params")
+        return out
+
+    def info(self):
+        t = np.zeros((16, 4), np.uint32)
+        fixed = _u32()
+        mu, sd, vj = (np.zeros(n, np.float32) for n in (64, 64, 16))
+        rc = lib().lz_selector_info(self.h, t.ctypes.data, ctypes.byref(fixed), mu.ctypes.data, sd.ctypes.data,
+                                    vj.ctypes.data)
+        if rc:
+            raise LzError(rc, "lz_selector_info")
+        return {"tuples": t, "fixed": fixed.value, "mu": mu, "sd": sd, "val_J": vj}
+
+    def set_norm(self, feats):
+        f = np.ascontiguousarray(feats, dtype=np.float32)
+        rc = lib().lz_selector_set_norm(self.h, f.ctypes.data, f.shape[0])
+        if rc:
+            raise LzError(rc, "lz_selector_set_norm")
+
+    def train(self, feats, labels, epochs=50, batch=256, lr=1e-3, seed=0, stream=None):
+        """GPU training with the library's kernels; returns the per-epoch loss."""
+        import torch
+        f = np.ascontiguousarray(feats, dtype=np.float32)
+        y = np.ascontiguousarray(labels, dtype=np.int32)
+        nb = _u64()
+        rc = lib().lz_selector_train_bytes(f.shape[0], batch, ctypes.byref(nb))
+        if rc:
+            raise LzError(rc, "lz_selector_train_bytes")
+        work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        hist = np.zeros(max(epochs, 1), dtype=np.float32)
+        rc = lib().lz_selector_train(self.h, f.ctypes.data, y.ctypes.data, f.shape[0], epochs, batch, lr, seed,
+                                     ctypes.c_void_p(work.data_ptr()), nb.value, hist.ctypes.data, _stream(stream))
+        if rc:
+            raise LzError(rc, "lz_selector_train")
+        return hist[:epochs].tolist()
+
+    def calibrate(self, feats, J, lam=1.0):
+        f = np.ascontiguousarray(feats, dtype=np.float32)
+        j = np.ascontiguousarray(J, dtype=np.float64)
+        rc = lib().lz_selector_calibrate(self.h, f.ctypes.data, j.ctypes.data, f.shape[0], lam)
+        if rc:
+            raise LzError(rc, "lz_selector_calibrate")
+
+    def choose(self, feats):
+        """(tuple index per row with the fallback applied, top probability)."""
+        f = np.ascontiguousarray(feats, dtype=np.float32)
+        c = np.zeros(max(f.shape[0], 1), np.uint8)
+        p = np.zeros(max(f.shape[0], 1), np.float32)
+        rc = lib().lz_selector_choose(self.h, f.ctypes.data, f.shape[0], c.ctypes.data, p.ctypes.data)
+        if rc:
+            raise LzError(rc, "lz_selector_choose")
+        return c[:f.shape[0]], p[:f.shape[0]]
+
+    def free(self):
+        if getattr(self, "h", None):
+            lib().lz_selector_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def learn_labels(file_blocks, size, counts, file_ms, file_depths, lam=1.0, fixed=1):
+    """Time-model coefficients, J and labels (lz_learn_labels)."""
+    fb = np.ascontiguousarray(file_blocks, dtype=np.uint32)
+    sz = np.ascontiguousarray(size, dtype=np.float64)
+    ct = np.ascontiguousarray(counts, dtype=np.uint64)
+    ms = np.ascontiguousarray(file_ms, dtype=np.float64)
+    dp = np.ascontiguousarray(file_depths, dtype=np.uint32)
+    K = int(fb.sum())
+    assert sz.size == 16 * K and ct.size == 48 * K and ms.size == 16 * fb.size and dp.size == 16 * fb.size
+    coef = np.zeros(5, np.float64)
+    J = np.zeros((K, 16), np.float64)
+    lab = np.zeros(max(K, 1), np.int32)
+    rc = lib().lz_learn_labels(fb.size, fb.ctypes.data, fixed, sz.ctypes.data, ct.ctypes.data, ms.ctypes.data,
+                               dp.ctypes.data, lam, coef.ctypes.data, J.ctypes.data, lab.ctypes.data)
+    if rc:
+        raise LzError(rc, "lz_learn_labels")
+    return coef, J, lab[:K]
+
+
+def encode_learned(x, sel, log2_bs=16, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, depth_passes=1):
+    """Learned-mode encode: (archive, chosen tuple index per block)."""
+    x = _u8(x)
+    p = params(log2_bs, TUNED_THR, bounds, max_chain, n_threads, 0, depth_passes)
+    nb = (x.size + (1 << log2_bs) - 1) >> log2_bs
+    ch = np.zeros(max(nb, 1), np.uint8)
+    pa = _vp()
+    sz = _u64()
+    rc = lib().lz_encode_learned(x.ctypes.data, x.size, ctypes.byref(p), sel.h, ctypes.byref(pa), ctypes.byref(sz),
+                                 ch.ctypes.data)
+    if rc:
+        raise LzError(rc, "lz_encode_learned")
+    return _take_archive(pa, sz.value), ch[:nb]

@@ -55,12 +55,42 @@ def test_forward_backward_adam_match_reference(B):
     assert np.allclose(P.cpu().numpy(), rt, rtol=1e-6, atol=1e-7)
 
 
+def test_selector_training_step_matches_reference():
+    """lz_selector_train over one epoch whose single batch holds every row is
+    one Adam step on the mean gradient of the normalised rows: equal to the
+    float64 reference of the same step."""
+    _dev()
+    rng = np.random.default_rng(11)
+    B = 200
+    F = rng.uniform(0, 0.3, (B, 64)).astype(np.float32)
+    y = rng.integers(0, 16, B).astype(np.int32)
+    tuples = np.tile(np.array([12, 16, 24, 32], np.uint32), (16, 1))
+    sel = lz.Selector(tuples, 1, 4)
+    sel.set_norm(F)
+    theta = sel.params().astype(np.float64)
+    inf = sel.info()
+    x = (F.astype(np.float64) - inf["mu"]) / inf["sd"]
+    hist = sel.train(F, y, epochs=1, batch=256, lr=1e-3, seed=9)
+    assert abs(hist[0] - mlp_ref.loss(theta, x, y)) < 1e-4
+    g = mlp_ref.grad(theta, x, y)
+    want, _, _ = mlp_ref.adam(theta, g, np.zeros(theta.size), np.zeros(theta.size), 1)
+    got = sel.params().astype(np.float64)
+    # Adam's first step moves every weight by lr * sign(g) where |g| >> eps
+    big = np.abs(g) > 1e-5
+    assert np.allclose(got[big], want[big], rtol=1e-5, atol=1e-7)
+    assert np.abs(got - want).max() <= 1.01e-3
+
+
 def test_learned_selector_end_to_end():
+    """Train on measurements of generated files, calibrate the fallback, then
+    encode held-out files in learned mode and compare, measured end to end
+    (entropy-bound size and GPU decode time), with the fixed 12/16/24/32
+    encode: the learned choice must cost less (J below 2 by a margin)."""
     _dev()
     from paper_2607_18541_amd import learn
-    res, sel = learn.run(n_files=40, blocks_per_file=12, log2_bs=14, epochs=40, seed=3)
-    print("learned selector:", {k: res[k] for k in ("loss_first", "loss_last", "val_accuracy", "test_mean_J",
-                                                    "fixed_J", "test_gain")}, flush=True)
+    res, sel = learn.run(n_files=60, blocks_per_file=16, log2_bs=14, epochs=40, seed=3)
+    info = {k: res[k] for k in ("loss_first", "loss_last", "val_accuracy", "test_mean_J", "fixed_J", "test_gain",
+                                "test_size_ratio", "test_time_ratio", "test_non_fixed_blocks")}
+    print("learned selector:", info, flush=True)
     assert res["loss_last"] < res["loss_first"]
-    # the learned choice never loses much against the fixed setting it falls back to
-    assert res["test_mean_J"] <= res["fixed_J"] + 0.02
+    assert res["test_gain"] > 0.05, info
