@@ -679,7 +679,8 @@ def run_sweep(args, torch, lz):
         pc_alg = n + int(mlv.sum()) + int(llv.sum()) + T * 28
         for G in (8, 16, 32, 64):
             us = g(copy_units(llv + mlv, G, 2048), np.uint64)
-            lz.purecopy(tdst, tlo, tll, tsrc, tml, us, tlit, ref, out, G=G, unroll=args.unroll)
+            pc = lz.PureCopy(tdst, tlo, tll, tsrc, tml, us, tlit, ref, out)
+            pc.run(G=G, unroll=args.unroll)
             torch.cuda.synchronize()
             if not bool(torch.equal(out, expect)):
                 raise SystemExit("pure copy differs from the oracle (m=%d G=%d)" % (m, G))
@@ -687,7 +688,7 @@ def run_sweep(args, torch, lz):
             b = torch.cuda.Event(enable_timing=True)
             a.record()
             for _ in range(args.steps):
-                lz.purecopy(tdst, tlo, tll, tsrc, tml, us, tlit, ref, out, G=G, unroll=args.unroll)
+                pc.run(G=G, unroll=args.unroll)
             b.record()
             torch.cuda.synchronize()
             ms = a.elapsed_time(b) / args.steps
@@ -757,6 +758,27 @@ def run_seek(args, torch, lz):
                 del scratch, out
             log(json.dumps(best))
             rows.append(best)
+    # read-level seek (record id -> block -> record), FASTQ records of 4 lines
+    idx = lz.ReadIndex(x, args.log2_bs, 4)
+    out = torch.empty(1 << 16, dtype=torch.uint8, device=dev)
+    scratch = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+    R = idx.records
+    rec_rows = []
+    for frac in (0.0001, 0.01, 0.1, 0.5, 0.99):
+        rid = min(int(frac * R), R - 1)
+        best = None
+        for rep in range(args.steps):
+            t0 = time.perf_counter()
+            got = idx.seek(da, rid, out=out, scratch=scratch)
+            ms = (time.perf_counter() - t0) * 1e3
+            best = ms if best is None else min(best, ms)
+        rec = bytes(got.cpu().numpy())
+        # the record is 4 lines and its header names its id (ids count from 1)
+        if not (rec.count(b"\n") == 4 and rec.startswith(b"@SYN.%d " % (rid + 1))):
+            raise SystemExit("record %d: seek returned %r" % (rid, rec[:40]))
+        row = {"record": rid, "frac": frac, "bytes": len(rec), "total_ms": round(best, 3)}
+        log(json.dumps(row))
+        rec_rows.append(row)
     small = [r["total_ms"] for r in rows if r["len"] == 16384]
     return {
         "metric": "range seek latency, 16 KiB (device-resident, FASTQ-like)",
@@ -765,7 +787,7 @@ def run_seek(args, torch, lz):
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": "FASTQ-like reads %d B, 12/16/24/32, 64 KiB blocks%s; best of %d seeks per point"
                                % (n, ", encoded in %d MiB segments" % (seg >> 20) if seg else "", args.steps)},
-        "rows": rows,
+        "rows": rows, "record_seek": rec_rows,
     }
 
 
@@ -824,6 +846,8 @@ def run_ablate(args, torch, lz):
         da.close()
         del out
         torch.cuda.empty_cache()
+    rows += ablate_streams(args, torch, lz, x, xt)
+    rows += ablate_source_order(args, torch, lz)
     return {
         "metric": "decode GB/s and ratio under threshold, band and schedule variants (FASTQ-like)",
         "value": tuned_gbps, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
@@ -833,6 +857,105 @@ def run_ablate(args, torch, lz):
                                "paper = 128/16 Ki/2 Mi" % n},
         "rows": rows,
     }
+
+
+def ablate_streams(args, torch, lz, x, xt):
+    """Two concurrent decode streams (Sec. 3.3, last control): the tuned
+    archive opened twice and decoded into two outputs on two streams at once,
+    against one stream alone; aggregate output GB/s of each."""
+    dev = torch.device("cuda:0")
+    n = int(x.size)
+    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain,
+                    depth_passes=args.depth_passes)
+    das = [lz.DeviceArchive(arc, device=dev) for _ in range(2)]
+    outs = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(2)]
+    sts = [torch.cuda.Stream() for _ in range(2)]
+    for d, o, st in zip(das, outs, sts):
+        d.decode(o, stream=st)
+    torch.cuda.synchronize()
+    steps = max(args.steps, 5)
+    rows = []
+    for k in (1, 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for d, o, st in list(zip(das, outs, sts))[:k]:
+                d.decode_async(o, stream=st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        for d, o, st in list(zip(das, outs, sts))[:k]:
+            d.check(stream=st)
+            if not bool(torch.equal(o, xt)):
+                raise SystemExit("concurrent decode on %d streams differs from the input" % k)
+        row = {"thr": "12/16/24/32", "bands": "cfg", "mechanism": "%d concurrent stream%s" % (k, "s" * (k > 1)),
+               "ms_per_round": round(wall / steps * 1e3, 4), "aggregate_gbps": round(k * n * steps / wall / 1e9, 2)}
+        log(json.dumps(row))
+        rows.append(row)
+    rows[-1]["vs_one_stream"] = round(rows[-1]["aggregate_gbps"] / rows[0]["aggregate_gbps"], 3)
+    for d in das:
+        d.close()
+    del outs
+    torch.cuda.empty_cache()
+    return rows
+
+
+def ablate_source_order(args, torch, lz, m=256, n=1 << 28):
+    """Sorted against scattered source addresses (Sec. 3.3, third control) on
+    the pure-copy path: the generated stream of mean match length m with its
+    sources as generated (uniform over the output, scattered) and the same
+    tokens with the sources sorted into increasing order, each copied from a
+    reference buffer; every output checked against a plain PyTorch gather."""
+    import synth
+    dev = torch.device("cuda:0")
+    ll, ml, sr, lit = synth.geo_tokens(n, m, seed=2 + 3)
+    llv = np.asarray(ll, dtype=np.int64)
+    mlv = np.asarray(ml, dtype=np.int64)
+    mstart = np.concatenate([[0], np.cumsum(llv + mlv)[:-1]]) + llv
+    dst = (mstart - llv).astype(np.uint64)
+    loff = np.concatenate([[0], np.cumsum(llv)[:-1]]).astype(np.uint64)
+    g = lambda a, dt: torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(dt))).to(dev)
+    ref = torch.randint(0, 256, (n,), dtype=torch.uint8, device=dev)
+    tlit = g(lit, np.uint8)
+    us = g(copy_units(llv + mlv, 64, 2048), np.uint64)
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    # the bytes each match must copy, for the check: output position -> reference position
+    pos = torch.arange(n, device=dev, dtype=torch.int64)
+    tok_of = torch.from_numpy(np.repeat(np.arange(llv.size), llv + mlv)).to(dev)
+    rows = []
+    srcs = {"scattered (as generated)": np.asarray(sr, dtype=np.int64),
+            "sorted (increasing)": np.sort(np.asarray(sr, dtype=np.int64))}
+    tdst, tlo, tll, tml = g(dst, np.uint64), g(loff, np.uint64), g(llv, np.uint32), g(mlv, np.uint32)
+    for label, s in srcs.items():
+        s = np.where(mlv > 0, s, 0)
+        tsrc = g(s, np.uint64)
+        pc = lz.PureCopy(tdst, tlo, tll, tsrc, tml, us, tlit, ref, out)
+        pc.run(G=64, unroll=args.unroll)
+        torch.cuda.synchronize()
+        t_ms = torch.from_numpy(mstart).to(dev)[tok_of]
+        in_match = pos >= t_ms
+        want_ref = ref[(torch.from_numpy(s).to(dev)[tok_of] + (pos - t_ms)).clamp(0, n - 1)]
+        want_lit = tlit[(torch.from_numpy(loff.astype(np.int64)).to(dev)[tok_of]
+                         + (pos - torch.from_numpy(dst.astype(np.int64)).to(dev)[tok_of])).clamp(0, tlit.numel() - 1)]
+        want = torch.where(in_match, want_ref, want_lit)
+        if not bool(torch.equal(out, want)):
+            raise SystemExit("pure copy with %s sources differs from the gather" % label)
+        del want, want_ref, want_lit, in_match, t_ms
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            pc.run(G=64, unroll=args.unroll)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        row = {"mechanism": "pure copy, %s sources" % label, "m": m, "n_bytes": n, "ms": round(ms, 4),
+               "gbps": round(n / ms / 1e6, 2)}
+        log(json.dumps(row))
+        rows.append(row)
+    rows[-1]["vs_scattered"] = round(rows[-1]["gbps"] / rows[0]["gbps"], 3)
+    del out, ref, pos, tok_of
+    torch.cuda.empty_cache()
+    return rows
 
 
 def main():

@@ -248,6 +248,38 @@ int lz_range_scratch_bytes(lz_dev* h, uint64_t off, uint64_t len, uint64_t* byte
 int lz_decode_range(lz_dev* h, uint64_t off, uint64_t len, uint8_t* d_out, void* d_scratch, uint64_t scratch_cap,
                     void* stream);
 
+/* ------------------------------------------------------------ read seek */
+
+/* Read-level seek (Sec. 6, first limitation: seek is read id -> block; Sec. 1
+ * "Positioning": seek into compressed-resident data).  A record is `lines`
+ * newline-terminated lines (FASTQ: 4); record r starts at 0 (r = 0) or just
+ * after the (lines * r)-th newline, and ends where record r + 1 starts (the
+ * last one at its last newline, or at n when that is missing).  The index
+ * holds, per LZ block of 2^log2_bs bytes, the id and offset of the first
+ * record starting in that block or later (offset n when none does): 16
+ * bytes per block.  Built on the host from the input (at encode time). */
+typedef struct lz_read_index lz_read_index;
+int lz_read_index_build(const uint8_t* in, uint64_t n, uint32_t log2_bs, uint32_t lines, lz_read_index** index);
+void lz_read_index_free(lz_read_index* index);
+uint64_t lz_read_index_records(const lz_read_index* index);
+int lz_read_index_block(const lz_read_index* index, uint64_t block, uint64_t* first_id, uint64_t* first_off);
+/* File: "LZRIX001", u64 n, u32 log2_bs, u32 lines, u64 records, u64 blocks,
+ * u64 first_id[blocks], u64 first_off[blocks]; LZ_E_CORRUPT if not one. */
+int lz_read_index_save(const lz_read_index* index, const char* path);
+int lz_read_index_load(const char* path, lz_read_index** index);
+
+/* Record `id` (LZ_E_RANGE if >= the record count) of a device-resident
+ * archive of the same input: its block b is the last whose first record id is
+ * <= id; the bytes from b's first record start to the first record start of
+ * the next block with one (or n) hold it whole and are range-decoded on the
+ * device (lz_range_plan_create / lz_range_run), then one workgroup counts
+ * newlines and copies the record to d_out[0, *len).  d_scratch (256-byte
+ * aligned) holds lz_seek_record_scratch_bytes for this id; LZ_E_NOMEM (with
+ * *len set) if the record exceeds out_cap.  Synchronises `stream`. */
+int lz_seek_record_scratch_bytes(lz_dev* h, const lz_read_index* index, uint64_t id, uint64_t* bytes);
+int lz_seek_record(lz_dev* h, const lz_read_index* index, uint64_t id, uint8_t* d_out, uint64_t out_cap,
+                   void* d_scratch, uint64_t scratch_cap, uint64_t* len, void* stream);
+
 /* ------------------------------------------------------------ batch decode */
 
 /* Many archives in one replayable launch sequence (one graph launch): work of

@@ -134,6 +134,14 @@ def lib():
             "lz_selector_choose": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp]),
             "lz_encode_learned": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp), _p64,
                                                  _vp]),
+            "lz_read_index_build": (ctypes.c_int, [_vp, _u64, _u32, _u32, ctypes.POINTER(_vp)]),
+            "lz_read_index_free": (None, [_vp]),
+            "lz_read_index_records": (_u64, [_vp]),
+            "lz_read_index_block": (ctypes.c_int, [_vp, _u64, _p64, _p64]),
+            "lz_read_index_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+            "lz_read_index_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
+            "lz_seek_record_scratch_bytes": (ctypes.c_int, [_vp, _vp, _u64, _p64]),
+            "lz_seek_record": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _p64, _vp]),
             "lz_purecopy_device": (ctypes.c_int, [_u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp,
                                                   _u64, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
         }
@@ -371,31 +379,44 @@ class DeviceArchive:
             pass
 
 
+class PureCopy:
+    """Pre-decoded tokens bound to their device buffers (torch cuda tensors),
+    bounds-checked once here on the host; run() only launches."""
+
+    def __init__(self, dst, lit_off, lit_len, src, mlen, unit_start, lit, ref, out):
+        import torch
+        T = dst.numel()
+        for t in (lit_off, lit_len, src, mlen):
+            assert t.numel() == T
+        if T:
+            ends = (dst.to(torch.int64) + lit_len.to(torch.int64) + mlen.to(torch.int64)).max().item()
+            lend = (lit_off.to(torch.int64) + lit_len.to(torch.int64)).max().item()
+            send = (src.to(torch.int64) + mlen.to(torch.int64)).max().item()
+            if ends > out.numel() or lend > lit.numel() or send > ref.numel():
+                raise ValueError("pre-decoded tokens index outside their buffers")
+            us = unit_start.to("cpu").to(torch.int64)
+            if us[0].item() != 0 or us[-1].item() != T or bool((us[1:] < us[:-1]).any()):
+                raise ValueError("unit starts must run from 0 to ntok")
+        self.args = (dst, lit_off, lit_len, src, mlen, unit_start, lit, ref, out)
+
+    def run(self, G=32, unroll=2, stream=None):
+        dst, lit_off, lit_len, src, mlen, unit_start, lit, ref, out = self.args
+        c = _cfg(G, unroll, 0)
+        rc = lib().lz_purecopy_device(dst.numel(), ctypes.c_void_p(dst.data_ptr()),
+                                      ctypes.c_void_p(lit_off.data_ptr()), ctypes.c_void_p(lit_len.data_ptr()),
+                                      ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(mlen.data_ptr()),
+                                      unit_start.numel() - 1, ctypes.c_void_p(unit_start.data_ptr()),
+                                      ctypes.c_void_p(lit.data_ptr()), lit.numel(), ctypes.c_void_p(ref.data_ptr()),
+                                      ref.numel(), ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
+                                      _stream(stream))
+        if rc:
+            raise LzError(rc, "lz_purecopy_device")
+
+
 def purecopy(dst, lit_off, lit_len, src, mlen, unit_start, lit, ref, out, G=32, unroll=2, stream=None):
     """Runs pre-decoded tokens on the device (all arguments torch cuda tensors).
     Bounds are checked here on the host copies before launch."""
-    import torch
-    T = dst.numel()
-    for t in (lit_off, lit_len, src, mlen):
-        assert t.numel() == T
-    if T:
-        ends = (dst.to(torch.int64) + lit_len.to(torch.int64) + mlen.to(torch.int64)).max().item()
-        lend = (lit_off.to(torch.int64) + lit_len.to(torch.int64)).max().item()
-        send = (src.to(torch.int64) + mlen.to(torch.int64)).max().item()
-        if ends > out.numel() or lend > lit.numel() or send > ref.numel():
-            raise ValueError("pre-decoded tokens index outside their buffers")
-        us = unit_start.to("cpu").to(torch.int64)
-        if us[0].item() != 0 or us[-1].item() != T or bool((us[1:] < us[:-1]).any()):
-            raise ValueError("unit starts must run from 0 to ntok")
-    c = _cfg(G, unroll, 0)
-    rc = lib().lz_purecopy_device(T, ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(lit_off.data_ptr()),
-                                  ctypes.c_void_p(lit_len.data_ptr()), ctypes.c_void_p(src.data_ptr()),
-                                  ctypes.c_void_p(mlen.data_ptr()), unit_start.numel() - 1,
-                                  ctypes.c_void_p(unit_start.data_ptr()), ctypes.c_void_p(lit.data_ptr()),
-                                  lit.numel(), ctypes.c_void_p(ref.data_ptr()), ref.numel(),
-                                  ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c), _stream(stream))
-    if rc:
-        raise LzError(rc, "lz_purecopy_device")
+    PureCopy(dst, lit_off, lit_len, src, mlen, unit_start, lit, ref, out).run(G, unroll, stream)
 
 
 class RangePlan:
@@ -777,3 +798,65 @@ def encode_learned(x, sel, log2_bs=16, bounds=BOUNDS_CFG, max_chain=32, n_thread
     if rc:
         raise LzError(rc, "lz_encode_learned")
     return _take_archive(pa, sz.value), ch[:nb]
+
+
+# ------------------------------------------------------------ read seek
+
+class ReadIndex:
+    """Record id -> LZ block index of an input (records of `lines` lines)."""
+
+    def __init__(self, x=None, log2_bs=16, lines=4, path=None):
+        h = _vp()
+        if path is not None:
+            rc = lib().lz_read_index_load(os.fsencode(path), ctypes.byref(h))
+            what = "lz_read_index_load"
+        else:
+            a = _u8(x)
+            rc = lib().lz_read_index_build(a.ctypes.data, a.size, log2_bs, lines, ctypes.byref(h))
+            what = "lz_read_index_build"
+        if rc:
+            raise LzError(rc, what)
+        self.h = h
+        self.records = int(lib().lz_read_index_records(h))
+
+    def block(self, b):
+        fi, fo = _u64(), _u64()
+        rc = lib().lz_read_index_block(self.h, b, ctypes.byref(fi), ctypes.byref(fo))
+        if rc:
+            raise LzError(rc, "lz_read_index_block")
+        return fi.value, fo.value
+
+    def save(self, path):
+        rc = lib().lz_read_index_save(self.h, os.fsencode(path))
+        if rc:
+            raise LzError(rc, "lz_read_index_save")
+
+    def seek(self, da, rid, out=None, scratch=None, stream=None):
+        """Record `rid` of DeviceArchive `da` as a device tensor (synchronous)."""
+        import torch
+        sb = _u64()
+        rc = lib().lz_seek_record_scratch_bytes(da.h, self.h, rid, ctypes.byref(sb))
+        if rc:
+            raise LzError(rc, "lz_seek_record_scratch_bytes")
+        if scratch is None or scratch.numel() < sb.value:
+            scratch = torch.empty(sb.value, dtype=torch.uint8, device=da.buf.device)
+        if out is None:
+            out = torch.empty(1 << 16, dtype=torch.uint8, device=da.buf.device)
+        n = _u64()
+        rc = lib().lz_seek_record(da.h, self.h, rid, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                  ctypes.c_void_p(scratch.data_ptr()), scratch.numel(), ctypes.byref(n),
+                                  _stream(stream))
+        if rc:
+            raise LzError(rc, "lz_seek_record")
+        return out[:n.value]
+
+    def free(self):
+        if getattr(self, "h", None):
+            lib().lz_read_index_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
