@@ -208,6 +208,44 @@ uint64_t lz_device_n(const lz_dev* h);
 uint32_t lz_device_levels(const lz_dev* h); /* number of match depths (launches of schedule 1) */
 void lz_device_close(lz_dev* h);
 
+/* ------------------------------------------------------------ entropy stage */
+
+/* Tile-rANS entropy stage (Sec. 2, Experimental Setup: entropy decoded over
+ * 64 KB tiles, cut independently of the LZ blocks, before the match phase).
+ * lz_entropy_encode codes a container (host): every byte region of it -- the
+ * header and block table, each stream, and each of the four byte planes of
+ * the 32-bit sources (stride 4) -- in tiles of at most 65,536 symbols, each
+ * stored raw, as one repeated byte, or order-0 rANS coded, whichever is
+ * smallest.  rANS: probabilities quantised to 1/4096 (f = floor(count * 4096 /
+ * N), present symbols at least 1, the sum corrected on the most frequent
+ * symbol), 32-bit states in [2^16, 2^32) renormalised by 16-bit words, 64
+ * states interleaved (symbol i to state i mod 64), words consumed in symbol
+ * order.  Coded container "LZE1": a 64-byte header, the coded container's
+ * 128-byte header, 32-byte tile records {payload offset, first output byte,
+ * symbols, payload bytes, output stride, mode}, payloads; a rANS payload is
+ * a 32-byte symbol bitmap, u16 frequencies, 64 u32 initial states, u16 words.
+ * Library-allocated; free with lz_free. */
+int lz_entropy_encode(const uint8_t* arc, uint64_t arc_size, uint8_t** coded, uint64_t* coded_size);
+/* Validates a coded container (every tile inside it, tables summing to 4096,
+ * every output byte written exactly once); decoded size, tile count and tiles
+ * per mode {raw, rANS, repeated} (each may be NULL). */
+int lz_entropy_info(const uint8_t* coded, uint64_t size, uint64_t* decoded_size, uint64_t* tiles,
+                    uint64_t* tiles_by_mode);
+/* Device bytes lz_device_open_coded needs: the resident coded container plus
+ * the layout of lz_device_bytes for the container it decodes to. */
+int lz_coded_device_bytes(const uint8_t* coded, uint64_t size, uint64_t* bytes);
+/* Opens a coded container: validated on the host, copied to d_buf, entropy-
+ * decoded on the GPU (one wave per tile) into the handle's archive region,
+ * then read back once to validate the decoded container and build the plan
+ * (LZ_E_CORRUPT if a tile decodes inconsistently).  The handle then decodes
+ * like one from lz_device_open, and lz_entropy_decode_device re-runs the
+ * entropy stage into the archive region (asynchronous on `stream`; errors
+ * show in lz_device_check), so a full pipeline decode is that call followed
+ * by lz_decode_device on the same stream. */
+int lz_device_open_coded(const uint8_t* coded, uint64_t size, void* d_buf, uint64_t d_cap, void* stream,
+                         lz_dev** h);
+int lz_entropy_decode_device(lz_dev* h, void* stream);
+
 /* ------------------------------------------------------------ range decode */
 
 /* Region seek on a device-resident archive (Abstract; Sec. 1 "Positioning":

@@ -6,10 +6,12 @@ the oracle shares no code with it: ``lz_oracle.c`` is a plain sequential
 implementation written from the paper's definitions (see its header), and
 ``mlp_ref.py`` is a float64 numpy restatement of the threshold selector.
 
-Wrapped functions (each cites the passage it follows in ``lz_oracle.c``):
-``fnv1a64``, ``encode`` (exhaustive greedy parse), ``write_archive``,
-``decode``, ``tokens``, ``levels``, ``entropy_size``, ``purecopy``,
-``exec_tokens``.
+Wrapped functions (each cites the passage it follows in ``lz_oracle.c`` and
+``lz_rans.c``): ``fnv1a64``, ``encode`` (exhaustive greedy parse),
+``write_archive``, ``decode``, ``tokens``, ``levels``, ``entropy_size``,
+``purecopy``, ``exec_tokens``, and the tile-rANS stage: ``rans_normalise``,
+``rans_encode_tile``, ``rans_decode_tile``, ``entropy_encode``,
+``entropy_decode``.
 """
 import ctypes
 import os
@@ -73,6 +75,16 @@ def lib():
         L.or_decode_levels_omp.argtypes = [_u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _vp]
         L.or_exec_tokens.restype = ctypes.c_int
         L.or_exec_tokens.argtypes = [_u64, _u64, _vp, _vp, _vp, _vp, _u64, _vp]
+        L.or_rans_normalise.restype = ctypes.c_int
+        L.or_rans_normalise.argtypes = [_vp, _u64, _vp]
+        L.or_rans_encode_tile.restype = _u64
+        L.or_rans_encode_tile.argtypes = [_vp, _u64, _u64, ctypes.POINTER(_vp)]
+        L.or_rans_decode_tile.restype = ctypes.c_int
+        L.or_rans_decode_tile.argtypes = [_vp, _u64, _u64, _vp, _u64]
+        L.or_entropy_encode.restype = ctypes.c_int
+        L.or_entropy_encode.argtypes = [_vp, _u64, ctypes.POINTER(_vp), _p64]
+        L.or_entropy_decode.restype = ctypes.c_int
+        L.or_entropy_decode.argtypes = [_vp, _u64, _vp, _u64, _p64]
         _LIB = L
     return _LIB
 
@@ -250,6 +262,66 @@ def purecopy(n, dst, lit_off, lit_len, src, mlen, lit, ref):
     lib().or_purecopy(d.size, d.ctypes.data, lo.ctypes.data, ll.ctypes.data, s.ctypes.data, ml.ctypes.data,
                       lt.ctypes.data, rf.ctypes.data, out.ctypes.data)
     return out[:n]
+
+
+def rans_normalise(counts):
+    """Quantised frequencies (total 4096) of a 256-entry count vector."""
+    c = np.ascontiguousarray(counts, dtype=np.uint64)
+    f = np.zeros(256, np.uint32)
+    if not lib().or_rans_normalise(c.ctypes.data, int(c.sum()), f.ctypes.data):
+        raise OracleError(OR_E_INVAL, "rans_normalise")
+    return f
+
+
+def rans_encode_tile(sym, stride=1):
+    """rANS payload of the symbols sym[0], sym[stride], ... (bytes)."""
+    a = _u8(sym)
+    N = (a.size + stride - 1) // stride
+    out = _vp()
+    n = lib().or_rans_encode_tile(a.ctypes.data, stride, N, ctypes.byref(out))
+    if n == 0:
+        raise OracleError(OR_E_INVAL, "rans_encode_tile")
+    res = np.ctypeslib.as_array(ctypes.cast(out, ctypes.POINTER(ctypes.c_uint8)), shape=(n,)).copy()
+    lib().or_free(out)
+    return res
+
+
+def rans_decode_tile(payload, N):
+    p = _u8(payload)
+    out = np.zeros(max(N, 1), np.uint8)
+    rc = lib().or_rans_decode_tile(p.ctypes.data, p.size, N, out.ctypes.data, 1)
+    if rc:
+        raise OracleError(rc, "rans_decode_tile")
+    return out[:N]
+
+
+def entropy_encode(arc):
+    """Tile-rANS coded container of a container."""
+    a = _u8(arc)
+    out = _vp()
+    n = _u64()
+    rc = lib().or_entropy_encode(a.ctypes.data, a.size, ctypes.byref(out), ctypes.byref(n))
+    if rc:
+        raise OracleError(rc, "entropy_encode")
+    res = np.ctypeslib.as_array(ctypes.cast(out, ctypes.POINTER(ctypes.c_uint8)), shape=(n.value,)).copy()
+    lib().or_free(out)
+    return res
+
+
+def entropy_decode(coded):
+    """The container a coded container decodes to (every byte written once)."""
+    c = _u8(coded)
+    if c.size < 16:
+        raise OracleError(OR_E_CORRUPT, "entropy_decode")
+    total = int(np.frombuffer(c[8:16].tobytes(), np.uint64)[0])
+    if total > (1 << 40):
+        raise OracleError(OR_E_CORRUPT, "entropy_decode")
+    out = np.zeros(max(total, 1), np.uint8)
+    n = _u64()
+    rc = lib().or_entropy_decode(c.ctypes.data, c.size, out.ctypes.data, out.size, ctypes.byref(n))
+    if rc:
+        raise OracleError(rc, "entropy_decode")
+    return out[:n.value]
 
 
 def exec_tokens(n, lit_len, mlen, src, lit):

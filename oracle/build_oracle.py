@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def build(verbose=False):
-    srcs = [os.path.join(HERE, f) for f in ("lz_oracle.c", "lz_levels_omp.c")]
+    srcs = [os.path.join(HERE, f) for f in ("lz_oracle.c", "lz_levels_omp.c", "lz_rans.c")]
     out = os.path.join(HERE, "liboracle.so")
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-Wall", "-Wextra", "-shared", "-fPIC"] + srcs + ["-o", out, "-lm"]
     if verbose:

@@ -919,6 +919,10 @@ struct lz_dev {
   std::vector<uint64_t> h_wdst;  // per window: output position of its first byte
   uint32_t log2_grain = 20;      // output grains: see Plan
   std::vector<uint64_t> grain_low;
+  // coded archives: the tile-rANS container stays resident; the entropy stage
+  // decodes it into the archive region (d_arc) before the match phase
+  uint8_t* d_coded = nullptr;
+  uint64_t coded_size = 0, coded_payload = 0, coded_tiles = 0;
   int cu_count = 0;
   // replayable launch sequences, one per (output, config)
   struct GraphKey {
@@ -1233,11 +1237,14 @@ int lz_device_bytes(const uint8_t* arc, uint64_t arc_size, uint64_t* bytes) {
   return 0;
 }
 
-int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t d_cap, void* stream, lz_dev** out) {
-  if (!out || !d_buf) return lz::fail(LZ_E_INVAL, "null argument");
-  *out = nullptr;
-  // the buffer holds words that kernels update atomically (error flags, counters)
-  if ((uintptr_t)d_buf & 255u) return lz::fail(LZ_E_INVAL, "d_buf must be 256-byte aligned");
+}  // extern "C"
+
+namespace {
+
+// Opens a validated archive whose device layout starts at d_buf; with
+// upload_archive false its bytes are already in the archive region.
+int open_impl(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t d_cap, void* stream, lz_dev** out,
+              bool upload_archive) {
   lz::ArcView v;
   int rc = lz::view_archive(arc, arc_size, &v);
   if (rc) return rc;
@@ -1318,8 +1325,10 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
     ok = ok && hipMemcpyAsync(q.dst, hp + off, q.bytes, hipMemcpyHostToDevice, s) == hipSuccess;
     off += (q.bytes + 255) & ~uint64_t(255);
   }
-  memcpy(hp + off, arc, v.total);
-  ok = ok && hipMemcpyAsync(h->d_arc, hp + off, v.total, hipMemcpyHostToDevice, s) == hipSuccess;
+  if (upload_archive) {
+    memcpy(hp + off, arc, v.total);
+    ok = ok && hipMemcpyAsync(h->d_arc, hp + off, v.total, hipMemcpyHostToDevice, s) == hipSuccess;
+  }
   ok = ok && hipStreamSynchronize(s) == hipSuccess;
   ok = (hipHostFree(hp) == hipSuccess) && ok;
   if (!ok) {
@@ -1328,6 +1337,88 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
   }
   *out = h;
   return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t d_cap, void* stream, lz_dev** out) {
+  if (!out || !d_buf) return lz::fail(LZ_E_INVAL, "null argument");
+  *out = nullptr;
+  // the buffer holds words that kernels update atomically (error flags, counters)
+  if ((uintptr_t)d_buf & 255u) return lz::fail(LZ_E_INVAL, "d_buf must be 256-byte aligned");
+  return open_impl(arc, arc_size, d_buf, d_cap, stream, out, true);
+}
+
+int lz_coded_device_bytes(const uint8_t* coded, uint64_t size, uint64_t* bytes) {
+  if (!bytes) return lz::fail(LZ_E_INVAL, "null output");
+  lz::CodedView cv;
+  int rc = lz::parse_coded(coded, size, &cv);
+  if (rc) return rc;
+  lz::ArcView hv;
+  rc = lz::view_header(coded + 64, &hv);
+  if (rc) return rc;
+  *bytes = ((size + 16 + 255) & ~uint64_t(255)) + layout(hv).total;
+  return 0;
+}
+
+int lz_device_open_coded(const uint8_t* coded, uint64_t size, void* d_buf, uint64_t d_cap, void* stream,
+                         lz_dev** out) {
+  if (!out || !d_buf) return lz::fail(LZ_E_INVAL, "null argument");
+  *out = nullptr;
+  if ((uintptr_t)d_buf & 255u) return lz::fail(LZ_E_INVAL, "d_buf must be 256-byte aligned");
+  uint64_t need = 0;
+  int rc = lz_coded_device_bytes(coded, size, &need);  // validates the whole coded container
+  if (rc) return rc;
+  if (d_cap < need)
+    return lz::fail(LZ_E_NOMEM, "device buffer %llu < %llu bytes", (unsigned long long)d_cap, (unsigned long long)need);
+  lz::CodedView cv;
+  (void)lz::parse_coded(coded, size, &cv);
+  const uint64_t creg = (size + 16 + 255) & ~uint64_t(255);
+  uint8_t* d_coded = (uint8_t*)d_buf;
+  uint8_t* base = d_coded + creg;
+  const DevLayout L = [&] {
+    lz::ArcView hv;
+    (void)lz::view_header(coded + 64, &hv);
+    return layout(hv);
+  }();
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0, cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return lz::fail(LZ_E_HIP, "device query failed");
+  // resident coded container; entropy stage into the archive region; the
+  // decoded container comes back to the host for validation and planning
+  uint8_t* hp = nullptr;
+  const uint64_t stage = std::max<uint64_t>(size, cv.out_size) + 16;
+  if (hipHostMalloc((void**)&hp, stage, 0) != hipSuccess)
+    return lz::fail(LZ_E_NOMEM, "pinned staging allocation of %llu bytes failed", (unsigned long long)stage);
+  uint32_t* d_err = (uint32_t*)(base + L.ctrl) + 2;
+  uint32_t err = 0;
+  memcpy(hp, coded, size);
+  bool ok = hipMemcpyAsync(d_coded, hp, size, hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipMemsetAsync(d_err, 0, 4, s) == hipSuccess;
+  if (ok) ok = lz::entropy_launch(d_coded, cv.payload, cv.n_tiles, base + L.arc, d_err, cu, stream) == 0;
+  ok = ok && hipMemcpyAsync(hp, base + L.arc, cv.out_size, hipMemcpyDeviceToHost, s) == hipSuccess &&
+       hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, s) == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
+  if (!ok || err) {
+    (void)hipHostFree(hp);
+    return ok ? lz::fail(LZ_E_CORRUPT, "entropy stage failed (err %u)", err) : lz::fail(LZ_E_HIP, "entropy stage failed");
+  }
+  rc = open_impl(hp, cv.out_size, base, d_cap - creg, stream, out, false);
+  (void)hipHostFree(hp);
+  if (rc) return rc;
+  (*out)->d_coded = d_coded;
+  (*out)->coded_size = size;
+  (*out)->coded_payload = cv.payload;
+  (*out)->coded_tiles = cv.n_tiles;
+  return 0;
+}
+
+int lz_entropy_decode_device(lz_dev* h, void* stream) {
+  if (!h || !h->d_coded) return lz::fail(LZ_E_INVAL, "not a coded archive handle");
+  return lz::entropy_launch(h->d_coded, h->coded_payload, h->coded_tiles, h->d_arc, h->d_ctrl + 2, h->cu_count, stream);
 }
 
 uint64_t lz_device_n(const lz_dev* h) { return h ? h->v.n : 0; }
@@ -1446,6 +1537,12 @@ int lz_device_check(lz_dev* h, void* stream) {
   uint32_t err = 0;
   HIPCHK(hipMemcpyAsync(&err, h->d_ctrl + 1, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  uint32_t eerr = 0;
+  if (h->d_coded) {
+    HIPCHK(hipMemcpyAsync(&eerr, h->d_ctrl + 2, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  if (eerr) return lz::fail(LZ_E_CORRUPT, "the entropy stage met a corrupt tile (err %u)", eerr);
   if (err & 1u) return lz::fail(LZ_E_BUSY, "a bounded device wait expired (err %u)", err);
   if (err & 4u) return lz::fail(LZ_E_CORRUPT, "a match record outside the output was skipped (err %u)", err);
   if (err) return lz::fail(LZ_E_INVAL, "a kernel was launched with the wrong workgroup size (err %u)", err);

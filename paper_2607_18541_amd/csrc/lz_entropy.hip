@@ -1,0 +1,279 @@
+// lz_entropy.hip -- gfx950 decoder of the tile-rANS entropy stage.
+//
+// One wave64 per tile (Sec. 2: entropy decoded over 64 KB tiles by many
+// cooperating groups, tiles cut independently of the LZ blocks); the tile's
+// 64 interleaved rANS states live one per lane, so a step decodes 64
+// consecutive symbols.  Steps run in blocks of 8: a block's 512 symbols are
+// staged in LDS and written by one coalesced store at the start of the next
+// block, right after the word ring advances, so the ring's wait (stores and
+// loads share one counter on this GPU) finds that store a block old.  Per wave, LDS
+// holds the slot -> symbol table (4096 bytes), the frequencies and cumulative
+// frequencies (256 + 256 u16) and a ring of 2 x 1024 words of the tile's word
+// stream, refilled a chunk at a time, so a renormalisation reads LDS.  The
+// lanes that need a word in a step take consecutive words in lane order
+// (ballot + popcount of the lower lanes).  Raw tiles are copied and repeated-
+// byte tiles filled.  Every bound was checked on the host; a word read past
+// the payload (possible only on a corrupt stream that passed those checks)
+// sets an error bit and stops the tile.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lz_internal.h"
+
+// Global-memory accesses go through address-space-1 pointers: flat stores
+// would also count against the LDS wait counter, so every step's LDS lookups
+// would wait for the previous step's output store.
+#define LZ_G __attribute__((address_space(1)))
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T gld(const uint8_t* p) {
+  return *(const LZ_G T*)(p);
+}
+__device__ __forceinline__ void gst8(uint8_t* p, uint8_t v) { *(LZ_G uint8_t*)(p) = v; }
+
+constexpr int kWaves = 4;  // tiles per workgroup
+constexpr uint32_t kRing = 1024, kChunk = 512;  // word ring: two chunks of 512 words
+constexpr uint32_t kBlock = 8;                  // steps between ring advances and output stores
+
+struct alignas(16) WaveLds {
+  uint8_t sym[lz::kRansM];
+  uint32_t fc[256];  // f | c << 16
+  uint16_t ring[kRing];
+  uint8_t outb[kBlock * 64];  // one block's decoded symbols, in order
+};
+
+__device__ __forceinline__ uint32_t ld_u32_unaligned(const uint8_t* p) {
+  return (uint32_t)gld<uint8_t>(p) | ((uint32_t)gld<uint8_t>(p + 1) << 8) | ((uint32_t)gld<uint8_t>(p + 2) << 16) |
+         ((uint32_t)gld<uint8_t>(p + 3) << 24);
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4_a1 __attribute__((ext_vector_type(4), aligned(1)));
+typedef unsigned long long uint64_a1 __attribute__((aligned(1)));
+
+// Chunk k of the word stream (words [512 k, 512 k + 512), n words in all):
+// lane j holds words 8 j .. 8 j + 7 of it (16 bytes); past the end, zeros.
+// The load is issued a block before its bytes are written to the ring.
+__device__ __forceinline__ u32x4 fetch_chunk(const uint8_t* words, uint64_t n, uint64_t k, int lane) {
+  const uint64_t w0 = k * kChunk + 8 * (uint64_t)lane;
+  if (w0 + 8 <= n) return *(const LZ_G u32x4_a1*)(words + 2 * w0);
+  uint32_t d[4] = {0u, 0u, 0u, 0u};
+  for (uint64_t q = 0; w0 < n && q < 2 * (n - w0); ++q) d[q >> 2] |= (uint32_t)gld<uint8_t>(words + 2 * w0 + q) << (8 * (q & 3));
+  return u32x4{d[0], d[1], d[2], d[3]};
+}
+
+__device__ __forceinline__ void put_chunk(WaveLds& L, uint64_t k, u32x4 v, int lane) {
+  ((u32x4*)(L.ring + (k & 1) * kChunk))[lane] = v;
+}
+
+__global__ __launch_bounds__(64 * kWaves) void k_entropy(const uint8_t* coded, uint64_t payload_off, uint64_t n_tiles,
+                                                         uint8_t* out, uint32_t* err) {
+  __shared__ WaveLds lds[kWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  WaveLds& L = lds[wv];
+  const uint64_t nwaves = (uint64_t)gridDim.x * kWaves;
+  for (uint64_t t = (uint64_t)blockIdx.x * kWaves + wv; t < n_tiles; t += nwaves) {
+    const uint8_t* r = coded + lz::kCodedHead + 32 * t;  // directory record
+    const uint64_t po = __builtin_amdgcn_readfirstlane(ld_u32_unaligned(r)) |
+                        ((uint64_t)__builtin_amdgcn_readfirstlane(ld_u32_unaligned(r + 4)) << 32);
+    const uint64_t dst = __builtin_amdgcn_readfirstlane(ld_u32_unaligned(r + 8)) |
+                         ((uint64_t)__builtin_amdgcn_readfirstlane(ld_u32_unaligned(r + 12)) << 32);
+    const uint32_t cnt = __builtin_amdgcn_readfirstlane(ld_u32_unaligned(r + 16));
+    const uint32_t pb = __builtin_amdgcn_readfirstlane(ld_u32_unaligned(r + 20));
+    const uint32_t stride = __builtin_amdgcn_readfirstlane(ld_u32_unaligned(r + 24));
+    const uint32_t mode = __builtin_amdgcn_readfirstlane(ld_u32_unaligned(r + 28));
+    const uint8_t* p = coded + payload_off + po;
+    uint8_t* o = out + dst;
+    if (mode == 2) {
+      const uint8_t v = gld<uint8_t>(p);
+#pragma clang loop vectorize(disable) unroll(disable)
+      for (uint32_t i = lane; i < cnt; i += 64) gst8(o + (uint64_t)i * stride, v);
+      continue;
+    }
+    if (mode == 0) {
+#pragma clang loop vectorize(disable) unroll(disable)
+      for (uint32_t i = lane; i < cnt; i += 64) gst8(o + (uint64_t)i * stride, gld<uint8_t>(p + i));
+      continue;
+    }
+    // frequencies: symbol s present <=> bit s of the bitmap; its f is the
+    // (number of present symbols below s)-th u16 after the bitmap
+    uint32_t below = 0;  // present symbols below this lane's group of 64
+    for (int g = 0; g < 4; ++g) {
+      const int s = g * 64 + lane;
+      const uint64_t bits = ((uint64_t)ld_u32_unaligned(p + 8 * g + 4) << 32) | ld_u32_unaligned(p + 8 * g);
+      const bool present = (bits >> lane) & 1;
+      const uint32_t idx = below + __builtin_popcountll(bits & ((1ull << lane) - 1));
+      L.fc[s] = present ? (uint32_t)(gld<uint8_t>(p + 32 + 2 * idx) | (gld<uint8_t>(p + 33 + 2 * idx) << 8)) : 0u;
+      below += __builtin_popcountll(bits);
+    }
+    const uint32_t nsym = below;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // cumulative frequencies: 4 groups of 64, each a wave prefix sum
+    uint32_t run = 0;
+    for (int g = 0; g < 4; ++g) {
+      uint32_t v = L.fc[g * 64 + lane], x = v;
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+      }
+      L.fc[g * 64 + lane] = v | ((run + x - v) << 16);
+      run += __shfl(x, 63, 64);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // slot -> symbol: mark the first slot of every present symbol above 0
+    // with the symbol, then take the running maximum over the slots (symbols
+    // start in increasing order, and symbol 0, when present, starts at 0)
+    {
+      u32x4* row = (u32x4*)L.sym + 4 * lane;  // this lane's 64 slots
+      const u32x4 z = {0u, 0u, 0u, 0u};
+      row[0] = z;
+      row[1] = z;
+      row[2] = z;
+      row[3] = z;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (int g = 0; g < 4; ++g) {
+        const int s = g * 64 + lane;
+        const uint32_t v = L.fc[s];
+        if (s > 0 && (v & 0xFFFFu)) L.sym[v >> 16] = (uint8_t)s;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // the largest symbol starting in each lane's 64 slots, by LDS atomics
+      // into a scratch row of the (not yet filled) word ring
+      uint32_t* rowmax = (uint32_t*)L.ring;
+      rowmax[lane] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (int g = 0; g < 4; ++g) {
+        const int s = g * 64 + lane;
+        const uint32_t v = L.fc[s];
+        if (s > 0 && (v & 0xFFFFu)) atomicMax(rowmax + (v >> 22), (uint32_t)s);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const uint32_t mx = rowmax[lane];
+      // maximum over the lanes below: an exclusive max-scan of the lane maxima
+      uint32_t inc = mx;
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc = max(inc, y);
+      }
+      uint32_t run = __shfl_up(inc, 1, 64);
+      if (lane == 0) run = 0;
+#pragma unroll 1
+      for (int q = 0; q < 4; ++q) {
+        u32x4 w = row[q];
+        for (int e = 0; e < 4; ++e) {
+          uint32_t o = 0;
+          for (int b = 0; b < 4; ++b) {
+            run = max(run, (w[e] >> (8 * b)) & 0xFFu);
+            o |= run << (8 * b);
+          }
+          w[e] = o;
+        }
+        row[q] = w;
+      }
+    }
+    // states, and the word stream into the ring
+    const uint8_t* st = p + 32 + 2 * nsym;
+    uint32_t x = ld_u32_unaligned(st + 4 * lane);
+    const uint8_t* words = st + 4 * lz::kRansLanes;
+    const uint64_t nwords = (pb - (32 + 2 * nsym + 4 * lz::kRansLanes)) / 2;
+    put_chunk(L, 0, fetch_chunk(words, nwords, 0, lane), lane);
+    put_chunk(L, 1, fetch_chunk(words, nwords, 1, lane), lane);
+    u32x4 ahead = fetch_chunk(words, nwords, 2, lane);  // in flight until the ring next advances
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    uint32_t wpos = 0, chunk = 0;
+    // one step: state `lane` decodes symbol 64 k + lane (when below cnt);
+    // the states that fell below 2^16 take the next words in lane order
+    auto step = [&](bool act) -> uint32_t {
+      const uint32_t slot = x & (lz::kRansM - 1);
+      const uint32_t sv = L.sym[slot];
+      const uint32_t fcv = L.fc[sv];
+      const uint32_t nx = (fcv & 0xFFFFu) * (x >> 12) + slot - (fcv >> 16);
+      if (act) x = nx;
+      const bool need = act && x < lz::kRansL;
+      const uint64_t m = __ballot(need);
+      const uint32_t pos = wpos + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      const uint32_t w = L.ring[pos & (kRing - 1)];
+      x = need ? ((x << 16) | w) : x;
+      wpos += (uint32_t)__builtin_popcountll(m);
+      return sv;
+    };
+    // symbols [i0, i0 + 512) of the last block, from LDS to the output:
+    // lane j writes symbols i0 + 8 j .. + 7 (one 8-byte store when they are
+    // consecutive in the output and all present)
+    auto flush = [&](uint32_t i0) {
+      const uint32_t a = i0 + 8 * (uint32_t)lane;
+      const uint64_t v = ((const uint64_t*)L.outb)[lane];
+      if (stride == 1 && a + 8 <= cnt) {
+        *(LZ_G uint64_a1*)(o + a) = v;
+      } else {
+        for (uint32_t u = 0; u < 8 && a + u < cnt; ++u) gst8(o + (uint64_t)(a + u) * stride, (uint8_t)(v >> (8 * u)));
+      }
+    };
+    const uint32_t steps = (cnt + 63) / 64;
+    for (uint32_t k0 = 0; k0 < steps; k0 += kBlock) {
+      // a block reads at most 512 words: the ring (chunks `chunk`, +1) covers
+      // it after at most one advance; `ahead` was loaded a block ago, and the
+      // last output store was issued a block ago too
+      if ((wpos >> 9) > chunk) {
+        __builtin_amdgcn_wave_barrier();
+        ++chunk;
+        put_chunk(L, chunk + 1, ahead, lane);
+        ahead = fetch_chunk(words, nwords, chunk + 2, lane);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (k0) {
+        flush((k0 - kBlock) * 64);
+        __builtin_amdgcn_wave_barrier();  // outb is rewritten below
+      }
+#pragma unroll
+      for (int u = 0; u < (int)kBlock; ++u) {
+        if (k0 + u >= steps) break;
+        const uint32_t i = (k0 + u) * 64 + lane;
+        const uint32_t sv = step(i < cnt);
+        L.outb[u * 64 + lane] = (uint8_t)sv;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (steps) flush((steps - 1) / kBlock * kBlock * 64);
+    // words past the stream read as zero, so a corrupt stream decodes to
+    // garbage but stays in bounds; it is caught here: every word consumed,
+    // and every state back at the encoder's start (2^16)
+    const bool short_words = wpos != nwords;
+    const bool off_end = __any(x != lz::kRansL);
+    if (lane == 0 && (short_words || off_end)) atomicOr(err, short_words ? 1u : 2u);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+}  // namespace
+
+namespace lz {
+
+int entropy_launch(const uint8_t* d_coded, uint64_t payload_off, uint64_t n_tiles, uint8_t* d_out, uint32_t* d_err,
+                   int cu_count, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (n_tiles == 0) return 0;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_entropy, 64 * kWaves, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const uint64_t groups = std::min<uint64_t>((n_tiles + kWaves - 1) / kWaves, (uint64_t)per_cu * std::max(cu_count, 1));
+  hipLaunchKernelGGL(k_entropy, dim3((unsigned)groups), dim3(64 * kWaves), 0, s, d_coded, payload_off, n_tiles, d_out,
+                     d_err);
+  if (hipGetLastError() != hipSuccess) return fail(LZ_E_HIP, "entropy launch failed");
+  return 0;
+}
+
+}  // namespace lz

@@ -79,12 +79,11 @@ static void parallel_for(uint64_t count, unsigned threads, F&& f) {
 
 // ------------------------------------------------------------------ reading
 
-int view_archive(const uint8_t* arc, uint64_t size, ArcView* v) {
-  if (!arc || size < kHeader) return fail(LZ_E_CORRUPT, "archive shorter than its header");
+int view_header(const uint8_t* arc, ArcView* out) {
+  if (!arc) return fail(LZ_E_CORRUPT, "null header");
   if (rd_le(arc, 4) != kMagic || rd_le(arc + 4, 4) != 1) return fail(LZ_E_CORRUPT, "bad magic or version");
   ArcView a;
   a.base = arc;
-  a.size = size;
   a.n = rd_le(arc + 8, 8);
   if (a.n > (1ull << 48)) return fail(LZ_E_CORRUPT, "n out of range");
   a.log2_bs = (uint32_t)rd_le(arc + 16, 4);
@@ -127,6 +126,17 @@ int view_archive(const uint8_t* arc, uint64_t size, ArcView* v) {
   }
   off += 16;
   a.total = off;
+  *out = a;
+  return 0;
+}
+
+int view_archive(const uint8_t* arc, uint64_t size, ArcView* v) {
+  if (!arc || size < kHeader) return fail(LZ_E_CORRUPT, "archive shorter than its header");
+  ArcView a;
+  int rc = view_header(arc, &a);
+  if (rc) return rc;
+  a.size = size;
+  const uint64_t off = a.total;
   if (size < off) return fail(LZ_E_CORRUPT, "archive truncated (%llu < %llu)", (unsigned long long)size,
                               (unsigned long long)off);
   const uint64_t* T = a.tab();

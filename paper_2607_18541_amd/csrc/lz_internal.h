@@ -2,7 +2,10 @@
 #pragma once
 #include <stdint.h>
 
+#include <array>
+#include <atomic>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/lz.h"
@@ -34,6 +37,8 @@ struct ArcView {
 
 // Header and table checks only.
 int view_archive(const uint8_t* arc, uint64_t size, ArcView* v);
+// The layout a 128-byte header describes (offsets and total; no table checks).
+int view_header(const uint8_t* arc, ArcView* v);
 
 // A decoded token, block-local order.
 struct Tok {
@@ -58,6 +63,25 @@ int validate_archive(const ArcView& v, uint32_t n_threads);
 int compute_levels(const ArcView& v, uint32_t* levels, uint32_t* max_level, uint8_t* has_match = nullptr);
 
 unsigned hw_threads(uint32_t requested);
+
+// Tile-rANS entropy stage: tiles of at most kRansTile symbols, probabilities
+// in units of 1/kRansM, 32-bit states in [kRansL, 2^32), kRansLanes states.
+constexpr uint64_t kRansTile = 65536;
+constexpr uint64_t kCodedHead = 192;  // 64-byte header + a copy of the 128-byte container header
+constexpr uint32_t kRansM = 4096, kRansL = 1u << 16, kRansLanes = 64;
+bool rans_normalise(const uint64_t* count, uint64_t N, uint32_t* f);
+uint64_t rans_encode_tile(const uint8_t* sym, uint64_t stride, uint32_t N, std::vector<uint8_t>& out);
+struct CodedView {
+  const uint8_t* base = nullptr;
+  uint64_t size = 0, out_size = 0, n_tiles = 0, dir = 0, payload = 0;
+};
+// Header and directory checks of a coded container (bounds, tables, coverage).
+int parse_coded(const uint8_t* a, uint64_t size, CodedView* v);
+// Launches the tile decoder: tiles of the coded container at d_coded (device)
+// into d_out (the decoded container); d_err bit 0: a word read past a
+// payload, bit 1: a tile did not end in the encoder's initial states.
+int entropy_launch(const uint8_t* d_coded, uint64_t payload_off, uint64_t n_tiles, uint8_t* d_out, uint32_t* d_err,
+                   int cu_count, void* stream);
 
 // Learned threshold selector (host object behind lz_selector).
 constexpr uint32_t kSelIn = 64, kSelHidden = 128, kSelTuples = 16;

@@ -142,6 +142,11 @@ def lib():
             "lz_read_index_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
             "lz_seek_record_scratch_bytes": (ctypes.c_int, [_vp, _vp, _u64, _p64]),
             "lz_seek_record": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _p64, _vp]),
+            "lz_entropy_encode": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(_vp), _p64]),
+            "lz_entropy_info": (ctypes.c_int, [_vp, _u64, _p64, _p64, _vp]),
+            "lz_coded_device_bytes": (ctypes.c_int, [_vp, _u64, _p64]),
+            "lz_device_open_coded": (ctypes.c_int, [_vp, _u64, _vp, _u64, _vp, ctypes.POINTER(_vp)]),
+            "lz_entropy_decode_device": (ctypes.c_int, [_vp, _vp]),
             "lz_purecopy_device": (ctypes.c_int, [_u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp,
                                                   _u64, _vp, _u64, ctypes.POINTER(DecodeCfg), _vp]),
         }
@@ -293,21 +298,26 @@ def _stream(stream=None):
 
 
 class DeviceArchive:
-    """A validated archive resident in device memory (torch-owned buffer)."""
+    """A validated archive resident in device memory (torch-owned buffer).
+    coded=True: `arc` is a tile-rANS coded container (lz_entropy_encode),
+    entropy-decoded on the GPU at open and kept resident."""
 
-    def __init__(self, arc, device="cuda", stream=None):
+    def __init__(self, arc, device="cuda", stream=None, coded=False):
         import torch
         self.arc = _u8(arc)
+        self.coded = coded
         nb = _u64()
-        rc = lib().lz_device_bytes(self.arc.ctypes.data, self.arc.size, ctypes.byref(nb))
+        sizer = lib().lz_coded_device_bytes if coded else lib().lz_device_bytes
+        rc = sizer(self.arc.ctypes.data, self.arc.size, ctypes.byref(nb))
         if rc:
-            raise LzError(rc, "lz_device_bytes")
+            raise LzError(rc, "lz_coded_device_bytes" if coded else "lz_device_bytes")
         self.buf = torch.empty(nb.value, dtype=torch.uint8, device=device)
         h = _vp()
-        rc = lib().lz_device_open(self.arc.ctypes.data, self.arc.size, ctypes.c_void_p(self.buf.data_ptr()),
-                                  nb.value, _stream(stream), ctypes.byref(h))
+        opener = lib().lz_device_open_coded if coded else lib().lz_device_open
+        rc = opener(self.arc.ctypes.data, self.arc.size, ctypes.c_void_p(self.buf.data_ptr()), nb.value,
+                    _stream(stream), ctypes.byref(h))
         if rc:
-            raise LzError(rc, "lz_device_open")
+            raise LzError(rc, "lz_device_open_coded" if coded else "lz_device_open")
         self.h = h
         self.n = int(lib().lz_device_n(h))
         self.levels = int(lib().lz_device_levels(h))
@@ -340,6 +350,12 @@ class DeviceArchive:
                                           int(stage), _stream(stream))
         if rc:
             raise LzError(rc, "lz_decode_device_stage")
+
+    def entropy_decode_async(self, stream=None):
+        """Re-runs the entropy stage into the archive region (coded only)."""
+        rc = lib().lz_entropy_decode_device(self.h, _stream(stream))
+        if rc:
+            raise LzError(rc, "lz_entropy_decode_device")
 
     def check(self, stream=None):
         rc = lib().lz_device_check(self.h, _stream(stream))
@@ -860,3 +876,27 @@ class ReadIndex:
             self.free()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ entropy stage
+
+def entropy_encode(arc):
+    """Tile-rANS coded container of a container (host)."""
+    a = _u8(arc)
+    pa = _vp()
+    sz = _u64()
+    rc = lib().lz_entropy_encode(a.ctypes.data, a.size, ctypes.byref(pa), ctypes.byref(sz))
+    if rc:
+        raise LzError(rc, "lz_entropy_encode")
+    return _take_archive(pa, sz.value)
+
+
+def entropy_info(coded):
+    a = _u8(coded)
+    ds, nt = _u64(), _u64()
+    modes = np.zeros(3, np.uint64)
+    rc = lib().lz_entropy_info(a.ctypes.data, a.size, ctypes.byref(ds), ctypes.byref(nt), modes.ctypes.data)
+    if rc:
+        raise LzError(rc, "lz_entropy_info")
+    return {"decoded_size": ds.value, "tiles": nt.value, "raw": int(modes[0]), "rans": int(modes[1]),
+            "repeat": int(modes[2])}
