@@ -569,8 +569,9 @@ def run_batch(args, torch, lz):
 def run_serve(args, torch, lz):
     """Serving loop: Poisson arrivals of range decodes (lengths log-uniform
     16 KiB-64 MiB, offsets uniform) against one device-resident FASTQ-like
-    archive, admitted by slots and arena memory, one merged launch group per
-    tick.  Latency = submit to observed completion (host clock)."""
+    archive, admitted by slots and arena memory; each tick launches one merged
+    group per decode horizon.  Latency = submit to observed completion (host
+    clock)."""
     import synth
     dev = torch.device("cuda:0")
     n = args.size
@@ -612,13 +613,13 @@ def run_serve(args, torch, lz):
                 pending[rid] = (nxt, T0 + arrive[nxt])
                 nxt += 1
             srv.tick()
-            for rid in list(pending):
-                st, _ = srv.status(rid)
-                if st == 2:
-                    i, ta = pending.pop(rid)
-                    lat[i] = time.perf_counter() - ta
-                    srv.release(rid)
-                    done += 1
+            for rid in srv.completed():
+                i, ta = pending.pop(rid)
+                lat[i] = time.perf_counter() - ta
+                if srv.status(rid)[0] != 2:
+                    raise SystemExit("%s: request %d failed" % (label, i))
+                srv.release(rid)
+                done += 1
             if time.perf_counter() - last_log > 10:
                 last_log = time.perf_counter()
                 log("%s: served %d/%d requests" % (label, done, k))
@@ -666,7 +667,7 @@ def run_serve(args, torch, lz):
             "vs_baseline": None, "dtype": "u8", "data": "synthetic",
             "config": {"workload": "FASTQ-like %d B (12/16/24/32, %s), %d range requests of 16 KiB-64 MiB per "
                                    "level: all at once (saturated), then Poisson at fractions of that capacity"
-                                   % (n, "1 GiB segments" if seg else "one segment", k),
+                                   % (n, "%d MiB segments" % (seg >> 20) if seg else "one segment", k),
                        "arena_mib": args.arena, "slots": args.slots},
             "detail": {"alone_ms": round(per_req * 1e3, 2), "mean_request_bytes": int(lens.mean()),
                        "capacity_req_per_s": round(cap, 2), "loads": rows, "best": best}}

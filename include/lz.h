@@ -358,9 +358,15 @@ int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* const* d_out, c
  * (Sec. 1 "Positioning": compressed residency with sub-millisecond seek).
  * Requests queue in arrival order.  lz_serve_tick retires finished groups
  * (frees their scratch), admits waiting requests in order while one of
- * `slots` is free and the arena has room for the output and the scratch of
- * the group, and launches all requests admitted in that tick as one merged
- * range plan, alternating two streams so new groups overlap running ones.
+ * `slots` is free and the arena has room for the output, splits what it
+ * admitted by decode horizon (the grain where a request's prefix decode
+ * starts; on a segment-encoded archive, its segment) and launches one merged
+ * range plan per horizon, in order of each group's oldest request, round-robin
+ * over four streams so groups overlap each other and earlier ones.  Requests
+ * whose horizon already has a group on the device stay admitted (state 0)
+ * until it finishes and then join the next group of that horizon.  A group
+ * whose scratch does not fit sends later groups, then its own newest
+ * requests, back to the head of the queue (arrival order is kept).
  * A tick allocates no device or pinned memory (plan staging comes from a
  * pinned pool the server owns, which grows only while no group is in flight).
  * Outputs live in the arena until lz_serve_release.  A request that can never
@@ -375,6 +381,11 @@ int lz_serve_tick(lz_server* server, uint64_t* n_done, uint64_t* n_admitted);
 int lz_serve_status(lz_server* server, uint64_t id,
                     int* state /* 0 waiting, 1 running, 2 done, 3 released, 4 failed */, uint8_t** d_ptr);
 int lz_serve_release(lz_server* server, uint64_t id);
+/* Ids of requests that finished (done or failed) since the last call, in the
+ * order the ticks saw them finish, at most `cap` of them; returns how many
+ * were written.  Lets a caller find its finished requests without polling
+ * every outstanding id. */
+uint64_t lz_serve_completed(lz_server* server, uint64_t* ids, uint64_t cap);
 void lz_serve_stats(const lz_server* server, uint64_t* waiting, uint64_t* running_groups, uint64_t* arena_used,
                     uint64_t* arena_high_water);
 uint64_t lz_serve_max_running(const lz_server* server); /* most groups in flight after any tick so far */

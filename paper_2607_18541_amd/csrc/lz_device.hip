@@ -47,6 +47,7 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -2373,10 +2374,12 @@ extern "C" int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* cons
 // Requests wait in a FIFO; a tick first retires every launched group whose
 // completion event has fired (their requests become done, their scratch and
 // staging are freed), then admits waiting requests in arrival order while a
-// request slot is free and the device arena has room for its output plus its
-// share of scratch, and launches everything admitted in this tick as one
-// merged range plan on the next of two streams, so a new group runs while
-// earlier ones are still on the device.  Outputs stay in the arena until
+// request slot is free and the device arena has room for its output, splits
+// them by decode horizon and launches one merged range plan per horizon on the
+// next of four streams, so groups run beside each other and beside earlier
+// ones (a horizon with a group still on the device holds its new requests for
+// the next one); a group whose scratch does not fit sends later groups and
+// then its newest requests back to the head of the queue.  Outputs stay in the arena until
 // released.  A tick allocates and frees no device or pinned memory and creates
 // no events: plan staging comes from a pinned pool and completion events from
 // a pool, both owned by the server (freeing pinned memory waits for the whole
@@ -2428,6 +2431,7 @@ struct Extents {
 };
 
 constexpr uint64_t kPinPoolMin = 16ull << 20;  // initial pinned staging pool of a server
+constexpr int kServeStreams = 4;               // groups launched round-robin on these
 
 }  // namespace
 
@@ -2437,19 +2441,22 @@ struct lz_server {
   uint64_t arena_bytes = 0;
   uint32_t slots = 0;
   lz_decode_cfg cfg{64, 2, 1, 0};
-  hipStream_t streams[2] = {nullptr, nullptr};
+  hipStream_t streams[kServeStreams] = {};
   uint32_t next_stream = 0;
   struct Req {
     uint64_t id, off, len;
     uint64_t out_at = 0;          // arena offset of the output
+    uint64_t hz = 0;              // decode horizon (set on admission)
     int state = 0;                // 0 waiting, 1 running, 2 done, 3 released, 4 failed
   };
-  std::vector<Req> reqs;          // indexed by id
-  std::vector<uint64_t> fifo;     // waiting ids, arrival order
-  size_t fifo_head = 0;
+  std::vector<Req> reqs;          // indexed by id (ids increase in arrival order)
+  std::deque<uint64_t> queue;     // waiting ids, arrival order
+  std::vector<uint64_t> held;     // admitted, waiting for a running group of their horizon
+  std::deque<uint64_t> completed; // finished (done or failed), not yet taken by lz_serve_completed
   uint32_t active = 0;            // admitted (or failed), not yet released
   struct Group {
     hipEvent_t ev;
+    uint64_t hz;
     lz_range_plan* plan;
     uint64_t scratch_at, scratch_len, pin_at, pin_len;
     std::vector<uint64_t> ids;
@@ -2468,21 +2475,24 @@ struct lz_server {
       if (st) (void)hipStreamDestroy(st);
   }
   void finish_group(Group& G, int state) {
-    for (uint64_t id : G.ids) reqs[id].state = state;
+    for (uint64_t id : G.ids) {
+      reqs[id].state = state;
+      completed.push_back(id);
+    }
     mem.release(G.scratch_at, G.scratch_len);
     pin.release(G.pin_at, G.pin_len);
     ev_free.push_back(G.ev);
     lz_range_plan_free(G.plan);
   }
-  // the newest admission goes back to the head of the queue
-  void unadmit(std::vector<uint64_t>& ids, std::vector<uint64_t>& offs, std::vector<uint64_t>& lens) {
-    auto& r = reqs[ids.back()];
-    mem.release(r.out_at, r.len);
-    --active;
-    --fifo_head;
-    ids.pop_back();
-    offs.pop_back();
-    lens.pop_back();
+  // admitted requests back to the front of the queue, arrival order kept
+  void requeue(std::vector<uint64_t> ids) {
+    std::sort(ids.begin(), ids.end());
+    for (auto it = ids.rbegin(); it != ids.rend(); ++it) {
+      auto& r = reqs[*it];
+      mem.release(r.out_at, r.len);
+      --active;
+      queue.push_front(r.id);
+    }
   }
 };
 
@@ -2525,7 +2535,7 @@ int lz_serve_submit(lz_server* S, uint64_t off, uint64_t len, uint64_t* id) {
   r.off = off;
   r.len = len;
   S->reqs.push_back(r);
-  S->fifo.push_back(r.id);
+  S->queue.push_back(r.id);
   *id = r.id;
   return 0;
 }
@@ -2552,104 +2562,167 @@ int lz_serve_tick(lz_server* S, uint64_t* n_done, uint64_t* n_admitted) {
   }
   if (n_done) *n_done = done;
   if (rc_retire) return rc_retire;
-  // 2. admit in arrival order
-  std::vector<uint64_t> ids, offs, lens;
-  while (S->fifo_head < S->fifo.size() && S->active < S->slots) {
-    auto& r = S->reqs[S->fifo[S->fifo_head]];
+  // 2. admit in arrival order while a slot and room for the output remain
+  std::vector<uint64_t> adm;
+  while (!S->queue.empty() && S->active < S->slots) {
+    auto& r = S->reqs[S->queue.front()];
     uint64_t at;
-    if (!S->mem.alloc(r.len, &at)) break;  // head waits for memory: FIFO order
+    if (!S->mem.alloc(r.len, &at)) break;  // the head waits for memory
     r.out_at = at;
-    ids.push_back(r.id);
-    offs.push_back(r.off);
-    lens.push_back(r.len);
-    ++S->fifo_head;
+    r.hz = r.len ? decode_horizon(S->h, r.off, r.off + r.len) : 0;
+    adm.push_back(r.id);
+    S->queue.pop_front();
     ++S->active;
   }
-  while (!ids.empty()) {
-    // 3. one merged plan for everything admitted now; shrink if scratch does not fit
-    lz_range_plan* P = nullptr;
-    int rc = lz_range_plan_create(S->h, ids.size(), offs.data(), lens.data(), &P);
-    if (rc) {
-      while (!ids.empty()) S->unadmit(ids, offs, lens);
-      return rc;
-    }
-    uint64_t sat = 0, pat = 0;
-    const bool got_mem = S->mem.alloc(P->scratch_bytes, &sat);
-    bool got_pin = got_mem && S->pin.alloc(P->staging_bytes, &pat);
-    if (got_mem && !got_pin && S->running.empty() && Extents::a256(P->staging_bytes) > S->pin_bytes) {
-      // the pool is too small for this plan and nothing is in flight: grow it
-      // (freeing pinned memory waits for the device, which is idle here)
-      (void)hipHostFree(S->pin_base);
-      S->pin_base = nullptr;
-      const uint64_t nb = std::max(2 * S->pin_bytes, Extents::a256(P->staging_bytes));
-      if (hipHostMalloc((void**)&S->pin_base, nb, 0) != hipSuccess) {
-        S->pin_base = nullptr;
-        S->pin_bytes = 0;
-        S->pin.reset(0);
-      } else {
-        S->pin_bytes = nb;
-        S->pin.reset(nb);
-      }
-      got_pin = S->pin.alloc(P->staging_bytes, &pat);
-    }
-    if (!got_pin) {
-      if (got_mem) S->mem.release(sat, P->scratch_bytes);
-      const uint64_t need = Extents::a256(std::max<uint64_t>(lens.back(), 1)) + Extents::a256(P->scratch_bytes);
-      // a lone request whose output and scratch exceed the whole arena, or
-      // whose staging the pool could not grow to, can never be served
-      const bool never = ids.size() == 1 && S->running.empty() && (need > S->arena_bytes || got_mem);
-      lz_range_plan_free(P);
-      if (never) {
-        // nothing else holds memory: this request can never be served
-        auto& r = S->reqs[ids[0]];
-        S->mem.release(r.out_at, r.len);
-        r.state = 4;  // failed; its slot is held until released
-        return lz::fail(LZ_E_NOMEM, "request %llu needs %llu bytes of arena (or its staging the pinned pool), "
-                        "more than there is", (unsigned long long)ids[0], (unsigned long long)need);
-      }
-      S->unadmit(ids, offs, lens);
+  adm.insert(adm.end(), S->held.begin(), S->held.end());
+  S->held.clear();
+  if (adm.empty()) return 0;
+  std::sort(adm.begin(), adm.end());
+  // 3. one group per decode horizon: ranges whose prefix decodes start at the
+  // same grain share one plan (on a segment-encoded archive, one segment), so
+  // no plan decodes the stretch between far-apart ranges.  A horizon that
+  // already has a group on the device holds its requests until that group is
+  // done, so they merge into one later group instead of decoding the same
+  // prefix beside it.
+  std::vector<std::pair<uint64_t, std::vector<uint64_t>>> parts;  // horizon, ids in arrival order
+  for (uint64_t id : adm) {
+    const uint64_t hz = S->reqs[id].hz;
+    bool busy = false;
+    for (const auto& G : S->running) busy = busy || G.hz == hz;
+    if (busy) {
+      S->held.push_back(id);
       continue;
     }
-    P->staging = S->pin_base + pat;
-    P->staging_owned = false;
-    std::vector<uint64_t> oo;
-    for (uint64_t id : ids) oo.push_back(S->reqs[id].out_at);
-    hipStream_t st = S->streams[S->next_stream];
-    S->next_stream ^= 1;
-    hipEvent_t ev = nullptr;
-    if (!S->ev_free.empty()) {
-      ev = S->ev_free.back();
-      S->ev_free.pop_back();
-    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-      ev = nullptr;
-    }
-    rc = ev ? lz_range_run(S->h, P, S->arena, S->arena_bytes, oo.data(), S->arena + sat, P->scratch_bytes, &S->cfg, st)
-            : lz::fail(LZ_E_HIP, "event creation failed");
-    if (rc == 0 && hipEventRecord(ev, st) != hipSuccess) {
-      // the work is enqueued but cannot be tracked: wait for it here
-      rc = (hipStreamSynchronize(st) == hipSuccess) ? 0 : lz::fail(LZ_E_HIP, "event record and stream sync failed");
-      lz_server::Group G{ev, P, sat, P->scratch_bytes, pat, P->staging_bytes, ids};
+    size_t k = 0;
+    while (k < parts.size() && parts[k].first != hz) ++k;
+    if (k == parts.size()) parts.push_back({hz, {}});
+    parts[k].second.push_back(id);
+  }
+  // 4. launch the groups in order of their oldest request.  A group whose
+  // scratch or staging does not fit first sends every later group back to the
+  // queue, then its own newest requests, one at a time, and tries again; what
+  // still does not fit waits for running groups to finish.
+  auto requeue_from = [&](size_t k) {
+    std::vector<uint64_t> back;
+    for (size_t j = k; j < parts.size(); ++j) back.insert(back.end(), parts[j].second.begin(), parts[j].second.end());
+    parts.resize(k);
+    S->requeue(back);
+  };
+  for (size_t k = 0; k < parts.size(); ++k) {
+    std::vector<uint64_t>& ids = parts[k].second;
+    for (;;) {
+      std::vector<uint64_t> offs, lens;
+      for (uint64_t id : ids) {
+        offs.push_back(S->reqs[id].off);
+        lens.push_back(S->reqs[id].len);
+      }
+      lz_range_plan* P = nullptr;
+      int rc = lz_range_plan_create(S->h, ids.size(), offs.data(), lens.data(), &P);
+      if (rc) {
+        requeue_from(k);
+        S->max_running = std::max<uint64_t>(S->max_running, S->running.size());
+        if (n_admitted) *n_admitted = admitted;
+        return rc;
+      }
+      uint64_t sat = 0, pat = 0;
+      const bool idle = S->running.empty();
+      const bool got_mem = S->mem.alloc(P->scratch_bytes, &sat);
+      bool got_pin = got_mem && S->pin.alloc(P->staging_bytes, &pat);
+      if (got_mem && !got_pin && idle && Extents::a256(P->staging_bytes) > S->pin_bytes) {
+        // the pool is too small for this plan and nothing is in flight: grow it
+        // (freeing pinned memory waits for the device, which is idle here)
+        (void)hipHostFree(S->pin_base);
+        S->pin_base = nullptr;
+        const uint64_t nb = std::max(2 * S->pin_bytes, Extents::a256(P->staging_bytes));
+        if (hipHostMalloc((void**)&S->pin_base, nb, 0) != hipSuccess) {
+          S->pin_base = nullptr;
+          S->pin_bytes = 0;
+          S->pin.reset(0);
+        } else {
+          S->pin_bytes = nb;
+          S->pin.reset(nb);
+        }
+        got_pin = S->pin.alloc(P->staging_bytes, &pat);
+      }
+      if (!got_pin) {
+        if (got_mem) S->mem.release(sat, P->scratch_bytes);
+        const uint64_t need = Extents::a256(std::max<uint64_t>(lens.back(), 1)) + Extents::a256(P->scratch_bytes);
+        lz_range_plan_free(P);
+        if (k + 1 < parts.size()) {
+          requeue_from(k + 1);
+          continue;
+        }
+        if (ids.size() > 1) {
+          S->requeue({ids.back()});
+          ids.pop_back();
+          continue;
+        }
+        // a lone request that meets an idle server and still does not fit (its
+        // output and scratch exceed the whole arena, or its staging the pool
+        // could not grow to) can never be served
+        if (idle && (need > S->arena_bytes || got_mem)) {
+          auto& r = S->reqs[ids[0]];
+          S->mem.release(r.out_at, r.len);
+          r.state = 4;  // failed; its slot is held until released
+          S->completed.push_back(r.id);
+          parts.resize(k);
+          S->max_running = std::max<uint64_t>(S->max_running, S->running.size());
+          if (n_admitted) *n_admitted = admitted;
+          return lz::fail(LZ_E_NOMEM, "request %llu needs %llu bytes of arena (or its staging the pinned pool), "
+                          "more than there is", (unsigned long long)ids[0], (unsigned long long)need);
+        }
+        requeue_from(k);  // waits for a running group to finish
+        break;
+      }
+      P->staging = S->pin_base + pat;
+      P->staging_owned = false;
+      std::vector<uint64_t> oo;
+      for (uint64_t id : ids) oo.push_back(S->reqs[id].out_at);
+      hipStream_t st = S->streams[S->next_stream];
+      S->next_stream = (S->next_stream + 1) % kServeStreams;
+      hipEvent_t ev = nullptr;
+      if (!S->ev_free.empty()) {
+        ev = S->ev_free.back();
+        S->ev_free.pop_back();
+      } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        ev = nullptr;
+      }
+      rc = ev ? lz_range_run(S->h, P, S->arena, S->arena_bytes, oo.data(), S->arena + sat, P->scratch_bytes, &S->cfg, st)
+              : lz::fail(LZ_E_HIP, "event creation failed");
+      if (rc == 0 && hipEventRecord(ev, st) != hipSuccess) {
+        // the work is enqueued but cannot be tracked: wait for it here
+        rc = (hipStreamSynchronize(st) == hipSuccess) ? 0 : lz::fail(LZ_E_HIP, "event record and stream sync failed");
+        lz_server::Group G{ev, parts[k].first, P, sat, P->scratch_bytes, pat, P->staging_bytes, ids};
+        for (uint64_t id : ids) S->reqs[id].state = 1;
+        S->finish_group(G, rc == 0 ? 2 : 4);
+        admitted += ids.size();
+        if (rc) {
+          requeue_from(k + 1);
+          S->max_running = std::max<uint64_t>(S->max_running, S->running.size());
+          if (n_admitted) *n_admitted = admitted;
+          return rc;
+        }
+        break;
+      }
+      if (rc) {
+        // nothing of this group reached the device after a failed launch call;
+        // wait for what did, then give everything back
+        (void)hipStreamSynchronize(st);
+        if (ev) S->ev_free.push_back(ev);
+        S->mem.release(sat, P->scratch_bytes);
+        S->pin.release(pat, P->staging_bytes);
+        lz_range_plan_free(P);
+        requeue_from(k);
+        S->max_running = std::max<uint64_t>(S->max_running, S->running.size());
+        if (n_admitted) *n_admitted = admitted;
+        return rc;
+      }
+      lz_server::Group G{ev, parts[k].first, P, sat, P->scratch_bytes, pat, P->staging_bytes, ids};
       for (uint64_t id : ids) S->reqs[id].state = 1;
-      S->finish_group(G, rc == 0 ? 2 : 4);
-      if (n_admitted) *n_admitted = ids.size();
-      return rc;
+      S->running.push_back(std::move(G));
+      admitted += ids.size();
+      break;
     }
-    if (rc) {
-      // nothing of this group reached the device after a failed launch call;
-      // wait for what did, then give everything back
-      (void)hipStreamSynchronize(st);
-      if (ev) S->ev_free.push_back(ev);
-      S->mem.release(sat, P->scratch_bytes);
-      S->pin.release(pat, P->staging_bytes);
-      lz_range_plan_free(P);
-      while (!ids.empty()) S->unadmit(ids, offs, lens);
-      return rc;
-    }
-    lz_server::Group G{ev, P, sat, P->scratch_bytes, pat, P->staging_bytes, ids};
-    for (uint64_t id : ids) S->reqs[id].state = 1;
-    S->running.push_back(std::move(G));
-    admitted += ids.size();
-    break;
   }
   S->max_running = std::max<uint64_t>(S->max_running, S->running.size());
   if (n_admitted) *n_admitted = admitted;
@@ -2675,10 +2748,20 @@ int lz_serve_release(lz_server* S, uint64_t id) {
   return 0;
 }
 
+uint64_t lz_serve_completed(lz_server* S, uint64_t* ids, uint64_t cap) {
+  if (!S || !ids) return 0;
+  uint64_t k = 0;
+  for (; k < cap && !S->completed.empty(); ++k) {
+    ids[k] = S->completed.front();
+    S->completed.pop_front();
+  }
+  return k;
+}
+
 void lz_serve_stats(const lz_server* S, uint64_t* waiting, uint64_t* running_groups, uint64_t* arena_used,
                     uint64_t* arena_high_water) {
   if (!S) return;
-  if (waiting) *waiting = S->fifo.size() - S->fifo_head;
+  if (waiting) *waiting = S->queue.size() + S->held.size();
   if (running_groups) *running_groups = S->running.size();
   if (arena_used) *arena_used = S->mem.used;
   if (arena_high_water) *arena_high_water = S->mem.high_water;

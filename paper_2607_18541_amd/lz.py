@@ -108,6 +108,7 @@ def lib():
             "lz_serve_tick": (ctypes.c_int, [_vp, _p64, _p64]),
             "lz_serve_status": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_vp)]),
             "lz_serve_release": (ctypes.c_int, [_vp, _u64]),
+            "lz_serve_completed": (_u64, [_vp, _p64, _u64]),
             "lz_serve_stats": (None, [_vp, _p64, _p64, _p64, _p64]),
             "lz_serve_max_running": (_u64, [_vp]),
             "lz_serve_destroy": (ctypes.c_int, [_vp]),
@@ -612,6 +613,12 @@ class Server:
         rc = lib().lz_serve_release(self.s, rid)
         if rc:
             raise LzError(rc, "lz_serve_release")
+
+    def completed(self, cap=4096):
+        """Ids that finished (done or failed) since the last call."""
+        buf = np.zeros(cap, dtype=np.uint64)
+        k = int(lib().lz_serve_completed(self.s, buf.ctypes.data_as(_p64), cap))
+        return buf[:k].tolist()
 
     def stats(self):
         w, r, u, hw = _u64(), _u64(), _u64(), _u64()

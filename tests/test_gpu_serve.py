@@ -5,8 +5,10 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 import synth
 from paper_2607_18541_amd import lz
+from test_gpu_range import horizon_by_definition
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -142,5 +144,53 @@ def test_serve_never_fitting_request_fails_cleanly():
             break
     assert bytes(srv.result(rid, 1000).cpu().numpy()) == bytes(x[100:1100])
     srv.release(rid)
+    assert srv.stats()["arena_used"] == 0
+    srv.destroy()
+
+
+@pytest.mark.parametrize("arena_mib", [256, 24])
+def test_serve_splits_tick_by_horizon(arena_mib):
+    """Requests admitted in one tick are split by decode horizon: on an
+    archive encoded in 8 MiB segments, requests in different segments become
+    different groups launched in the same tick (several groups in flight right
+    after it when the arena holds them).  With an arena too small for all of
+    them the groups that do not fit go back to the queue and run later.  Every
+    result equals the range decoded alone and the input bytes."""
+    dev = _dev()
+    seg = 8 << 20
+    x = synth.fastq(64 << 20, seed=12)
+    da = lz.DeviceArchive(lz.encode(x, 16, lz.TUNED_THR, segment=seg), device=dev)
+    n = da.n
+    k = 24
+    lens = synth.loguniform(k, 64 << 10, 1 << 20, 23).astype(np.int64)
+    offs = (synth.uniform(k, 24) * (n - lens)).astype(np.int64)
+    tk = oracle.tokens(da.arc)
+    horizons = {horizon_by_definition(tk, int(o), int(o + L)) for o, L in zip(offs, lens)}
+    assert len(horizons) >= 4
+    srv = lz.Server(da, arena_mib << 20, slots=64)
+    rids = [srv.submit(int(offs[i]), int(lens[i])) for i in range(k)]
+    srv.tick()
+    first = srv.stats()["running_groups"]
+    finished = list(srv.completed())
+    t_end = time.time() + 60
+    while time.time() < t_end and len(finished) < k:
+        srv.tick()
+        finished += srv.completed()
+    # the completion queue names every request once
+    assert sorted(finished) == sorted(rids)
+    st = srv.stats()
+    print("groups after the first tick %d, horizons %d, max in flight %d, arena high water %d" %
+          (first, len(horizons), st["max_running_groups"], st["arena_high_water"]), flush=True)
+    if arena_mib == 256:
+        assert first == len(horizons)
+    else:
+        assert 1 <= first < len(horizons)
+    assert st["arena_high_water"] <= arena_mib << 20
+    for i, r in enumerate(rids):
+        assert srv.status(r)[0] == 2, i
+        got = srv.result(r, int(lens[i])).clone()
+        assert bytes(got.cpu().numpy()) == bytes(x[int(offs[i]):int(offs[i]) + int(lens[i])]), i
+        assert torch.equal(got, da.decode_range(int(offs[i]), int(lens[i]))), i
+        srv.release(r)
     assert srv.stats()["arena_used"] == 0
     srv.destroy()
