@@ -164,12 +164,18 @@ typedef struct lz_dev lz_dev; /* opaque handle of a device-resident archive */
  * schedule 1 = one launch per depth, except that the deepest depths that each
  * have at most `tail` windows run in a single one-workgroup launch with a
  * barrier between depths (0 = 32 windows; 0xFFFFFFFF = no such launch).
- * NULL config = G 64, unroll 2, schedule 1, tail 0. */
+ * mapping = which workgroup takes which work item: 0 = in launch order (the
+ * hardware deals consecutive workgroups to the 8 XCDs in turn, so neighbouring
+ * segments and windows run on different XCDs), 1 = XCD-contiguous (the
+ * workgroups one XCD receives take one contiguous run of items, so
+ * neighbouring writes meet in that XCD's L2).
+ * NULL config = G 64, unroll 2, schedule 1, tail 0, mapping 0. */
 typedef struct lz_decode_cfg {
   uint32_t G;
   uint32_t unroll;
   uint32_t schedule;
   uint32_t tail;
+  uint32_t mapping;
 } lz_decode_cfg;
 
 /* Device bytes lz_device_open needs for this archive: the archive itself, the
@@ -338,15 +344,16 @@ uint64_t lz_batch_launches(const lz_batch* batch); /* kernel launches per replay
 void lz_batch_destroy(lz_batch* batch);
 
 /* Autotuner: archives are bucketed by size (x4 buckets from 16 KiB); for each
- * bucket every (G in {16,32,64}) x (unroll in {1,2,4}) x (schedule 1, 0) is
- * timed with HIP events as a batch of that bucket alone (one warm-up, `reps`
- * replays) and the fastest is written to chosen[i] for the bucket's archives.
+ * bucket every (G in {16,32,64}) x (unroll in {1,2,4}) x (schedule 1, 0) x
+ * (mapping 0, 1) is timed with HIP events as a batch of that bucket alone
+ * (one warm-up, `reps` replays) and the fastest is written to chosen[i] for
+ * the bucket's archives.
  * report (optional) receives one entry per non-empty bucket. */
 typedef struct lz_tune_report {
   uint64_t min_bytes, max_bytes, bytes;
   uint32_t archives;
   lz_decode_cfg best;
-  float best_ms, default_ms; /* default: G 64, unroll 2, schedule 1 */
+  float best_ms, default_ms; /* default: G 64, unroll 2, schedule 1, mapping 0 */
 } lz_tune_report;
 int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* const* d_out, const uint64_t* out_cap,
                 void* d_scratch, uint64_t scratch_cap, void* stream, uint32_t reps, lz_decode_cfg* chosen,

@@ -137,6 +137,7 @@ struct KArgs {
   const uint32_t* p_mlen;
   const uint64_t* p_unit;  // token ranges of the work items; null = windows of G tokens over [lo, hi)
   uint64_t nunits;
+  uint32_t xcd_map;  // 1: the workgroups of one XCD take one contiguous run of work items
 };
 
 struct Desc {
@@ -467,7 +468,15 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
   const int gw = lane / G;             // group in wave
   const int gslot = threadIdx.x - gl;  // first LDS slot of this group
   const uint64_t ngroups = (uint64_t)gridDim.x * (WG / G);
-  const uint64_t gid = uni<G>((uint64_t)blockIdx.x * (WG / G) + threadIdx.x / G);
+  // Workgroup b runs on XCD b mod 8.  XCD-contiguous mapping: XCD x takes
+  // the x-th of 8 contiguous runs of logical workgroups (sizes differing by
+  // at most one), in the order it receives them.
+  uint64_t wg = blockIdx.x;
+  if (A.xcd_map) {
+    const uint64_t nb = gridDim.x, x = wg & 7u, q = nb >> 3, r = nb & 7u;
+    wg = x * q + min(x, r) + (wg >> 3);
+  }
+  const uint64_t gid = uni<G>(wg * (WG / G) + threadIdx.x / G);
   ArcDesc D = A.one;
   uint64_t bs = 1ull << D.log2_bs;
   uintptr_t out_b = (uintptr_t)D.out;
@@ -929,10 +938,10 @@ struct lz_dev {
   struct GraphKey {
     uint8_t* out;
     uint64_t cap;
-    uint32_t G, U, sched, tail, stage;
+    uint32_t G, U, sched, tail, stage, map;
     bool operator==(const GraphKey& o) const {
       return out == o.out && cap == o.cap && G == o.G && U == o.U && sched == o.sched && tail == o.tail &&
-             stage == o.stage;
+             stage == o.stage && map == o.map;
     }
   };
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
@@ -1202,11 +1211,14 @@ uint64_t tail_start(const std::vector<uint64_t>& windows, uint32_t limit) {
   return (windows.size() - p >= 2) ? p : windows.size();
 }
 
-int resolve_cfg(const lz_decode_cfg* cfg, uint32_t& G, uint32_t& U, uint32_t& sched, uint32_t* tail = nullptr) {
+int resolve_cfg(const lz_decode_cfg* cfg, uint32_t& G, uint32_t& U, uint32_t& sched, uint32_t* tail = nullptr,
+                uint32_t* map = nullptr) {
   G = cfg ? cfg->G : 64;
   U = cfg ? cfg->unroll : 2;
   sched = cfg ? cfg->schedule : 1;
   if (tail) *tail = (cfg && cfg->tail) ? cfg->tail : kTailWindows;
+  if (map) *map = cfg ? cfg->mapping : 0;
+  if (cfg && cfg->mapping > 1) return lz::fail(LZ_E_INVAL, "mapping must be 0 or 1");
   if (!(G == 8 || G == 16 || G == 32 || G == 64)) return lz::fail(LZ_E_INVAL, "G must be 8, 16, 32 or 64");
   if (!(U == 1 || U == 2 || U == 4)) return lz::fail(LZ_E_INVAL, "unroll must be 1, 2 or 4");
   if (sched > 1) return lz::fail(LZ_E_INVAL, "schedule must be 0 or 1");
@@ -1437,14 +1449,14 @@ int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cf
   if (out_cap < h->v.n) return lz::fail(LZ_E_INVAL, "output capacity %llu < n %llu", (unsigned long long)out_cap,
                                         (unsigned long long)h->v.n);
   if (h->v.n && !d_out) return lz::fail(LZ_E_INVAL, "null output");
-  uint32_t G, U, sched, tail;
-  int rc = resolve_cfg(cfg, G, U, sched, &tail);
+  uint32_t G, U, sched, tail, map;
+  int rc = resolve_cfg(cfg, G, U, sched, &tail, &map);
   if (rc) return rc;
   if (sched == 0 && out_cap > 0xFFFFFFFFull)
     return lz::fail(LZ_E_INVAL, "schedule 0 addresses outputs below 4 GiB; use schedule 1");
   if (h->v.nb == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
-  lz_dev::GraphKey key{d_out, out_cap, G, U, sched, tail, (uint32_t)stage};
+  lz_dev::GraphKey key{d_out, out_cap, G, U, sched, tail, (uint32_t)stage, map};
   for (auto& g : h->graphs)
     if (g.first == key) {
       HIPCHK(hipGraphLaunch(g.second, s));
@@ -1453,6 +1465,7 @@ int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cf
   // build the launch sequence once: parse, then the match windows level by level
   KArgs A = base_args(h);
   A.one = arc_desc(h, d_out, out_cap);
+  A.xcd_map = map;
   struct Launch {
     kfn_t k;
     uint64_t grid;
@@ -1556,12 +1569,13 @@ int lz_purecopy_device(uint64_t ntok, const uint64_t* d_dst, const uint64_t* d_l
                        uint8_t* d_out, uint64_t out_size, const lz_decode_cfg* cfg, void* stream) {
   if (ntok && (!d_dst || !d_lit_off || !d_lit_len || !d_src || !d_mlen || !d_unit_start || !d_out))
     return lz::fail(LZ_E_INVAL, "null argument");
-  uint32_t G, U, sched;
-  int rc = resolve_cfg(cfg, G, U, sched);
+  uint32_t G, U, sched, tail, map;
+  int rc = resolve_cfg(cfg, G, U, sched, &tail, &map);
   if (rc) return rc;
   if (nunits == 0) return 0;
   KArgs A;
   memset(&A, 0, sizeof(A));
+  A.xcd_map = map;
   A.one.lit = d_lit;
   A.one.lit_lo = (uintptr_t)d_lit;
   A.one.lit_hi = (uintptr_t)d_lit + lit_size;
@@ -1877,8 +1891,8 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
   for (uint64_t r = 0; r < P->count; ++r)
     if (out_off[r] > out_cap || P->range_len[r] > out_cap - out_off[r])
       return lz::fail(LZ_E_INVAL, "range %llu does not fit the output arena", (unsigned long long)r);
-  uint32_t G, U, sched;
-  int rc = resolve_cfg(cfg, G, U, sched);
+  uint32_t G, U, sched, tail, map;
+  int rc = resolve_cfg(cfg, G, U, sched, &tail, &map);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   const uint64_t np = P->p_dst.size();
@@ -1908,6 +1922,7 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
   uint8_t* data = D + P->staging_bytes;
   KArgs A;
   memset(&A, 0, sizeof(A));
+  A.xcd_map = map;
   A.p_dst = (const uint64_t*)(D + o_dst);
   A.p_lit_off = (const uint64_t*)(D + o_loff);
   A.p_src = (const uint64_t*)(D + o_src);
@@ -1918,6 +1933,7 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
     // output base is placed `horizon` bytes before it, so absolute positions
     // index it directly, and no match may touch a position below the horizon
     KArgs A = base_args(h);
+    A.xcd_map = map;
     A.one = arc_desc(h, data - P->horizon, P->data_end);
     A.one.msrc_lo = (uintptr_t)data;
     A.one.msrc_hi = (uintptr_t)data + P->data_bytes;
@@ -2073,7 +2089,7 @@ std::vector<BatchGroup> make_groups(uint32_t count, const lz_decode_cfg* cfgs) {
     size_t k = 0;
     for (; k < groups.size(); ++k)
       if (groups[k].cfg.G == c.G && groups[k].cfg.unroll == c.unroll && groups[k].cfg.schedule == c.schedule &&
-          groups[k].cfg.tail == c.tail)
+          groups[k].cfg.tail == c.tail && groups[k].cfg.mapping == c.mapping)
         break;
     if (k == groups.size()) groups.push_back(BatchGroup{c, {}});
     groups[k].arcs.push_back(i);
@@ -2137,8 +2153,8 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
   int cu = 0;
   for (lz_dev* h : H) cu = std::max(cu, h->cu_count);
   for (auto& g : groups) {
-    uint32_t G, U, sched, tail;
-    (void)resolve_cfg(&g.cfg, G, U, sched, &tail);
+    uint32_t G, U, sched, tail, map;
+    (void)resolve_cfg(&g.cfg, G, U, sched, &tail, &map);
     uint64_t nseg, nw, nl;
     group_scratch(H, g, &nseg, &nw, &nl);
     const uint64_t o_desc = off;
@@ -2182,6 +2198,7 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
     lvls[nl] = (uint32_t)wi;
     KArgs A;
     memset(&A, 0, sizeof(A));
+    A.xcd_map = map;
     A.arcs = (const ArcDesc*)(D0 + o_desc);
     A.one = desc[0];
     A.seg = (const uint64_t*)(D0 + o_seg);
@@ -2298,7 +2315,7 @@ extern "C" int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* cons
   };
   std::vector<std::vector<uint32_t>> buckets(16);
   for (uint32_t i = 0; i < count; ++i) buckets[bucket_of(handles[i]->v.n)].push_back(i);
-  static const uint32_t Gs[3] = {16, 32, 64}, Us[3] = {1, 2, 4}, Ss[2] = {1, 0};
+  static const uint32_t Gs[3] = {16, 32, 64}, Us[3] = {1, 2, 4}, Ss[2] = {1, 0}, Ms[2] = {0, 1};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -2319,10 +2336,11 @@ extern "C" int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* cons
     }
     lz_decode_cfg best{64, 2, 1, 0};
     float best_ms = 1e30f, default_ms = -1.f;
+    for (uint32_t M : Ms)
     for (uint32_t S : Ss)
       for (uint32_t G : Gs)
         for (uint32_t U : Us) {
-          lz_decode_cfg c{G, U, S, 0};
+          lz_decode_cfg c{G, U, S, 0, M};
           bool too_big = false;
           if (S == 0)
             for (uint64_t cap : C) too_big = too_big || cap > 0xFFFFFFFFull;
@@ -2342,7 +2360,7 @@ extern "C" int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* cons
           lz_batch_destroy(B);
           if (rc) break;
           ms /= (float)reps;
-          if (G == 64 && U == 2 && S == 1) default_ms = ms;
+          if (G == 64 && U == 2 && S == 1 && M == 0) default_ms = ms;
           if (ms < best_ms) {
             best_ms = ms;
             best = c;

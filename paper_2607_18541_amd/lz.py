@@ -51,7 +51,7 @@ class Info(ctypes.Structure):
 
 
 class DecodeCfg(ctypes.Structure):
-    _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("tail", _u32)]
+    _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("tail", _u32), ("mapping", _u32)]
 
 
 class TuneReport(ctypes.Structure):
@@ -286,9 +286,9 @@ def fnv1a64(data, seed=0xcbf29ce484222325):
 TAIL_OFF = 0xFFFFFFFF
 
 
-def _cfg(G=64, unroll=2, schedule=1, tail=0):
+def _cfg(G=64, unroll=2, schedule=1, tail=0, mapping=0):
     c = DecodeCfg()
-    c.G, c.unroll, c.schedule, c.tail = G, unroll, schedule, tail
+    c.G, c.unroll, c.schedule, c.tail, c.mapping = G, unroll, schedule, tail, mapping
     return c
 
 
@@ -324,11 +324,11 @@ class DeviceArchive:
         self.levels = int(lib().lz_device_levels(h))
         self.device_bytes = nb.value
 
-    def decode(self, out=None, G=64, unroll=2, schedule=1, stream=None, check=True, tail=0):
+    def decode(self, out=None, G=64, unroll=2, schedule=1, stream=None, check=True, tail=0, mapping=0):
         import torch
         if out is None:
             out = torch.empty(max(self.n, 1), dtype=torch.uint8, device=self.buf.device)
-        c = _cfg(G, unroll, schedule, tail)
+        c = _cfg(G, unroll, schedule, tail, mapping)
         rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                     _stream(stream))
         if rc:
@@ -337,16 +337,16 @@ class DeviceArchive:
             self.check(stream)
         return out[:self.n]
 
-    def decode_async(self, out, G=64, unroll=2, schedule=1, stream=None, tail=0):
-        c = _cfg(G, unroll, schedule, tail)
+    def decode_async(self, out, G=64, unroll=2, schedule=1, stream=None, tail=0, mapping=0):
+        c = _cfg(G, unroll, schedule, tail, mapping)
         rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                     _stream(stream))
         if rc:
             raise LzError(rc, "lz_decode_device")
 
-    def decode_stage(self, out, stage, G=64, unroll=2, schedule=1, stream=None, tail=0):
+    def decode_stage(self, out, stage, G=64, unroll=2, schedule=1, stream=None, tail=0, mapping=0):
         """Stage 1 = parse launch, 2 = match passes (after stage 1), 0 = both."""
-        c = _cfg(G, unroll, schedule, tail)
+        c = _cfg(G, unroll, schedule, tail, mapping)
         rc = lib().lz_decode_device_stage(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                           int(stage), _stream(stream))
         if rc:
@@ -490,15 +490,14 @@ def _cfg_array(cfgs):
         if isinstance(c, DecodeCfg):
             arr[i] = c
         else:
-            G, U, S = c
-            arr[i] = _cfg(G, U, S)
+            arr[i] = _cfg(*c)
     return arr
 
 
 class Batch:
     """One replayable launch sequence decoding many DeviceArchives; archive i
     into outs[i] (torch tensors).  cfgs: None, or per archive a DecodeCfg or a
-    (G, unroll, schedule) tuple."""
+    (G, unroll, schedule[, tail[, mapping]]) tuple."""
 
     def __init__(self, archives, outs, cfgs=None, stream=None):
         import torch
@@ -558,9 +557,10 @@ def autotune(archives, outs, reps=3, stream=None):
                            _stream(stream), reps, chosen, rep, 16, ctypes.byref(nrep))
     if rc:
         raise LzError(rc, "lz_autotune")
-    cfgs = [(chosen[i].G, chosen[i].unroll, chosen[i].schedule) for i in range(n)]
+    cfgs = [(chosen[i].G, chosen[i].unroll, chosen[i].schedule, chosen[i].tail, chosen[i].mapping) for i in range(n)]
     report = [{"min_bytes": rep[i].min_bytes, "max_bytes": rep[i].max_bytes, "archives": rep[i].archives,
-               "bytes": rep[i].bytes, "best": (rep[i].best.G, rep[i].best.unroll, rep[i].best.schedule),
+               "bytes": rep[i].bytes,
+               "best": (rep[i].best.G, rep[i].best.unroll, rep[i].best.schedule, rep[i].best.mapping),
                "best_ms": rep[i].best_ms, "default_ms": rep[i].default_ms} for i in range(nrep.value)]
     return cfgs, report
 

@@ -24,23 +24,26 @@ def _check(arc, expect, cfgs, label):
     da = lz.DeviceArchive(arc, device=dev)
     exp_t = torch.from_numpy(np.ascontiguousarray(expect)).to(dev)
     h = oracle.fnv1a64(expect)
-    for (G, U, S) in cfgs:
-        print(f"[{label}] G={G} U={U} sched={S} n={da.n}", flush=True)
+    for c in cfgs:
+        G, U, S = c[:3]
+        M = c[3] if len(c) > 3 else 0
+        print(f"[{label}] G={G} U={U} sched={S} mapping={M} n={da.n}", flush=True)
         out = torch.full((max(da.n, 1) + 64,), 0xA5, dtype=torch.uint8, device=dev)
-        got = da.decode(out, G=G, unroll=U, schedule=S)
+        got = da.decode(out, G=G, unroll=U, schedule=S, mapping=M)
         torch.cuda.synchronize()
         if not torch.equal(got, exp_t):
             bad = (got != exp_t).nonzero()
             i = int(bad[0].item())
-            raise AssertionError(f"{label} G={G} U={U} S={S}: {bad.numel()} bytes differ, first at {i}")
+            raise AssertionError(f"{label} G={G} U={U} S={S} M={M}: {bad.numel()} bytes differ, first at {i}")
         assert lz.fnv1a64(got.cpu().numpy()) == h
         # nothing written past n
         assert bool((out[da.n:] == 0xA5).all().item())
     da.close()
 
 
-ALL = [(G, U, S) for G in GS for U in (1, 2, 4) for S in (0, 1)]
-SOME = [(8, 2, 0), (32, 1, 0), (64, 4, 0), (16, 2, 1), (32, 4, 1)]
+# (G, unroll, schedule[, mapping]); mapping 1 = XCD-contiguous workgroups
+ALL = [(G, U, S) for G in GS for U in (1, 2, 4) for S in (0, 1)] + [(64, 2, 1, 1), (32, 4, 0, 1), (8, 1, 1, 1)]
+SOME = [(8, 2, 0), (32, 1, 0), (64, 4, 0), (16, 2, 1), (32, 4, 1), (64, 2, 1, 1), (16, 2, 0, 1)]
 
 
 def test_zipf_1mib_all_configs():
