@@ -218,9 +218,10 @@ void lz_device_close(lz_dev* h);
 
 /* Tile-rANS entropy stage (Sec. 2, Experimental Setup: entropy decoded over
  * 64 KB tiles, cut independently of the LZ blocks, before the match phase).
- * lz_entropy_encode codes a container (host): every byte region of it -- the
- * header and block table, each stream, and each of the four byte planes of
- * the 32-bit sources (stride 4) -- in tiles of at most 65,536 symbols, each
+ * lz_entropy_encode codes a container (host): its bytes before the 32-bit
+ * sources (header, block table, cmd, x16, x32), each of the four byte planes
+ * of the sources (stride 4), and its bytes after them (high source plane,
+ * literals), each cut into tiles of at most 65,536 symbols, each
  * stored raw, as one repeated byte, or order-0 rANS coded, whichever is
  * smallest.  rANS: probabilities quantised to 1/4096 (f = floor(count * 4096 /
  * N), present symbols at least 1, the sum corrected on the most frequent
@@ -282,7 +283,10 @@ void lz_range_plan_free(lz_range_plan* plan);
 
 /* Runs a plan on `stream`: range i is written to d_out[out_off[i], +len[i]),
  * which must lie inside [d_out, d_out+out_cap); d_scratch holds at least
- * lz_range_plan_scratch_bytes.  All ranges of the plan share each launch. */
+ * lz_range_plan_scratch_bytes.  All ranges of the plan share each launch.
+ * cfg (NULL = defaults): G, unroll and mapping as for a decode; a prefix
+ * decode launches its depths one by one and runs the deepest that have at
+ * most `tail` windows in one workgroup, as schedule 1 does. */
 int lz_range_run(lz_dev* h, lz_range_plan* plan, uint8_t* d_out, uint64_t out_cap, const uint64_t* out_off,
                  void* d_scratch, uint64_t scratch_cap, const lz_decode_cfg* cfg, void* stream);
 

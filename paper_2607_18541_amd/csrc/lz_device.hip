@@ -19,11 +19,13 @@
 //         has one more than the deepest token that wrote any of its source
 //         bytes (its own bytes excluded), so matches of one depth never read
 //         each other's output.  Slots are ordered by (depth, token) and cut
-//         into windows of at most 64 matches and 3 KiB (a longer match is
-//         split over windows).  Schedule 1 launches each depth's windows
-//         separately (kernel boundaries order the depths) with ordinary cached
-//         accesses, and runs the deepest, smallest depths in one workgroup
-//         with a barrier between them.  Schedule 0 runs every depth in one
+//         into windows of at most 64 matches and 3 KiB inside one output
+//         grain of max(2^20, block) bytes (a longer match is split over
+//         windows), so a range decode that starts at a grain boundary (its
+//         decode horizon) runs whole windows.  Schedule 1 launches each
+//         depth's windows separately (kernel boundaries order the depths)
+//         with ordinary cached accesses, and runs the deepest, smallest
+//         depths in one workgroup with a barrier between them.  Schedule 0 runs every depth in one
 //         launch: groups take windows depth by depth from per-depth tickets,
 //         wait until the depth below has counted all its windows done, and
 //         read and write output bytes with agent-scope (sc1) accesses.
@@ -40,6 +42,10 @@
 //
 // Mode 2 executes pre-decoded tokens whose match sources are in a separate
 // buffer (the pure-copy control of Sec. 3.3).
+//
+// Work items are taken in workgroup order, or (mapping 1) so that the
+// workgroups one XCD receives -- the hardware deals them to the 8 XCDs in
+// turn -- take one contiguous run of items.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -85,7 +91,8 @@ constexpr uint32_t kWinMatches = 64;  // ... and at most this many matches
 constexpr uint32_t kLog2Grain = 20;  // and its matches lie in one aligned grain of max(2^20, block) bytes
 constexpr uint64_t kClosureMin = 1ull << 20;  // range closures of up to max(1 MiB, prefix / 4096) bytes;
 constexpr uint64_t kClosureRatio = 4096;      // beyond that the prefix is decoded instead
-constexpr uint64_t kGatherPiece = 64ull << 10;  // ranges are gathered into the output in pieces of this size
+constexpr uint64_t kGatherPiece = 8ull << 10;  // ranges are gathered into the output in pieces of this size,
+                                               // one piece per group
 
 constexpr uint64_t kIdleTicks = 500000000ull;  // 5 s of the 100 MHz clock without progress
 constexpr int kWG = 256;
@@ -137,6 +144,7 @@ struct KArgs {
   const uint32_t* p_mlen;
   const uint64_t* p_unit;  // token ranges of the work items; null = windows of G tokens over [lo, hi)
   uint64_t nunits;
+  uint32_t per_item;  // mode 2 without p_unit: tokens per work item (0 = G)
   uint32_t xcd_map;  // 1: the workgroups of one XCD take one contiguous run of work items
 };
 
@@ -590,7 +598,8 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
       } else if (MODE == kModePure) {
         const uint64_t k = gid + iter * ngroups;
         ++iter;
-        const uint64_t cnt = A.p_unit ? A.nunits : (A.hi - A.lo + G - 1) / G;
+        const uint64_t per = A.per_item ? A.per_item : G;
+        const uint64_t cnt = A.p_unit ? A.nunits : (A.hi - A.lo + per - 1) / per;
         if (k >= cnt) {
           finished = true;
         } else {
@@ -598,8 +607,8 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
             t_next = A.p_unit[k];
             t_end = A.p_unit[k + 1];
           } else {
-            t_next = A.lo + k * G;
-            t_end = min(t_next + G, A.hi);
+            t_next = A.lo + k * per;
+            t_end = min(t_next + per, A.hi);
           }
           have_item = true;
         }
@@ -1952,7 +1961,7 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
     const uint64_t NL = P->win_hi.size();
     std::vector<uint64_t> cnt(NL);
     for (uint64_t p = 0; p < NL; ++p) cnt[p] = P->win_hi[p] - P->win_lo[p];
-    const uint64_t pt = tail_start(cnt, kTailWindows);
+    const uint64_t pt = (tail == kTailOff) ? NL : tail_start(cnt, tail);
     for (uint64_t p = 0; p < pt; ++p) {
       KArgs a = A;
       a.lo = P->win_lo[p];
@@ -1981,6 +1990,7 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
     a.lo = p0;  // windows of G pieces (pieces of one depth are independent)
     a.hi = p1;
     const bool gather = (l + 1 == L);
+    if (gather) a.per_item = 1;  // a group per gather piece: the copy is spread over the GPU
     if (l == 0) {  // literal pieces: archive literals -> scratch data
       a.one.lit = h->d_arc + h->v.off_lit;
       a.one.lit_lo = (uintptr_t)h->d_arc;
@@ -1997,7 +2007,8 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
     a.one.msrc = data;
     a.one.msrc_lo = (uintptr_t)data;
     a.one.msrc_hi = (uintptr_t)data + P->data_bytes + 16;
-    hipLaunchKernelGGL(k, dim3((unsigned)grid_for((p1 - p0 + G - 1) / G, res, G)), dim3(kWG), 0, s, a);
+    const uint64_t items = gather ? (p1 - p0) : (p1 - p0 + G - 1) / G;
+    hipLaunchKernelGGL(k, dim3((unsigned)grid_for(items, res, G)), dim3(kWG), 0, s, a);
     HIPCHK(hipGetLastError());
   }
   return 0;

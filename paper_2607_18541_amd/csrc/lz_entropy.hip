@@ -191,19 +191,23 @@ __global__ __launch_bounds__(64 * kWaves) void k_entropy(const uint8_t* coded, u
     __builtin_amdgcn_wave_barrier();
     uint32_t wpos = 0, chunk = 0;
     // one step: state `lane` decodes symbol 64 k + lane (when below cnt);
-    // the states that fell below 2^16 take the next words in lane order
+    // the states that fell below 2^16 take the next words in lane order.
+    // Branch-free: every lane reads the table and a ring word (in bounds),
+    // selects keep what an inactive lane or a lane without renormalisation
+    // must not change.
     auto step = [&](bool act) -> uint32_t {
       const uint32_t slot = x & (lz::kRansM - 1);
       const uint32_t sv = L.sym[slot];
       const uint32_t fcv = L.fc[sv];
-      const uint32_t nx = (fcv & 0xFFFFu) * (x >> 12) + slot - (fcv >> 16);
-      if (act) x = nx;
-      const bool need = act && x < lz::kRansL;
+      uint32_t nx = (fcv & 0xFFFFu) * (x >> 12) + slot - (fcv >> 16);
+      nx = act ? nx : x;
+      const bool need = act && nx < lz::kRansL;
       const uint64_t m = __ballot(need);
       const uint32_t pos = wpos + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      const uint32_t w = L.ring[pos & (kRing - 1)];
-      x = need ? ((x << 16) | w) : x;
+      uint32_t w = L.ring[pos & (kRing - 1)];
+      asm volatile("" : "+v"(w));  // keeps the read unconditional (no branch around it)
+      x = need ? ((nx << 16) | w) : nx;
       wpos += (uint32_t)__builtin_popcountll(m);
       return sv;
     };
@@ -236,12 +240,16 @@ __global__ __launch_bounds__(64 * kWaves) void k_entropy(const uint8_t* coded, u
         flush((k0 - kBlock) * 64);
         __builtin_amdgcn_wave_barrier();  // outb is rewritten below
       }
+      if (k0 + kBlock < steps) {  // a whole block of full steps (not the last step)
 #pragma unroll
-      for (int u = 0; u < (int)kBlock; ++u) {
-        if (k0 + u >= steps) break;
-        const uint32_t i = (k0 + u) * 64 + lane;
-        const uint32_t sv = step(i < cnt);
-        L.outb[u * 64 + lane] = (uint8_t)sv;
+        for (int u = 0; u < (int)kBlock; ++u) L.outb[u * 64 + lane] = (uint8_t)step(true);
+      } else {
+#pragma unroll
+        for (int u = 0; u < (int)kBlock; ++u) {
+          if (k0 + u >= steps) break;
+          const uint32_t i = (k0 + u) * 64 + lane;
+          L.outb[u * 64 + lane] = (uint8_t)step(i < cnt);
+        }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();

@@ -455,10 +455,10 @@ class RangePlan:
         self.prefix_bytes = int(lib().lz_range_plan_prefix_bytes(p))
         self.horizon = int(lib().lz_range_plan_horizon(p))
 
-    def run(self, out, out_offs, scratch, G=64, unroll=2, stream=None):
+    def run(self, out, out_offs, scratch, G=64, unroll=2, stream=None, tail=0):
         """Enqueues the plan; range i lands at out[out_offs[i]:+lens[i]]."""
         oo = np.ascontiguousarray(out_offs, dtype=np.uint64)
-        c = _cfg(G, unroll, 0)
+        c = _cfg(G, unroll, 0, tail)
         rc = lib().lz_range_run(self.da.h, self.p, ctypes.c_void_p(out.data_ptr()), out.numel(), oo.ctypes.data,
                                 ctypes.c_void_p(scratch.data_ptr()), scratch.numel(), ctypes.byref(c),
                                 _stream(stream))
