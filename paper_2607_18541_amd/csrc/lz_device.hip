@@ -963,8 +963,16 @@ struct lz_dev {
   std::vector<std::vector<RTok>> tok_cache;
   std::vector<uint8_t> tok_cached;
   std::mutex mu;
+  // pinned staging lent to the synchronous range calls (lz_decode_range,
+  // lz_seek_record) and kept across them, so a seek neither allocates nor
+  // frees pinned memory (freeing it waits for the whole device); sync_mu
+  // serialises those calls
+  uint8_t* sync_pin = nullptr;
+  uint64_t sync_pin_bytes = 0;
+  std::mutex sync_mu;
   ~lz_dev() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    if (sync_pin) (void)hipHostFree(sync_pin);
   }
 };
 
@@ -1647,6 +1655,30 @@ struct lz_range_plan {
   }
 };
 
+namespace lz {
+
+uint8_t* lend_sync_staging(lz_dev* h, lz_range_plan* P, uint64_t extra, std::unique_lock<std::mutex>& lock) {
+  lock = std::unique_lock<std::mutex>(h->sync_mu);
+  const uint64_t at = (P->staging_bytes + 255) & ~uint64_t(255);
+  const uint64_t need = at + extra;
+  if (need > h->sync_pin_bytes) {
+    if (h->sync_pin) (void)hipHostFree(h->sync_pin);
+    h->sync_pin = nullptr;
+    h->sync_pin_bytes = 0;
+    const uint64_t nb = std::max<uint64_t>(need, 1ull << 20);
+    if (hipHostMalloc((void**)&h->sync_pin, nb, 0) != hipSuccess) {
+      h->sync_pin = nullptr;
+      return nullptr;  // the plan allocates its own staging
+    }
+    h->sync_pin_bytes = nb;
+  }
+  P->staging = h->sync_pin;
+  P->staging_owned = false;
+  return h->sync_pin + at;
+}
+
+}  // namespace lz
+
 namespace {
 
 const std::vector<lz_dev::RTok>& block_tokens(lz_dev* h, uint64_t b) {
@@ -2030,8 +2062,11 @@ int lz_decode_range(lz_dev* h, uint64_t off, uint64_t len, uint8_t* d_out, void*
   int rc = lz_range_plan_create(h, 1, &off, &len, &P);
   if (rc) return rc;
   const uint64_t zero = 0;
+  std::unique_lock<std::mutex> lock;
+  (void)lz::lend_sync_staging(h, P, 0, lock);
   rc = lz_range_run(h, P, d_out, len, &zero, d_scratch, scratch_cap, nullptr, stream);
   // the plan's pinned staging is read by the copy engine: wait before freeing
+  // or lending it again
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && rc == 0) rc = lz::fail(LZ_E_HIP, "stream sync failed");
   delete P;
   return rc;

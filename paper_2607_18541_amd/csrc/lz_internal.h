@@ -4,6 +4,7 @@
 
 #include <array>
 #include <atomic>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -82,6 +83,13 @@ int parse_coded(const uint8_t* a, uint64_t size, CodedView* v);
 // payload, bit 1: a tile did not end in the encoder's initial states.
 int entropy_launch(const uint8_t* d_coded, uint64_t payload_off, uint64_t n_tiles, uint8_t* d_out, uint32_t* d_err,
                    int cu_count, void* stream);
+
+// Pinned staging that a handle keeps for its synchronous range calls: lends
+// the plan its staging (P->staging, not owned by the plan) followed, at a
+// 256-byte boundary, by `extra` bytes, whose address it returns.  `lock`
+// holds the handle's lock for these calls until the caller has synchronised
+// its stream.  nullptr (and no loan) if the pinned allocation fails.
+uint8_t* lend_sync_staging(lz_dev* h, lz_range_plan* P, uint64_t extra, std::unique_lock<std::mutex>& lock);
 
 // Learned threshold selector (host object behind lz_selector).
 constexpr uint32_t kSelIn = 64, kSelHidden = 128, kSelTuples = 16;

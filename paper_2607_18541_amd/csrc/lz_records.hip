@@ -240,14 +240,20 @@ int lz_seek_record(lz_dev* h, const lz_read_index* x, uint64_t id, uint8_t* d_ou
   uint64_t* res = (uint64_t*)(win + wbytes);
   const uint64_t zero = 0;
   hipStream_t s = (hipStream_t)stream;
+  // the plan's staging and the result words come from the handle's pinned
+  // staging (kept across calls), else from a pinned allocation of the plan
+  // and a pageable copy
+  std::unique_lock<std::mutex> lock;
+  uint64_t local[3] = {0, 0, 0};
+  uint8_t* pin = lz::lend_sync_staging(h, P, 3 * sizeof(uint64_t), lock);
+  uint64_t* hres = pin ? (uint64_t*)pin : local;
   rc = lz_range_run(h, P, win, W, &zero, win + wbytes + 256, scratch_cap - wbytes - 256, nullptr, stream);
   if (!rc) {
     hipLaunchKernelGGL(k_find_record, dim3(1), dim3(kFindThreads), 0, s, (const uint8_t*)win, W, skip, skip + x->lines,
                        d_out, out_cap, res);
     if (hipGetLastError() != hipSuccess) rc = lz::fail(LZ_E_HIP, "record search launch failed");
   }
-  uint64_t hres[3] = {0, 0, 0};
-  if (!rc && (hipMemcpyAsync(hres, res, sizeof(hres), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (!rc && (hipMemcpyAsync(hres, res, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
               hipStreamSynchronize(s) != hipSuccess))
     rc = lz::fail(LZ_E_HIP, "record search failed");
   if (rc) (void)hipStreamSynchronize(s);  // the plan's staging may still be read
