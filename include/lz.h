@@ -82,11 +82,17 @@ typedef struct lz_params {
    * a pass takes the depths of earlier blocks from the parse before it and
    * those of its own block from itself. */
   uint32_t depth_passes;
+  /* Threshold mode: 0 = thr[] for every block; 1 = learned (Sec. 4.3 and
+   * Sec. 6: the best tuple is data-dependent): each block's tuple is chosen
+   * by the selector stored at mlp_path (a file of lz_selector_save), as
+   * lz_encode_learned does with an in-memory selector. */
+  uint32_t mode;
+  const char* mlp_path;
 } lz_params;
 
 /* Fills the defaults: 64 KiB blocks, thresholds 6/8/10/12, bounds 4 KiB /
  * 64 KiB / 1 MiB, max_chain 32, all threads, whole-prefix window, one
- * depth-aware parse (depth_passes 1). */
+ * depth-aware parse (depth_passes 1), mode 0. */
 int lz_params_default(lz_params* p);
 
 /* Greedy LZ77 parse of in[0,n) with per-class thresholds (Sec. 4.2) into a

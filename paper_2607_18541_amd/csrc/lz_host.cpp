@@ -717,6 +717,18 @@ int lz_params_default(lz_params* p) {
 }
 
 int lz_encode(const uint8_t* in, uint64_t n, const lz_params* p, uint8_t** arc, uint64_t* arc_size) {
+  if (p && p->mode > 1) return fail(LZ_E_INVAL, "mode must be 0 (fixed) or 1 (learned)");
+  if (p && p->mode == 1) {
+    if (!p->mlp_path) return fail(LZ_E_INVAL, "learned mode needs mlp_path");
+    lz_selector* sel = nullptr;
+    int rc = lz_selector_load(p->mlp_path, &sel);
+    if (rc) return rc;
+    lz_params q = *p;
+    q.mode = 0;
+    rc = lz_encode_learned(in, n, &q, sel, arc, arc_size, nullptr);
+    lz_selector_free(sel);
+    return rc;
+  }
   return encode_impl(in, n, p, nullptr, nullptr, arc, arc_size);
 }
 

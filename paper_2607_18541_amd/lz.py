@@ -39,7 +39,7 @@ PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_
 class Params(ctypes.Structure):
     _fields_ = [("log2_bs", _u32), ("thr", _u32 * 4), ("bound", _u64 * 3), ("max_chain", _u32),
                 ("n_threads", _u32), ("segment", _u64), ("progress", PROGRESS_FN), ("progress_user", ctypes.c_void_p),
-                ("depth_passes", _u32)]
+                ("depth_passes", _u32), ("mode", _u32), ("mlp_path", ctypes.c_char_p)]
 
 
 class Info(ctypes.Structure):
@@ -198,13 +198,19 @@ def params(log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=
 
 
 def encode(x, log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0, progress=None,
-           depth_passes=1):
+           depth_passes=1, mlp_path=None):
     """Greedy parse with per-distance-class thresholds into a container.
     progress(done, total), if given, is called after each segment;
     depth_passes (default 1) re-parses that many times breaking length ties
-    by the lowest resulting dependency depth (0: nearest source)."""
+    by the lowest resulting dependency depth (0: nearest source); mlp_path,
+    if given, selects learned mode: each block's tuple comes from the
+    selector saved there (thr is then unused)."""
     x = _u8(x)
     p = params(log2_bs, thr, bounds, max_chain, n_threads, segment, depth_passes)
+    if mlp_path is not None:
+        path = os.fsencode(mlp_path)
+        p.mode = 1
+        p.mlp_path = path
     if progress is not None:
         cb = PROGRESS_FN(lambda d, t, u: progress(int(d), int(t)))
         p.progress = cb

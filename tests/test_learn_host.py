@@ -140,3 +140,26 @@ def test_learned_encode_stores_and_obeys_the_chosen_tuples(pick):
     cls = np.where(d < B[0], 0, np.where(d < B[1], 1, np.where(d < B[2], 2, 3)))
     last = np.r_[T["blk"][1:] != T["blk"][:-1], True][m]  # a block's last token has an implied length
     assert np.all((T["mlen"][m] >= TUPLES[pick][cls]) | last)
+
+
+def test_encode_learned_mode_through_params(tmp_path):
+    """lz_params.mode = 1 with a selector file gives the archive of
+    lz_encode_learned with the same selector, byte for byte; mode 1 without a
+    file and modes above 1 are refused."""
+    x = synth.fastq(200_000, seed=13)
+    sel = _selector(4, confident=10)
+    sel.calibrate(np.zeros((4, 64), np.float32), np.where(np.arange(16) == 10, 0.5, 2.0)[None, :].repeat(4, 0))
+    path = str(tmp_path / "sel.bin")
+    sel.save(path)
+    direct, _ = lz.encode_learned(x, sel, log2_bs=14)
+    via_params = lz.encode(x, 14, lz.TUNED_THR, mlp_path=path)  # header thresholds: informational
+    assert bytes(np.asarray(via_params)) == bytes(np.asarray(direct))
+    assert np.array_equal(oracle.decode(via_params), x)
+    p = lz.params(14)
+    for mode, fname in ((1, None), (2, path.encode())):
+        p.mode = mode
+        p.mlp_path = fname
+        pa, sz = lz.ctypes.c_void_p(), lz.ctypes.c_uint64()
+        rc = lz.lib().lz_encode(lz._u8(x).ctypes.data, x.size, lz.ctypes.byref(p), lz.ctypes.byref(pa),
+                                lz.ctypes.byref(sz))
+        assert rc == lz.LZ_E_INVAL
