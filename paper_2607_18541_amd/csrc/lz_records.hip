@@ -190,13 +190,25 @@ int lz_read_index_load(const char* path, lz_read_index** out) {
             fread(&nb, 8, 1, f) == 1 && x->log2_bs >= 4 && x->log2_bs <= 24 && x->lines > 0 &&
             nb == ((x->n + (1ull << x->log2_bs) - 1) >> x->log2_bs);
   if (ok) {
-    x->first_id.resize(nb);
-    x->first_off.resize(nb);
-    ok = fread(x->first_id.data(), 8, nb, f) == nb && fread(x->first_off.data(), 8, nb, f) == nb;
+    // the tables must be in the file before they are allocated (a corrupt
+    // size field must not ask for an arbitrary allocation)
+    const long at = ftell(f);
+    ok = at >= 0 && fseek(f, 0, SEEK_END) == 0 && ftell(f) >= at && (uint64_t)(ftell(f) - at) == 16 * nb &&
+         fseek(f, at, SEEK_SET) == 0;
+  }
+  if (ok) {
+    try {
+      x->first_id.resize(nb);
+      x->first_off.resize(nb);
+      ok = fread(x->first_id.data(), 8, nb, f) == nb && fread(x->first_off.data(), 8, nb, f) == nb;
+    } catch (const std::bad_alloc&) {
+      ok = false;
+    }
   }
   fclose(f);
   for (uint64_t b = 0; ok && b < nb; ++b)
-    ok = x->first_off[b] <= x->n && x->first_id[b] <= x->records && (b == 0 || x->first_id[b] >= x->first_id[b - 1]);
+    ok = x->first_off[b] <= x->n && x->first_id[b] <= x->records &&
+         (b == 0 || (x->first_id[b] >= x->first_id[b - 1] && x->first_off[b] >= x->first_off[b - 1]));
   if (!ok) {
     delete x;
     return lz::fail(LZ_E_CORRUPT, "%s is not a read index", path);

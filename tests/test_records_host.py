@@ -62,7 +62,27 @@ def test_index_file_round_trip(tmp_path):
     nb = (x.size + 1023) >> 10
     assert [back.block(b) for b in range(nb)] == [idx.block(b) for b in range(nb)]
     bad = tmp_path / "bad.bin"
-    bad.write_bytes(open(p, "rb").read()[:40])
+    good = open(p, "rb").read()
+    bad.write_bytes(good[:40])
     with pytest.raises(lz.LzError) as e:
         lz.ReadIndex(path=str(bad))
     assert e.value.rc == lz.LZ_E_CORRUPT
+    # a size field that claims a huge input (and so a huge table) is refused
+    # before anything is allocated for it
+    huge = bytearray(good)
+    huge[8:16] = (1 << 62).to_bytes(8, "little")
+    huge[32:40] = ((1 << 62) >> 10).to_bytes(8, "little")
+    bad.write_bytes(bytes(huge))
+    with pytest.raises(lz.LzError) as e:
+        lz.ReadIndex(path=str(bad))
+    assert e.value.rc == lz.LZ_E_CORRUPT
+    # record offsets that go backwards are refused
+    nbk = int.from_bytes(good[32:40], "little")
+    offs = np.frombuffer(good[40 + 8 * nbk:], np.uint64).copy()
+    if nbk > 2:
+        offs[2] = 0 if offs[1] > 0 else offs[2]
+        if offs[1] > 0:
+            bad.write_bytes(good[:40 + 8 * nbk] + offs.tobytes())
+            with pytest.raises(lz.LzError) as e:
+                lz.ReadIndex(path=str(bad))
+            assert e.value.rc == lz.LZ_E_CORRUPT
