@@ -80,8 +80,6 @@ uint32_t argmax16(const double* p) {
 // Gaussian elimination with partial pivoting; a pivot below tol leaves its
 // unknown at 0 (least squares with dependent columns).
 void solve_small(int n, double* A, double* b, double* c) {
-  int piv[8];
-  for (int i = 0; i < n; ++i) piv[i] = i;
   bool used[8] = {false};
   for (int col = 0; col < n; ++col) {
     int best = -1;
@@ -103,7 +101,6 @@ void solve_small(int n, double* A, double* b, double* c) {
     }
   }
   for (int i = 0; i < n; ++i) c[i] = used[i] ? b[i] / A[i * n + i] : 0.0;
-  (void)piv;
 }
 
 }  // namespace
