@@ -849,7 +849,9 @@ def run_ablate(args, torch, lz):
     """Threshold and distance-band variants and schedule mechanisms on the
     FASTQ-like workload: the tuple the paper rejects (16/24/32/48), the paper's
     own distance bands with both headline tuples, and, on 12/16/24/32, the
-    decode without the one-workgroup tail, with G = 32, and with schedule 0."""
+    decode without the one-workgroup tail, with G = 32, with schedule 0, and
+    with the depth passes held to 6, 4 and 3 resident workgroups per CU (of
+    8; the occupancy control of Sec. 3.3)."""
     import synth
     dev = torch.device("cuda:0")
     x = synth.fastq(args.size, seed=3)
@@ -867,11 +869,12 @@ def run_ablate(args, torch, lz):
         ent, _ = lz.entropy_size(arc)
         da = lz.DeviceArchive(arc, device=dev)
         out = torch.empty(n, dtype=torch.uint8, device=dev)
-        mechs = [("G64 U2 schedule 1", 64, 2, 1, 0)]
+        mechs = [("G64 U2 schedule 1", 64, 2, 1, 0, 0)]
         if name == "12/16/24/32" and bname == "cfg":
-            mechs += [("no tail", 64, 2, 1, lz.TAIL_OFF), ("G32", 32, 2, 1, 0), ("schedule 0", 64, 2, 0, 0)]
-        for mname, G, U, S, T in mechs:
-            da.decode(out, G=G, unroll=U, schedule=S, tail=T)
+            mechs += [("no tail", 64, 2, 1, lz.TAIL_OFF, 0), ("G32", 32, 2, 1, 0, 0), ("schedule 0", 64, 2, 0, 0, 0)]
+            mechs += [("occupancy %d of 8" % k, 64, 2, 1, 0, k) for k in (6, 4, 3)]
+        for mname, G, U, S, T, O in mechs:
+            da.decode(out, G=G, unroll=U, schedule=S, tail=T, occupancy=O)
             torch.cuda.synchronize()
             if not bool(torch.equal(out, xt)):
                 raise SystemExit("ablation %s %s %s: decode differs from the input" % (name, bname, mname))
@@ -880,7 +883,7 @@ def run_ablate(args, torch, lz):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(st)
             for _ in range(steps):
-                da.decode_async(out, G=G, unroll=U, schedule=S, tail=T)
+                da.decode_async(out, G=G, unroll=U, schedule=S, tail=T, occupancy=O)
             e1.record(st)
             e1.synchronize()
             da.check()

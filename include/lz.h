@@ -175,13 +175,19 @@ typedef struct lz_dev lz_dev; /* opaque handle of a device-resident archive */
  * segments and windows run on different XCDs), 1 = XCD-contiguous (the
  * workgroups one XCD receives take one contiguous run of items, so
  * neighbouring writes meet in that XCD's L2).
- * NULL config = G 64, unroll 2, schedule 1, tail 0, mapping 0. */
+ * occupancy = 0: as many workgroups per CU as fit; k in [3, 8]: the depth
+ * passes of a schedule 1 decode (lz_decode_device, lz_decode_device_stage)
+ * run with at most k resident workgroups per CU (their LDS is padded to
+ * that), an occupancy control (Sec. 3.3); LZ_E_INVAL outside that range or
+ * above what fits anyway.  Batches and range plans ignore it.
+ * NULL config = G 64, unroll 2, schedule 1, tail 0, mapping 0, occupancy 0. */
 typedef struct lz_decode_cfg {
   uint32_t G;
   uint32_t unroll;
   uint32_t schedule;
   uint32_t tail;
   uint32_t mapping;
+  uint32_t occupancy;
 } lz_decode_cfg;
 
 /* Device bytes lz_device_open needs for this archive: the archive itself, the

@@ -947,10 +947,10 @@ struct lz_dev {
   struct GraphKey {
     uint8_t* out;
     uint64_t cap;
-    uint32_t G, U, sched, tail, stage, map;
+    uint32_t G, U, sched, tail, stage, map, occ;
     bool operator==(const GraphKey& o) const {
       return out == o.out && cap == o.cap && G == o.G && U == o.U && sched == o.sched && tail == o.tail &&
-             stage == o.stage && map == o.map;
+             stage == o.stage && map == o.map && occ == o.occ;
     }
   };
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
@@ -1229,12 +1229,13 @@ uint64_t tail_start(const std::vector<uint64_t>& windows, uint32_t limit) {
 }
 
 int resolve_cfg(const lz_decode_cfg* cfg, uint32_t& G, uint32_t& U, uint32_t& sched, uint32_t* tail = nullptr,
-                uint32_t* map = nullptr) {
+                uint32_t* map = nullptr, uint32_t* occ = nullptr) {
   G = cfg ? cfg->G : 64;
   U = cfg ? cfg->unroll : 2;
   sched = cfg ? cfg->schedule : 1;
   if (tail) *tail = (cfg && cfg->tail) ? cfg->tail : kTailWindows;
   if (map) *map = cfg ? cfg->mapping : 0;
+  if (occ) *occ = cfg ? cfg->occupancy : 0;
   if (cfg && cfg->mapping > 1) return lz::fail(LZ_E_INVAL, "mapping must be 0 or 1");
   if (!(G == 8 || G == 16 || G == 32 || G == 64)) return lz::fail(LZ_E_INVAL, "G must be 8, 16, 32 or 64");
   if (!(U == 1 || U == 2 || U == 4)) return lz::fail(LZ_E_INVAL, "unroll must be 1, 2 or 4");
@@ -1242,11 +1243,34 @@ int resolve_cfg(const lz_decode_cfg* cfg, uint32_t& G, uint32_t& U, uint32_t& sc
   return 0;
 }
 
-uint64_t resident_groups(kfn_t k, int cu_count, uint32_t G) {
+uint64_t resident_groups(kfn_t k, int cu_count, uint32_t G, size_t smem = 0) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, kWG, 0) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, kWG, smem) != hipSuccess || per_cu < 1)
     per_cu = 1;
   return (uint64_t)per_cu * (uint64_t)std::max(cu_count, 1) * (kWG / G);
+}
+
+// Dynamic LDS that leaves room for at most `occ` workgroups of k per CU (0:
+// no padding); LZ_E_INVAL if that is not a reduction the LDS can make.
+int occupancy_pad(kfn_t k, uint32_t occ, size_t* pad) {
+  *pad = 0;
+  if (occ == 0) return 0;
+  constexpr size_t kLdsPerCu = 160 * 1024, kMaxDynamic = 64 * 1024;
+  hipFuncAttributes fa;
+  int natural = 0;
+  if (hipFuncGetAttributes(&fa, (const void*)k) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&natural, (const void*)k, kWG, 0) != hipSuccess)
+    return lz::fail(LZ_E_HIP, "occupancy query failed");
+  if (occ < 3 || occ > 8 || (int)occ > natural)
+    return lz::fail(LZ_E_INVAL, "occupancy %u outside [3, min(8, %d)]", occ, natural);
+  const size_t per = (kLdsPerCu / occ) & ~size_t(255);
+  if (per <= fa.sharedSizeBytes || per - fa.sharedSizeBytes > kMaxDynamic)
+    return lz::fail(LZ_E_INVAL, "occupancy %u cannot be set by LDS padding", occ);
+  *pad = (int)occ == natural ? 0 : per - fa.sharedSizeBytes;
+  int got = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&got, (const void*)k, kWG, *pad) != hipSuccess || got != (int)occ)
+    return lz::fail(LZ_E_INVAL, "occupancy %u not reached by LDS padding (%d)", occ, got);
+  return 0;
 }
 
 uint64_t grid_for(uint64_t items, uint64_t resident, uint32_t G) {
@@ -1466,14 +1490,16 @@ int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cf
   if (out_cap < h->v.n) return lz::fail(LZ_E_INVAL, "output capacity %llu < n %llu", (unsigned long long)out_cap,
                                         (unsigned long long)h->v.n);
   if (h->v.n && !d_out) return lz::fail(LZ_E_INVAL, "null output");
-  uint32_t G, U, sched, tail, map;
-  int rc = resolve_cfg(cfg, G, U, sched, &tail, &map);
+  uint32_t G, U, sched, tail, map, occ;
+  int rc = resolve_cfg(cfg, G, U, sched, &tail, &map, &occ);
   if (rc) return rc;
   if (sched == 0 && out_cap > 0xFFFFFFFFull)
     return lz::fail(LZ_E_INVAL, "schedule 0 addresses outputs below 4 GiB; use schedule 1");
+  size_t pad = 0;
+  if (sched == 1 && (rc = occupancy_pad(pick_kernel<kModeLevels>(G, U), occ, &pad))) return rc;
   if (h->v.nb == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
-  lz_dev::GraphKey key{d_out, out_cap, G, U, sched, tail, (uint32_t)stage, map};
+  lz_dev::GraphKey key{d_out, out_cap, G, U, sched, tail, (uint32_t)stage, map, occ};
   for (auto& g : h->graphs)
     if (g.first == key) {
       HIPCHK(hipGraphLaunch(g.second, s));
@@ -1488,6 +1514,7 @@ int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cf
     uint64_t grid;
     KArgs a;
     unsigned block = kWG;
+    size_t smem = 0;
   };
   std::vector<Launch> seq;
   kfn_t kp = pick_kernel<kModeParse>(G, U);
@@ -1499,7 +1526,7 @@ int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cf
       seq.push_back({k, grid_for(windows, resident_groups(k, h->cu_count, G), G), A});
     } else {
       kfn_t k = pick_kernel<kModeLevels>(G, U);
-      const uint64_t res = resident_groups(k, h->cu_count, G);
+      const uint64_t res = resident_groups(k, h->cu_count, G, pad);
       const uint64_t NL = h->lvl_start.size() - 1;
       std::vector<uint64_t> win(NL);
       for (uint64_t p = 0; p < NL; ++p) win[p] = h->lvl_start[p + 1] - h->lvl_start[p];
@@ -1509,7 +1536,7 @@ int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cf
         a.lo = h->lvl_start[p];
         a.hi = h->lvl_start[p + 1];
         if (a.hi == a.lo) continue;
-        seq.push_back({k, grid_for((a.hi - a.lo) * (64 / G), res, G), a});
+        seq.push_back({k, grid_for((a.hi - a.lo) * (64 / G), res, G), a, (unsigned)kWG, pad});
       }
       if (pt < NL) {  // the deepest levels: one workgroup
         KArgs a = A;
@@ -1529,7 +1556,7 @@ int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cf
     kp2.func = (void*)L.k;
     kp2.gridDim = dim3((unsigned)L.grid);
     kp2.blockDim = dim3(L.block);
-    kp2.sharedMemBytes = 0;
+    kp2.sharedMemBytes = (unsigned)L.smem;
     kp2.kernelParams = args;
     kp2.extra = nullptr;
     hipGraphNode_t node;

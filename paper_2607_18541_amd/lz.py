@@ -51,7 +51,8 @@ class Info(ctypes.Structure):
 
 
 class DecodeCfg(ctypes.Structure):
-    _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("tail", _u32), ("mapping", _u32)]
+    _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("tail", _u32), ("mapping", _u32),
+                ("occupancy", _u32)]
 
 
 class TuneReport(ctypes.Structure):
@@ -292,9 +293,9 @@ def fnv1a64(data, seed=0xcbf29ce484222325):
 TAIL_OFF = 0xFFFFFFFF
 
 
-def _cfg(G=64, unroll=2, schedule=1, tail=0, mapping=0):
+def _cfg(G=64, unroll=2, schedule=1, tail=0, mapping=0, occupancy=0):
     c = DecodeCfg()
-    c.G, c.unroll, c.schedule, c.tail, c.mapping = G, unroll, schedule, tail, mapping
+    c.G, c.unroll, c.schedule, c.tail, c.mapping, c.occupancy = G, unroll, schedule, tail, mapping, occupancy
     return c
 
 
@@ -330,11 +331,11 @@ class DeviceArchive:
         self.levels = int(lib().lz_device_levels(h))
         self.device_bytes = nb.value
 
-    def decode(self, out=None, G=64, unroll=2, schedule=1, stream=None, check=True, tail=0, mapping=0):
+    def decode(self, out=None, G=64, unroll=2, schedule=1, stream=None, check=True, tail=0, mapping=0, occupancy=0):
         import torch
         if out is None:
             out = torch.empty(max(self.n, 1), dtype=torch.uint8, device=self.buf.device)
-        c = _cfg(G, unroll, schedule, tail, mapping)
+        c = _cfg(G, unroll, schedule, tail, mapping, occupancy)
         rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                     _stream(stream))
         if rc:
@@ -343,8 +344,8 @@ class DeviceArchive:
             self.check(stream)
         return out[:self.n]
 
-    def decode_async(self, out, G=64, unroll=2, schedule=1, stream=None, tail=0, mapping=0):
-        c = _cfg(G, unroll, schedule, tail, mapping)
+    def decode_async(self, out, G=64, unroll=2, schedule=1, stream=None, tail=0, mapping=0, occupancy=0):
+        c = _cfg(G, unroll, schedule, tail, mapping, occupancy)
         rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                     _stream(stream))
         if rc:

@@ -273,3 +273,26 @@ def test_dense_short_runs_many_per_block():
         pos += M
     arc, exp = _tokens_to_arc(pos, toks, lits, 14)
     _check(arc, exp, [(64, 2, 1), (64, 1, 0), (32, 4, 1), (8, 2, 1)], "dense-short")
+
+
+def test_occupancy_control_decodes_exactly():
+    """The occupancy control (depth passes held to k resident workgroups per
+    CU by LDS padding) changes only the schedule: the bytes equal the
+    oracle's; values outside [3, 8] are refused."""
+    dev = _dev()
+    x = synth.fastq(4 << 20, seed=3)
+    arc = lz.encode(x, 16, lz.TUNED_THR)
+    da = lz.DeviceArchive(arc, device=dev)
+    exp_t = torch.from_numpy(oracle.decode(arc)).to(dev)
+    for k in (6, 4, 3):
+        print(f"[occupancy {k}]", flush=True)
+        out = torch.full((da.n + 64,), 0xA5, dtype=torch.uint8, device=dev)
+        got = da.decode(out, occupancy=k)
+        torch.cuda.synchronize()
+        assert torch.equal(got, exp_t), k
+        assert bool((out[da.n:] == 0xA5).all().item())
+    for bad in (2, 9):
+        with pytest.raises(lz.LzError) as e:
+            da.decode(occupancy=bad)
+        assert e.value.rc == lz.LZ_E_INVAL
+    da.close()
