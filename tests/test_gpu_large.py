@@ -93,3 +93,49 @@ def test_decode_above_4gib_matches_oracle():
     srv.release(rid)
     srv.destroy()
     da.close()
+
+
+@pytest.mark.parametrize("thr", [lz.BASE_THR, lz.TUNED_THR])
+def test_fastq_1gib_full_size_matches_oracle(thr):
+    """The benchmark's FASTQ-like workload at its full size (1,073,741,535
+    bytes, 64 KiB blocks) in the launch configuration the bench times (G 64,
+    unroll 2, schedule 1): the GPU decode equals the oracle's sequential
+    decode of the same archive and the input, byte for byte and by FNV-1a 64;
+    so do ranges sampled across the file."""
+    dev = _dev()
+    x = synth.fastq(1 << 30, seed=3)
+    print("encoding %d bytes with %s" % (x.size, thr), flush=True)
+    arc = lz.encode(x, 16, thr)
+    ref = oracle.decode(arc)
+    assert np.array_equal(ref, x)
+    da = lz.DeviceArchive(arc, device=dev)
+    out = da.decode(G=64, unroll=2, schedule=1)
+    torch.cuda.synchronize()
+    assert torch.equal(out, torch.from_numpy(ref).to(dev))
+    assert lz.fnv1a64(out.cpu().numpy()) == oracle.fnv1a64(ref)
+    rng = np.random.default_rng(7)
+    for _ in range(12):
+        L = int(np.exp(rng.uniform(np.log(16), np.log(8 << 20))))
+        o = int(rng.integers(0, x.size - L))
+        got = da.decode_range(o, L)
+        assert bytes(got.cpu().numpy()) == bytes(ref[o:o + L]), (o, L)
+    da.close()
+
+
+@pytest.mark.parametrize("m", [256, 1024])
+def test_sweep_stream_full_size_matches_oracle(m):
+    """The granularity sweep's 256 MiB streams at the mean match lengths where
+    the bandwidth target is set, 16 KiB blocks, every G: equal to the oracle's
+    execution of the same tokens."""
+    dev = _dev()
+    n = 1 << 28
+    seed = 2 + (32, 64, 128, 256, 512, 1024).index(m)
+    ll, ml, sr, lit = synth.geo_tokens(n, m, seed=seed)
+    exp = torch.from_numpy(oracle.exec_tokens(n, ll, ml, sr, lit)).to(dev)
+    da = lz.DeviceArchive(lz.build_archive(n, 14, ll, ml, sr, lit), device=dev)
+    for G in (8, 16, 32, 64):
+        print("m=%d G=%d" % (m, G), flush=True)
+        out = da.decode(G=G)
+        torch.cuda.synchronize()
+        assert torch.equal(out, exp), G
+    da.close()
