@@ -180,7 +180,12 @@ typedef struct lz_dev lz_dev; /* opaque handle of a device-resident archive */
  * run with at most k resident workgroups per CU (their LDS is padded to
  * that), an occupancy control (Sec. 3.3); LZ_E_INVAL outside that range or
  * above what fits anyway.  Batches and range plans ignore it.
- * NULL config = G 64, unroll 2, schedule 1, tail 0, mapping 0, occupancy 0. */
+ * G and unroll select the match copy; the parse launch has its own group
+ * size and unroll (parse_G, parse_unroll): a whole wave per 256-token
+ * segment is the fastest parse at every G (measured: at G = 32 the parse
+ * with 32-lane groups takes 1.07 ms of a 1.84 ms decode, with a wave 0.63).
+ * NULL config = G 64, unroll 2, schedule 1, tail 0, mapping 0, occupancy 0,
+ * parse_G 64, parse_unroll 2. */
 typedef struct lz_decode_cfg {
   uint32_t G;
   uint32_t unroll;
@@ -188,6 +193,8 @@ typedef struct lz_decode_cfg {
   uint32_t tail;
   uint32_t mapping;
   uint32_t occupancy;
+  uint32_t parse_G;       /* lanes per parse group (8, 16, 32, 64; 0 = 64, one wave) */
+  uint32_t parse_unroll;  /* 16-byte blocks per lane per parse step (1, 2, 4; 0 = 2) */
 } lz_decode_cfg;
 
 /* Device bytes lz_device_open needs for this archive: the archive itself, the

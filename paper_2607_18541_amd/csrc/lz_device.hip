@@ -947,10 +947,10 @@ struct lz_dev {
   struct GraphKey {
     uint8_t* out;
     uint64_t cap;
-    uint32_t G, U, sched, tail, stage, map, occ;
+    uint32_t G, U, sched, tail, stage, map, occ, pG, pU;
     bool operator==(const GraphKey& o) const {
       return out == o.out && cap == o.cap && G == o.G && U == o.U && sched == o.sched && tail == o.tail &&
-             stage == o.stage && map == o.map && occ == o.occ;
+             stage == o.stage && map == o.map && occ == o.occ && pG == o.pG && pU == o.pU;
     }
   };
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
@@ -1229,13 +1229,19 @@ uint64_t tail_start(const std::vector<uint64_t>& windows, uint32_t limit) {
 }
 
 int resolve_cfg(const lz_decode_cfg* cfg, uint32_t& G, uint32_t& U, uint32_t& sched, uint32_t* tail = nullptr,
-                uint32_t* map = nullptr, uint32_t* occ = nullptr) {
+                uint32_t* map = nullptr, uint32_t* occ = nullptr, uint32_t* pG = nullptr, uint32_t* pU = nullptr) {
   G = cfg ? cfg->G : 64;
   U = cfg ? cfg->unroll : 2;
   sched = cfg ? cfg->schedule : 1;
   if (tail) *tail = (cfg && cfg->tail) ? cfg->tail : kTailWindows;
   if (map) *map = cfg ? cfg->mapping : 0;
   if (occ) *occ = cfg ? cfg->occupancy : 0;
+  const uint32_t parse_G = (cfg && cfg->parse_G) ? cfg->parse_G : 64, parse_U = (cfg && cfg->parse_unroll) ? cfg->parse_unroll : 2;
+  if (!(parse_G == 8 || parse_G == 16 || parse_G == 32 || parse_G == 64))
+    return lz::fail(LZ_E_INVAL, "parse_G must be 8, 16, 32 or 64");
+  if (!(parse_U == 1 || parse_U == 2 || parse_U == 4)) return lz::fail(LZ_E_INVAL, "parse_unroll must be 1, 2 or 4");
+  if (pG) *pG = parse_G;
+  if (pU) *pU = parse_U;
   if (cfg && cfg->mapping > 1) return lz::fail(LZ_E_INVAL, "mapping must be 0 or 1");
   if (!(G == 8 || G == 16 || G == 32 || G == 64)) return lz::fail(LZ_E_INVAL, "G must be 8, 16, 32 or 64");
   if (!(U == 1 || U == 2 || U == 4)) return lz::fail(LZ_E_INVAL, "unroll must be 1, 2 or 4");
@@ -1490,8 +1496,8 @@ int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cf
   if (out_cap < h->v.n) return lz::fail(LZ_E_INVAL, "output capacity %llu < n %llu", (unsigned long long)out_cap,
                                         (unsigned long long)h->v.n);
   if (h->v.n && !d_out) return lz::fail(LZ_E_INVAL, "null output");
-  uint32_t G, U, sched, tail, map, occ;
-  int rc = resolve_cfg(cfg, G, U, sched, &tail, &map, &occ);
+  uint32_t G, U, sched, tail, map, occ, pG, pU;
+  int rc = resolve_cfg(cfg, G, U, sched, &tail, &map, &occ, &pG, &pU);
   if (rc) return rc;
   if (sched == 0 && out_cap > 0xFFFFFFFFull)
     return lz::fail(LZ_E_INVAL, "schedule 0 addresses outputs below 4 GiB; use schedule 1");
@@ -1499,7 +1505,7 @@ int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cf
   if (sched == 1 && (rc = occupancy_pad(pick_kernel<kModeLevels>(G, U), occ, &pad))) return rc;
   if (h->v.nb == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
-  lz_dev::GraphKey key{d_out, out_cap, G, U, sched, tail, (uint32_t)stage, map, occ};
+  lz_dev::GraphKey key{d_out, out_cap, G, U, sched, tail, (uint32_t)stage, map, occ, pG, pU};
   for (auto& g : h->graphs)
     if (g.first == key) {
       HIPCHK(hipGraphLaunch(g.second, s));
@@ -1517,8 +1523,8 @@ int decode_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cf
     size_t smem = 0;
   };
   std::vector<Launch> seq;
-  kfn_t kp = pick_kernel<kModeParse>(G, U);
-  if (stage != 2) seq.push_back({kp, grid_for(h->n_seg, resident_groups(kp, h->cu_count, G), G), A});
+  kfn_t kp = pick_kernel<kModeParse>(pG, pU);
+  if (stage != 2) seq.push_back({kp, grid_for(h->n_seg, resident_groups(kp, h->cu_count, pG), pG), A});
   if (h->n_match && stage != 1) {
     if (sched == 0) {
       kfn_t k = pick_kernel<kModeFlow>(G, U);
@@ -1959,8 +1965,8 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
   for (uint64_t r = 0; r < P->count; ++r)
     if (out_off[r] > out_cap || P->range_len[r] > out_cap - out_off[r])
       return lz::fail(LZ_E_INVAL, "range %llu does not fit the output arena", (unsigned long long)r);
-  uint32_t G, U, sched, tail, map;
-  int rc = resolve_cfg(cfg, G, U, sched, &tail, &map);
+  uint32_t G, U, sched, tail, map, occ, pG, pU;
+  int rc = resolve_cfg(cfg, G, U, sched, &tail, &map, &occ, &pG, &pU);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   const uint64_t np = P->p_dst.size();
@@ -2010,9 +2016,9 @@ int lz_range_run(lz_dev* h, lz_range_plan* P, uint8_t* d_out, uint64_t out_cap, 
     A.seg = h->d_seg + 8 * P->seg_lo;
     A.nseg = P->seg_hi - P->seg_lo;
     if (A.nseg) {
-      kfn_t kp = pick_kernel<kModeParse>(G, U);
-      hipLaunchKernelGGL(kp, dim3((unsigned)grid_for(A.nseg, resident_groups(kp, h->cu_count, G), G)), dim3(kWG), 0,
-                         s, A);
+      kfn_t kp = pick_kernel<kModeParse>(pG, pU);
+      hipLaunchKernelGGL(kp, dim3((unsigned)grid_for(A.nseg, resident_groups(kp, h->cu_count, pG), pG)), dim3(kWG),
+                         0, s, A);
       HIPCHK(hipGetLastError());
     }
     kfn_t kl = pick_kernel<kModeLevels>(G, U);
@@ -2159,10 +2165,13 @@ std::vector<BatchGroup> make_groups(uint32_t count, const lz_decode_cfg* cfgs) {
     if (cfgs) c = cfgs[i];
     if (!c.G) c.G = 64;
     if (!c.unroll) c.unroll = 2;
+    if (!c.parse_G) c.parse_G = 64;
+    if (!c.parse_unroll) c.parse_unroll = 2;
     size_t k = 0;
     for (; k < groups.size(); ++k)
       if (groups[k].cfg.G == c.G && groups[k].cfg.unroll == c.unroll && groups[k].cfg.schedule == c.schedule &&
-          groups[k].cfg.tail == c.tail && groups[k].cfg.mapping == c.mapping)
+          groups[k].cfg.tail == c.tail && groups[k].cfg.mapping == c.mapping &&
+          groups[k].cfg.parse_G == c.parse_G && groups[k].cfg.parse_unroll == c.parse_unroll)
         break;
     if (k == groups.size()) groups.push_back(BatchGroup{c, {}});
     groups[k].arcs.push_back(i);
@@ -2226,8 +2235,8 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
   int cu = 0;
   for (lz_dev* h : H) cu = std::max(cu, h->cu_count);
   for (auto& g : groups) {
-    uint32_t G, U, sched, tail, map;
-    (void)resolve_cfg(&g.cfg, G, U, sched, &tail, &map);
+    uint32_t G, U, sched, tail, map, occ, pG, pU;
+    (void)resolve_cfg(&g.cfg, G, U, sched, &tail, &map, &occ, &pG, &pU);
     uint64_t nseg, nw, nl;
     group_scratch(H, g, &nseg, &nw, &nl);
     const uint64_t o_desc = off;
@@ -2283,8 +2292,8 @@ int lz_batch_create(uint32_t count, lz_dev* const* handles, uint8_t* const* d_ou
     A.err = (uint32_t*)(D0 + o_err);
     A.n_levels = (uint32_t)nl;
     if (nseg) {
-      kfn_t kp = pick_kernel<kModeParse>(G, U, true);
-      seq.push_back({kp, grid_for(nseg, resident_groups(kp, cu, G), G), A});
+      kfn_t kp = pick_kernel<kModeParse>(pG, pU, true);
+      seq.push_back({kp, grid_for(nseg, resident_groups(kp, cu, pG), pG), A});
     }
     if (nw) {
       if (sched == 0) {

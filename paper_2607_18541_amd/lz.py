@@ -52,7 +52,7 @@ class Info(ctypes.Structure):
 
 class DecodeCfg(ctypes.Structure):
     _fields_ = [("G", _u32), ("unroll", _u32), ("schedule", _u32), ("tail", _u32), ("mapping", _u32),
-                ("occupancy", _u32)]
+                ("occupancy", _u32), ("parse_G", _u32), ("parse_unroll", _u32)]
 
 
 class TuneReport(ctypes.Structure):
@@ -293,9 +293,10 @@ def fnv1a64(data, seed=0xcbf29ce484222325):
 TAIL_OFF = 0xFFFFFFFF
 
 
-def _cfg(G=64, unroll=2, schedule=1, tail=0, mapping=0, occupancy=0):
+def _cfg(G=64, unroll=2, schedule=1, tail=0, mapping=0, occupancy=0, parse_G=0, parse_unroll=0):
     c = DecodeCfg()
     c.G, c.unroll, c.schedule, c.tail, c.mapping, c.occupancy = G, unroll, schedule, tail, mapping, occupancy
+    c.parse_G, c.parse_unroll = parse_G, parse_unroll
     return c
 
 
@@ -331,11 +332,12 @@ class DeviceArchive:
         self.levels = int(lib().lz_device_levels(h))
         self.device_bytes = nb.value
 
-    def decode(self, out=None, G=64, unroll=2, schedule=1, stream=None, check=True, tail=0, mapping=0, occupancy=0):
+    def decode(self, out=None, G=64, unroll=2, schedule=1, stream=None, check=True, tail=0, mapping=0, occupancy=0,
+               parse_G=0, parse_unroll=0):
         import torch
         if out is None:
             out = torch.empty(max(self.n, 1), dtype=torch.uint8, device=self.buf.device)
-        c = _cfg(G, unroll, schedule, tail, mapping, occupancy)
+        c = _cfg(G, unroll, schedule, tail, mapping, occupancy, parse_G, parse_unroll)
         rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                     _stream(stream))
         if rc:
@@ -344,16 +346,18 @@ class DeviceArchive:
             self.check(stream)
         return out[:self.n]
 
-    def decode_async(self, out, G=64, unroll=2, schedule=1, stream=None, tail=0, mapping=0, occupancy=0):
-        c = _cfg(G, unroll, schedule, tail, mapping, occupancy)
+    def decode_async(self, out, G=64, unroll=2, schedule=1, stream=None, tail=0, mapping=0, occupancy=0,
+                     parse_G=0, parse_unroll=0):
+        c = _cfg(G, unroll, schedule, tail, mapping, occupancy, parse_G, parse_unroll)
         rc = lib().lz_decode_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                     _stream(stream))
         if rc:
             raise LzError(rc, "lz_decode_device")
 
-    def decode_stage(self, out, stage, G=64, unroll=2, schedule=1, stream=None, tail=0, mapping=0):
+    def decode_stage(self, out, stage, G=64, unroll=2, schedule=1, stream=None, tail=0, mapping=0, parse_G=0,
+                     parse_unroll=0):
         """Stage 1 = parse launch, 2 = match passes (after stage 1), 0 = both."""
-        c = _cfg(G, unroll, schedule, tail, mapping)
+        c = _cfg(G, unroll, schedule, tail, mapping, 0, parse_G, parse_unroll)
         rc = lib().lz_decode_device_stage(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(c),
                                           int(stage), _stream(stream))
         if rc:

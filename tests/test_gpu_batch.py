@@ -50,8 +50,11 @@ def test_batch_equals_solo(mix):
     if mix == "default":
         cfgs = None
     elif mix == "mixed":
-        # G, unroll, schedule, tail (default), mapping (XCD-contiguous on every other pair)
-        cfgs = [((16, 32, 64)[i % 3], (1, 2, 4)[i % 3], i % 2, 0, (i // 2) % 2) for i in range(len(das))]
+        # G, unroll, schedule, tail (default), mapping (XCD-contiguous on every
+        # other pair), occupancy (default), parse G and unroll (the copy's, or
+        # the default wave)
+        cfgs = [((16, 32, 64)[i % 3], (1, 2, 4)[i % 3], i % 2, 0, (i // 2) % 2, 0, ((16, 32, 64)[i % 3], 0)[i % 5 == 0],
+                 ((1, 2, 4)[i % 3], 0)[i % 5 == 0]) for i in range(len(das))]
     else:
         cfgs = [(32, 2, 0)] * len(das)
     print(f"[batch {mix}] {len(das)} archives", flush=True)

@@ -27,9 +27,12 @@ def _check(arc, expect, cfgs, label):
     for c in cfgs:
         G, U, S = c[:3]
         M = c[3] if len(c) > 3 else 0
-        print(f"[{label}] G={G} U={U} sched={S} mapping={M} n={da.n}", flush=True)
+        # the parse runs with the copy's G and unroll unless the case names its own
+        PG = c[4] if len(c) > 4 else G
+        PU = c[5] if len(c) > 5 else U
+        print(f"[{label}] G={G} U={U} sched={S} mapping={M} parse {PG}/{PU} n={da.n}", flush=True)
         out = torch.full((max(da.n, 1) + 64,), 0xA5, dtype=torch.uint8, device=dev)
-        got = da.decode(out, G=G, unroll=U, schedule=S, mapping=M)
+        got = da.decode(out, G=G, unroll=U, schedule=S, mapping=M, parse_G=PG, parse_unroll=PU)
         torch.cuda.synchronize()
         if not torch.equal(got, exp_t):
             bad = (got != exp_t).nonzero()
@@ -41,9 +44,11 @@ def _check(arc, expect, cfgs, label):
     da.close()
 
 
-# (G, unroll, schedule[, mapping]); mapping 1 = XCD-contiguous workgroups
-ALL = [(G, U, S) for G in GS for U in (1, 2, 4) for S in (0, 1)] + [(64, 2, 1, 1), (32, 4, 0, 1), (8, 1, 1, 1)]
-SOME = [(8, 2, 0), (32, 1, 0), (64, 4, 0), (16, 2, 1), (32, 4, 1), (64, 2, 1, 1), (16, 2, 0, 1)]
+# (G, unroll, schedule[, mapping[, parse G, parse unroll]]); mapping 1 =
+# XCD-contiguous workgroups; without parse values the parse takes G and unroll
+ALL = [(G, U, S) for G in GS for U in (1, 2, 4) for S in (0, 1)] + [(64, 2, 1, 1), (32, 4, 0, 1), (8, 1, 1, 1)] + \
+    [(32, 2, 1, 0, 64, 2), (8, 4, 1, 0, 64, 2), (16, 1, 0, 0, 64, 4), (64, 2, 1, 0, 32, 1)]
+SOME = [(8, 2, 0), (32, 1, 0), (64, 4, 0), (16, 2, 1), (32, 4, 1), (64, 2, 1, 1), (16, 2, 0, 1), (32, 2, 1, 0, 64, 2)]
 
 
 def test_zipf_1mib_all_configs():
