@@ -557,7 +557,8 @@ def run_batch(args, torch, lz):
     res["batch_autotuned"] = {"ms": round(ms, 3), "gbps": round(total / ms / 1e6, 2), "launches": b.launches,
                               "buckets": [{"bytes": [r["min_bytes"], r["max_bytes"]], "archives": r["archives"],
                                            "best": list(r["best"]), "best_ms": round(r["best_ms"], 4),
-                                           "default_ms": round(r["default_ms"], 4)} for r in report]}
+                                           "default_ms": round(r["default_ms"], 4)} for r in report],
+                              "kept_bucket_choices": any(tuple(c)[:5] != (64, 2, 1, 0, 0) for c in cfgs)}
     log("one batch graph, autotuned: %.3f ms, %.1f GB/s" % (ms, total / ms / 1e6))
     b.destroy()
     best = max(v["gbps"] for v in res.values())

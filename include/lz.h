@@ -370,7 +370,11 @@ void lz_batch_destroy(lz_batch* batch);
  * bucket every (G in {16,32,64}) x (unroll in {1,2,4}) x (schedule 1, 0) x
  * (mapping 0, 1) is timed with HIP events as a batch of that bucket alone
  * (one warm-up, `reps` replays) and the fastest is written to chosen[i] for
- * the bucket's archives.
+ * the bucket's archives.  A batch with several configurations runs a launch
+ * sequence per configuration, so the whole batch is then timed with the
+ * choices and with the default, and every chosen[i] becomes the default
+ * when that is not slower (skipped when scratch_cap is below
+ * lz_batch_scratch_bytes for the choices).
  * report (optional) receives one entry per non-empty bucket. */
 typedef struct lz_tune_report {
   uint64_t min_bytes, max_bytes, bytes;

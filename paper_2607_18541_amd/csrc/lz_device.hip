@@ -2401,6 +2401,23 @@ extern "C" int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* cons
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
+  // mean time of one replay of a batch (one warm-up launch, `reps` timed)
+  auto time_batch = [&](uint32_t cnt, lz_dev* const* hs, uint8_t* const* outs, const uint64_t* caps,
+                        const lz_decode_cfg* cf, float* ms) -> int {
+    lz_batch* B = nullptr;
+    int r = lz_batch_create(cnt, hs, outs, caps, cf, d_scratch, scratch_cap, stream, &B);
+    if (r) return r;
+    *ms = 0;
+    r = lz_batch_launch(B, stream);
+    if (!r && hipEventRecord(e0, s) != hipSuccess) r = lz::fail(LZ_E_HIP, "event record failed");
+    for (uint32_t k = 0; k < reps && !r; ++k) r = lz_batch_launch(B, stream);
+    if (!r && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+               hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+      r = lz::fail(LZ_E_HIP, "event timing failed");
+    lz_batch_destroy(B);
+    *ms /= (float)reps;
+    return r;
+  };
   uint32_t nrep = 0;
   int rc = 0;
   for (int b = 0; b < 16 && rc == 0; ++b) {
@@ -2428,20 +2445,9 @@ extern "C" int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* cons
             for (uint64_t cap : C) too_big = too_big || cap > 0xFFFFFFFFull;
           if (too_big) continue;
           std::vector<lz_decode_cfg> cf(idx.size(), c);
-          lz_batch* B = nullptr;
-          rc = lz_batch_create((uint32_t)idx.size(), H.data(), O.data(), C.data(), cf.data(), d_scratch, scratch_cap,
-                               stream, &B);
-          if (rc) break;
           float ms = 0;
-          rc = lz_batch_launch(B, stream);
-          if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = lz::fail(LZ_E_HIP, "event record failed");
-          for (uint32_t r = 0; r < reps && !rc; ++r) rc = lz_batch_launch(B, stream);
-          if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                      hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            rc = lz::fail(LZ_E_HIP, "event timing failed");
-          lz_batch_destroy(B);
+          rc = time_batch((uint32_t)idx.size(), H.data(), O.data(), C.data(), cf.data(), &ms);
           if (rc) break;
-          ms /= (float)reps;
           if (G == 64 && U == 2 && S == 1 && M == 0) default_ms = ms;
           if (ms < best_ms) {
             best_ms = ms;
@@ -2461,6 +2467,21 @@ extern "C" int lz_autotune(uint32_t count, lz_dev* const* handles, uint8_t* cons
       R.default_ms = default_ms;
     }
     ++nrep;
+  }
+  // Buckets are tuned alone, but a batch with several configurations runs a
+  // launch sequence per configuration: keep the choices only if the whole
+  // batch is faster with them than with the default (when the scratch holds
+  // the batch with the choices)
+  if (rc == 0 && nrep > 1) {
+    std::vector<lz_decode_cfg> dflt(count, lz_decode_cfg{64, 2, 1, 0, 0, 0, 0, 0});
+    uint64_t need = 0;
+    if (lz_batch_scratch_bytes(count, handles, chosen, &need) == 0 && need <= scratch_cap) {
+      float t_chosen = 0, t_default = 0;
+      rc = time_batch(count, handles, d_out, out_cap, chosen, &t_chosen);
+      if (!rc) rc = time_batch(count, handles, d_out, out_cap, dflt.data(), &t_default);
+      if (!rc && t_default <= t_chosen)
+        for (uint32_t i = 0; i < count; ++i) chosen[i] = dflt[i];
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

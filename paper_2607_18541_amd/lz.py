@@ -558,7 +558,9 @@ def autotune(archives, outs, reps=3, stream=None):
     rc = lib().lz_batch_scratch_bytes(n, hs, None, ctypes.byref(sb))
     if rc:
         raise LzError(rc, "lz_batch_scratch_bytes")
-    scratch = torch.empty(max(sb.value, 256), dtype=torch.uint8, device=archives[0].buf.device)
+    # room for the whole batch with several configuration groups (their
+    # per-group tables), so the final whole-batch check can run
+    scratch = torch.empty(max(sb.value, 256) + (1 << 20), dtype=torch.uint8, device=archives[0].buf.device)
     op = _ptr_array([o.data_ptr() for o in outs])
     caps = np.array([o.numel() for o in outs], dtype=np.uint64)
     chosen = (DecodeCfg * max(n, 1))()
