@@ -280,7 +280,7 @@ int lz_entropy_decode_device(lz_dev* h, void* stream);
  * computes the token closure of each range (every token the range's bytes
  * depend on through match sources), lays it out in output order in device
  * scratch and orders its copies by dependency depth.  Closures cost host work
- * per byte, so once they exceed max(1 MiB, (E - H)/4096) bytes, E = the
+ * per byte, so once they exceed max(256 KiB, (E - H)/4096) bytes, E = the
  * largest range end, the plan instead decodes every token of [H, E) on the
  * device (parse segments and depth windows of that stretch) into scratch and
  * gathers the ranges from it.  H, the decode horizon, is the largest start of

@@ -89,7 +89,7 @@ constexpr uint64_t kSegTok = 256;    // tokens per parse segment
 constexpr uint32_t kWinBytes = 3072;  // a match window holds at most this many bytes ...
 constexpr uint32_t kWinMatches = 64;  // ... and at most this many matches
 constexpr uint32_t kLog2Grain = 20;  // and its matches lie in one aligned grain of max(2^20, block) bytes
-constexpr uint64_t kClosureMin = 1ull << 20;  // range closures of up to max(1 MiB, prefix / 4096) bytes;
+constexpr uint64_t kClosureMin = 256ull << 10;  // range closures of up to max(256 KiB, prefix / 4096) bytes;
 constexpr uint64_t kClosureRatio = 4096;      // beyond that the prefix is decoded instead
 constexpr uint64_t kGatherPiece = 8ull << 10;  // ranges are gathered into the output in pieces of this size,
                                                // one piece per group

@@ -112,17 +112,26 @@ def test_range_errors():
 
 def test_range_plan_modes():
     """A seek whose closure is small is served from its closure; one whose
-    closure would exceed max(1 MiB, end / 256) decodes its prefix on the
+    closure would exceed max(256 KiB, (end - horizon) / 4096) decodes its prefix on the
     device instead.  Both give the input's bytes."""
     dev = _dev()
     z = synth.zipf_text(8 << 20, seed=5)
     da = lz.DeviceArchive(lz.encode(z, 16, lz.TUNED_THR), device=dev)
     p = da.range_plan([100], [4096])
-    assert p.prefix_bytes == 0 and 0 < p.closure_bytes < (1 << 20)
+    assert p.prefix_bytes == 0 and 0 < p.closure_bytes < (256 << 10)
     p.free()
     da.close()
     x = synth.fastq(8 << 20, seed=5)
     da = lz.DeviceArchive(lz.encode(x, 16, lz.TUNED_THR), device=dev)
+    # a small range early in the file: a closure plan, whose bytes are the input's
+    p = da.range_plan([20_000], [3000])
+    assert p.prefix_bytes == 0 and 0 < p.closure_bytes < (256 << 10)
+    out = torch.zeros(3000, dtype=torch.uint8, device=dev)
+    scratch = torch.empty(p.scratch_bytes, dtype=torch.uint8, device=dev)
+    p.run(out, np.zeros(1, np.uint64), scratch)
+    torch.cuda.synchronize()
+    assert bytes(out.cpu().numpy()) == bytes(x[20_000:23_000])
+    p.free()
     p = da.range_plan([6 << 20, 1 << 20], [16 << 10, 1 << 20])
     assert p.closure_bytes == 0 and p.prefix_bytes == (6 << 20) + (16 << 10) - p.horizon
     assert p.horizon == horizon_by_definition(oracle.tokens(da.arc), 1 << 20, (6 << 20) + (16 << 10))
