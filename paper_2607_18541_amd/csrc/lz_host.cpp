@@ -308,12 +308,19 @@ struct HugeArray {
     p = nullptr;
     n = 0;
   }
-  static size_t bytes(size_t k) { return ((k * sizeof(T)) + (2u << 20) - 1) & ~size_t((2u << 20) - 1); }
+  // Large arrays are rounded to 2 MiB and asked for huge pages; small ones
+  // stay on 4 KiB pages, since the first touch of a huge page zeroes all of
+  // it (a fixed ~0.3 ms per array that dominated encodes of small inputs).
+  static constexpr size_t kHuge = 8u << 20;
+  static size_t bytes(size_t k) {
+    const size_t b = k * sizeof(T), a = b >= kHuge ? (2u << 20) : 4096;
+    return (b + a - 1) & ~(a - 1);
+  }
   void assign_zero(size_t k) {
     release();
     void* q = mmap(nullptr, bytes(k), PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
     if (q == MAP_FAILED) throw std::bad_alloc();
-    madvise(q, bytes(k), MADV_HUGEPAGE);
+    if (bytes(k) >= kHuge) madvise(q, bytes(k), MADV_HUGEPAGE);
     p = (T*)q;  // anonymous mappings start zeroed
     n = k;
   }
@@ -619,7 +626,7 @@ static int encode_impl(const uint8_t* in, uint64_t n, const lz_params* p, const 
   uint32_t kf = std::min<uint32_t>(std::min(tmin[2], tmin[3]), 16);
   std::vector<BlockEnc> blocks(nb);
   uint64_t seg = p->segment ? p->segment : std::max<uint64_t>(n, 1);
-  int bits = 16;
+  int bits = 10;
   while (bits < 28 && (1ull << bits) < std::min<uint64_t>(seg, n)) ++bits;
   unsigned idx_threads = threads;
   try {

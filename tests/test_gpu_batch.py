@@ -135,3 +135,42 @@ def test_autotune_choices_decode_exactly():
     for i, (d, x) in enumerate(zip(das, inputs)):
         assert np.array_equal(outs[i][:d.n].cpu().numpy(), x), i
     b.destroy()
+
+
+def test_batch_4096_archives():
+    """The batched workload's archive count (4096) in one batch graph with the
+    default configuration, half Zipf text and half FASTQ-like, the two
+    threshold tuples alternating: 4094 archives log-uniform 4 KiB - 256 KiB
+    plus two at the distribution's largest size, 16 MiB (the full 7.5 GiB
+    mix is checked byte for byte by the batch benchmark).  Every output
+    equals its input, and 64 sampled archives equal the oracle's decode."""
+    from concurrent.futures import ThreadPoolExecutor
+    dev = _dev()
+    k = 4096
+    sizes = [int(s) for s in synth.loguniform(k - 2, 4096, 256 << 10, 4)] + [16 << 20, 16 << 20]
+
+    def make(i):
+        sz = sizes[i]
+        x = synth.zipf_text(sz, seed=4000 + i) if i % 2 == 0 else synth.fastq(sz, seed=4000 + i)
+        return x, lz.encode(x, 16, (lz.BASE_THR, lz.TUNED_THR)[(i // 2) % 2])
+
+    with ThreadPoolExecutor(8) as pool:  # the encoder's ctypes calls release the GIL
+        made = list(pool.map(make, range(k)))
+    print("encoded %d archives, %d bytes" % (k, sum(x.size for x, _ in made)), flush=True)
+    inputs = [x for x, _ in made]
+    arcs = [a for _, a in made]
+    das = [lz.DeviceArchive(a, device=dev) for a in arcs]
+    outs = [torch.empty(max(d.n, 1), dtype=torch.uint8, device=dev) for d in das]
+    b = lz.Batch(das, outs, None)
+    b.launch()
+    torch.cuda.synchronize()
+    print("batch decoded", flush=True)
+    for i, (d, x) in enumerate(zip(das, inputs)):
+        assert d.n == x.size, i
+        assert torch.equal(outs[i][:d.n], torch.from_numpy(x).to(dev)), i
+    rng = np.random.default_rng(11)
+    for i in list(rng.choice(k - 2, 62, replace=False)) + [k - 2, k - 1]:
+        assert np.array_equal(outs[i][:das[i].n].cpu().numpy(), oracle.decode(arcs[i])), int(i)
+    b.destroy()
+    for d in das:
+        d.close()
