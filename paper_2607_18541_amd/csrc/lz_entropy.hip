@@ -1,20 +1,19 @@
 // lz_entropy.hip -- gfx950 decoder of the tile-rANS entropy stage.
 //
-// One wave64 per tile (Sec. 2: entropy decoded over 64 KB tiles by many
-// cooperating groups, tiles cut independently of the LZ blocks); the tile's
-// 64 interleaved rANS states live one per lane, so a step decodes 64
-// consecutive symbols.  Steps run in blocks of 8: a block's 512 symbols are
-// staged in LDS and written by one coalesced store at the start of the next
-// block, right after the word ring advances, so the ring's wait (stores and
-// loads share one counter on this GPU) finds that store a block old.  Per wave, LDS
-// holds the slot -> symbol table (4096 bytes), the frequencies and cumulative
-// frequencies (256 + 256 u16) and a ring of 2 x 1024 words of the tile's word
-// stream, refilled a chunk at a time, so a renormalisation reads LDS.  The
-// lanes that need a word in a step take consecutive words in lane order
-// (ballot + popcount of the lower lanes).  Raw tiles are copied and repeated-
-// byte tiles filled.  Every bound was checked on the host; a word read past
-// the payload (possible only on a corrupt stream that passed those checks)
-// sets an error bit and stops the tile.
+// One wave64 per tile, one tile per workgroup (Sec. 2: entropy decoded over
+// 64 KB tiles by many cooperating groups, tiles cut independently of the LZ
+// blocks); the tile's 64 interleaved rANS states live one per lane, so a
+// step decodes 64 consecutive symbols and stores them with one byte store of
+// the wave.  Per wave, LDS holds the slot -> symbol table (4096 bytes), the
+// frequencies and cumulative frequencies (256 + 256 u16) and a ring of
+// 2 x 512 words of the tile's word stream, refilled a chunk at a time every
+// block of 8 steps at most, so a renormalisation reads LDS; 7 KiB a tile
+// lets 22 tiles share a CU.  The lanes that need a word in a step take
+// consecutive words in lane order (ballot + popcount of the lower lanes).
+// Raw tiles are copied and repeated-byte tiles filled.  Every bound was
+// checked on the host; a word read past the payload (possible only on a
+// corrupt stream that passed those checks) sets an error bit and stops the
+// tile.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -33,15 +32,14 @@ __device__ __forceinline__ T gld(const uint8_t* p) {
 }
 __device__ __forceinline__ void gst8(uint8_t* p, uint8_t v) { *(LZ_G uint8_t*)(p) = v; }
 
-constexpr int kWaves = 4;  // tiles per workgroup
-constexpr uint32_t kRing = 1024, kChunk = 512;  // word ring: two chunks of 512 words
-constexpr uint32_t kBlock = 8;                  // steps between ring advances and output stores
-
+// BLOCK steps run between ring advances and output stores; a block reads
+// at most 64 BLOCK words, so the ring holds two chunks of that many words.
+template <int BLOCK>
 struct alignas(16) WaveLds {
+  static constexpr uint32_t kChunk = 64u * BLOCK, kRing = 2u * kChunk;
   uint8_t sym[lz::kRansM];
   uint32_t fc[256];  // f | c << 16
   uint16_t ring[kRing];
-  uint8_t outb[kBlock * 64];  // one block's decoded symbols, in order
 };
 
 __device__ __forceinline__ uint32_t ld_u32_unaligned(const uint8_t* p) {
@@ -50,31 +48,57 @@ __device__ __forceinline__ uint32_t ld_u32_unaligned(const uint8_t* p) {
 }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4_a1 __attribute__((ext_vector_type(4), aligned(1)));
-typedef unsigned long long uint64_a1 __attribute__((aligned(1)));
+typedef unsigned int u32x2_a1 __attribute__((ext_vector_type(2), aligned(1)));
 
-// Chunk k of the word stream (words [512 k, 512 k + 512), n words in all):
-// lane j holds words 8 j .. 8 j + 7 of it (16 bytes); past the end, zeros.
-// The load is issued a block before its bytes are written to the ring.
-__device__ __forceinline__ u32x4 fetch_chunk(const uint8_t* words, uint64_t n, uint64_t k, int lane) {
-  const uint64_t w0 = k * kChunk + 8 * (uint64_t)lane;
-  if (w0 + 8 <= n) return *(const LZ_G u32x4_a1*)(words + 2 * w0);
-  uint32_t d[4] = {0u, 0u, 0u, 0u};
+// A ring chunk gives each lane BLOCK words (2 BLOCK bytes).
+template <int BLOCK> struct Piece;
+template <> struct Piece<8> {
+  typedef u32x4 chunk_t;
+  typedef u32x4_a1 chunk_a1;
+};
+template <> struct Piece<4> {
+  typedef u32x2 chunk_t;
+  typedef u32x2_a1 chunk_a1;
+};
+
+// Chunk k of the word stream (words [64 BLOCK k, 64 BLOCK (k + 1)), n words
+// in all): lane j holds words BLOCK j .. BLOCK j + BLOCK - 1 of it; past the
+// end, zeros.  The load is issued a block before its bytes are written to
+// the ring.
+template <int BLOCK>
+__device__ __forceinline__ typename Piece<BLOCK>::chunk_t fetch_chunk(const uint8_t* words, uint64_t n, uint64_t k,
+                                                                      int lane) {
+  typedef typename Piece<BLOCK>::chunk_t C;
+  const uint64_t w0 = k * (64u * BLOCK) + BLOCK * (uint64_t)lane;
+  if (w0 + BLOCK <= n) return *(const LZ_G typename Piece<BLOCK>::chunk_a1*)(words + 2 * w0);
+  uint32_t d[BLOCK / 2] = {};
   for (uint64_t q = 0; w0 < n && q < 2 * (n - w0); ++q) d[q >> 2] |= (uint32_t)gld<uint8_t>(words + 2 * w0 + q) << (8 * (q & 3));
-  return u32x4{d[0], d[1], d[2], d[3]};
+  C v;
+#pragma unroll
+  for (int i = 0; i < BLOCK / 2; ++i) v[i] = d[i];
+  return v;
 }
 
-__device__ __forceinline__ void put_chunk(WaveLds& L, uint64_t k, u32x4 v, int lane) {
-  ((u32x4*)(L.ring + (k & 1) * kChunk))[lane] = v;
+template <int BLOCK>
+__device__ __forceinline__ void put_chunk(WaveLds<BLOCK>& L, uint64_t k, typename Piece<BLOCK>::chunk_t v, int lane) {
+  ((typename Piece<BLOCK>::chunk_t*)(L.ring + (k & 1) * WaveLds<BLOCK>::kChunk))[lane] = v;
 }
 
-__global__ __launch_bounds__(64 * kWaves) void k_entropy(const uint8_t* coded, uint64_t payload_off, uint64_t n_tiles,
-                                                         uint8_t* out, uint32_t* err) {
-  __shared__ WaveLds lds[kWaves];
+// tiles per workgroup and steps per block of the launched kernel
+constexpr int kEntWaves = 1, kEntBlock = 8;
+
+template <int WAVES, int BLOCK>
+__global__ __launch_bounds__(64 * WAVES) void k_entropy(const uint8_t* coded, uint64_t payload_off, uint64_t n_tiles,
+                                                        uint8_t* out, uint32_t* err) {
+  typedef WaveLds<BLOCK> Lds;
+  constexpr uint32_t kBlock = BLOCK, kChunk = Lds::kChunk, kRing = Lds::kRing;
+  __shared__ Lds lds[WAVES];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  WaveLds& L = lds[wv];
-  const uint64_t nwaves = (uint64_t)gridDim.x * kWaves;
-  for (uint64_t t = (uint64_t)blockIdx.x * kWaves + wv; t < n_tiles; t += nwaves) {
+  Lds& L = lds[wv];
+  const uint64_t nwaves = (uint64_t)gridDim.x * WAVES;
+  for (uint64_t t = (uint64_t)blockIdx.x * WAVES + wv; t < n_tiles; t += nwaves) {
     const uint8_t* r = coded + lz::kCodedHead + 32 * t;  // directory record
     const uint64_t po = __builtin_amdgcn_readfirstlane(ld_u32_unaligned(r)) |
                         ((uint64_t)__builtin_amdgcn_readfirstlane(ld_u32_unaligned(r + 4)) << 32);
@@ -184,9 +208,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_entropy(const uint8_t* coded, u
     uint32_t x = ld_u32_unaligned(st + 4 * lane);
     const uint8_t* words = st + 4 * lz::kRansLanes;
     const uint64_t nwords = (pb - (32 + 2 * nsym + 4 * lz::kRansLanes)) / 2;
-    put_chunk(L, 0, fetch_chunk(words, nwords, 0, lane), lane);
-    put_chunk(L, 1, fetch_chunk(words, nwords, 1, lane), lane);
-    u32x4 ahead = fetch_chunk(words, nwords, 2, lane);  // in flight until the ring next advances
+    put_chunk(L, 0, fetch_chunk<BLOCK>(words, nwords, 0, lane), lane);
+    put_chunk(L, 1, fetch_chunk<BLOCK>(words, nwords, 1, lane), lane);
+    auto ahead = fetch_chunk<BLOCK>(words, nwords, 2, lane);  // in flight until the ring next advances
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     uint32_t wpos = 0, chunk = 0;
@@ -211,50 +235,35 @@ __global__ __launch_bounds__(64 * kWaves) void k_entropy(const uint8_t* coded, u
       wpos += (uint32_t)__builtin_popcountll(m);
       return sv;
     };
-    // symbols [i0, i0 + 512) of the last block, from LDS to the output:
-    // lane j writes symbols i0 + 8 j .. + 7 (one 8-byte store when they are
-    // consecutive in the output and all present)
-    auto flush = [&](uint32_t i0) {
-      const uint32_t a = i0 + 8 * (uint32_t)lane;
-      const uint64_t v = ((const uint64_t*)L.outb)[lane];
-      if (stride == 1 && a + 8 <= cnt) {
-        *(LZ_G uint64_a1*)(o + a) = v;
-      } else {
-        for (uint32_t u = 0; u < 8 && a + u < cnt; ++u) gst8(o + (uint64_t)(a + u) * stride, (uint8_t)(v >> (8 * u)));
-      }
-    };
     const uint32_t steps = (cnt + 63) / 64;
     for (uint32_t k0 = 0; k0 < steps; k0 += kBlock) {
-      // a block reads at most 512 words: the ring (chunks `chunk`, +1) covers
-      // it after at most one advance; `ahead` was loaded a block ago, and the
-      // last output store was issued a block ago too
-      if ((wpos >> 9) > chunk) {
+      // a block reads at most kChunk words: the ring (chunks `chunk`, +1)
+      // covers it after at most one advance; `ahead` was loaded at least a
+      // block ago
+      if (wpos / kChunk > chunk) {
         __builtin_amdgcn_wave_barrier();
         ++chunk;
         put_chunk(L, chunk + 1, ahead, lane);
-        ahead = fetch_chunk(words, nwords, chunk + 2, lane);
+        ahead = fetch_chunk<BLOCK>(words, nwords, chunk + 2, lane);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
       }
-      if (k0) {
-        flush((k0 - kBlock) * 64);
-        __builtin_amdgcn_wave_barrier();  // outb is rewritten below
-      }
+      // every step stores its 64 symbols, consecutive in the output for
+      // stride-1 tiles (one 64-byte store of the wave)
       if (k0 + kBlock < steps) {  // a whole block of full steps (not the last step)
 #pragma unroll
-        for (int u = 0; u < (int)kBlock; ++u) L.outb[u * 64 + lane] = (uint8_t)step(true);
+        for (int u = 0; u < (int)kBlock; ++u)
+          gst8(o + (uint64_t)((k0 + u) * 64 + lane) * stride, (uint8_t)step(true));
       } else {
 #pragma unroll
         for (int u = 0; u < (int)kBlock; ++u) {
           if (k0 + u >= steps) break;
           const uint32_t i = (k0 + u) * 64 + lane;
-          L.outb[u * 64 + lane] = (uint8_t)step(i < cnt);
+          const uint8_t v = (uint8_t)step(i < cnt);
+          if (i < cnt) gst8(o + (uint64_t)i * stride, v);
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
     }
-    if (steps) flush((steps - 1) / kBlock * kBlock * 64);
     // words past the stream read as zero, so a corrupt stream decodes to
     // garbage but stays in bounds; it is caught here: every word consumed,
     // and every state back at the encoder's start (2^16)
@@ -273,13 +282,13 @@ int entropy_launch(const uint8_t* d_coded, uint64_t payload_off, uint64_t n_tile
                    int cu_count, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   if (n_tiles == 0) return 0;
+  constexpr int W = kEntWaves;
+  const void* k = (const void*)k_entropy<kEntWaves, kEntBlock>;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_entropy, 64 * kWaves, 0) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  const uint64_t groups = std::min<uint64_t>((n_tiles + kWaves - 1) / kWaves, (uint64_t)per_cu * std::max(cu_count, 1));
-  hipLaunchKernelGGL(k_entropy, dim3((unsigned)groups), dim3(64 * kWaves), 0, s, d_coded, payload_off, n_tiles, d_out,
-                     d_err);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * W, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  const uint64_t groups = std::min<uint64_t>((n_tiles + W - 1) / W, (uint64_t)per_cu * std::max(cu_count, 1));
+  hipLaunchKernelGGL((k_entropy<kEntWaves, kEntBlock>), dim3((unsigned)groups), dim3(64 * W), 0, s, d_coded,
+                     payload_off, n_tiles, d_out, d_err);
   if (hipGetLastError() != hipSuccess) return fail(LZ_E_HIP, "entropy launch failed");
   return 0;
 }
