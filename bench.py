@@ -302,6 +302,32 @@ def achieved_all(t):
     return t["alg_bytes"] / (t["mean_ms"] * 1e-3) / 1e9
 
 
+def capped_point(args, torch, lz, x, cap):
+    """12/16/24/32 encoded with the encoder's depth cap: the matches that would
+    lie deeper than `cap` become literals; decode time, depths and both ratios,
+    the output checked equal to the input."""
+    dev = torch.device("cuda:0")
+    n = int(x.size)
+    log("encoding 12/16/24/32 with depth cap %d" % cap)
+    arc = lz.encode(x, args.log2_bs, lz.TUNED_THR, lz.BOUNDS_CFG, max_chain=args.max_chain,
+                    depth_passes=args.depth_passes, depth_cap=cap)
+    ent, _ = lz.entropy_size(arc)
+    info = lz.archive_info(arc)
+    da = lz.DeviceArchive(arc, device=dev)
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    mean_ms, _, _ = time_decode(torch, da, out, args.G, args.unroll, args.schedule, args.warmup, args.steps)
+    if not bool(torch.equal(out, torch.from_numpy(x).to(dev))):
+        raise SystemExit("depth cap %d: GPU decode differs from the input" % cap)
+    pt = {"depth_cap": cap, "depths": da.levels, "ms": round(mean_ms, 4), "gbps": round(n / mean_ms / 1e6, 3),
+          "ratio_raw": round(n / arc.size, 4), "ratio_entropy": round(n / ent, 4),
+          "coverage": round(info["coverage"], 4), "bit_exact": True}
+    log("depth cap point: %s" % json.dumps(pt))
+    da.close()
+    del out
+    torch.cuda.empty_cache()
+    return pt
+
+
 def run_fastq(args, torch, lz):
     import synth
     dev = torch.device("cuda:0")
@@ -357,6 +383,7 @@ def run_fastq(args, torch, lz):
         da.close()
         del out
         torch.cuda.empty_cache()
+    cap_pt = capped_point(args, torch, lz, x, 16)
     t = res["tuned"]
     b = res["base"]
     # the two kernels of a decode and their algorithmic bytes: the parse launch
@@ -406,6 +433,7 @@ def run_fastq(args, torch, lz):
             "bit_exact": True, **gen,
             "tuned_G32": {"G": 32, "ms": round(t["g32_ms"], 4), "gbps": round(n / t["g32_ms"] / 1e6, 3)}
             if t["g32_ms"] else None,
+            "tuned_depth_cap16": cap_pt,
             # everything resident on the device per archive: the archive, the
             # depth plan and parse segments computed at open, and the match table
             "residency": {k: {"archive_bytes": int(res[k]["arc"].size), "device_bytes": int(res[k]["device_bytes"]),
@@ -849,7 +877,8 @@ PAPER_BANDS = (128, 16384, 2097152)
 def run_ablate(args, torch, lz):
     """Threshold and distance-band variants and schedule mechanisms on the
     FASTQ-like workload: the tuple the paper rejects (16/24/32/48), the paper's
-    own distance bands with both headline tuples, and, on 12/16/24/32, the
+    own distance bands with both headline tuples, the encoder's depth cap
+    (6/8/10/12 at 64, 12/16/24/32 at 16 and 12), and, on 12/16/24/32, the
     decode without the one-workgroup tail, with G = 32, with schedule 0, and
     with the depth passes held to 6, 4 and 3 resident workgroups per CU (of
     8; the occupancy control of Sec. 3.3)."""
@@ -859,19 +888,25 @@ def run_ablate(args, torch, lz):
     n = int(x.size)
     xt = torch.from_numpy(x).to(dev)
     rows = []
-    variants = [("6/8/10/12", lz.BASE_THR, lz.BOUNDS_CFG, "cfg"), ("12/16/24/32", lz.TUNED_THR, lz.BOUNDS_CFG, "cfg"),
-                ("16/24/32/48", (16, 24, 32, 48), lz.BOUNDS_CFG, "cfg"),
-                ("6/8/10/12", lz.BASE_THR, PAPER_BANDS, "paper"), ("12/16/24/32", lz.TUNED_THR, PAPER_BANDS, "paper")]
+    variants = [("6/8/10/12", lz.BASE_THR, lz.BOUNDS_CFG, "cfg", 0),
+                ("12/16/24/32", lz.TUNED_THR, lz.BOUNDS_CFG, "cfg", 0),
+                ("16/24/32/48", (16, 24, 32, 48), lz.BOUNDS_CFG, "cfg", 0),
+                ("6/8/10/12", lz.BASE_THR, PAPER_BANDS, "paper", 0),
+                ("12/16/24/32", lz.TUNED_THR, PAPER_BANDS, "paper", 0),
+                ("6/8/10/12", lz.BASE_THR, lz.BOUNDS_CFG, "cfg", 64),
+                ("12/16/24/32", lz.TUNED_THR, lz.BOUNDS_CFG, "cfg", 16),
+                ("12/16/24/32", lz.TUNED_THR, lz.BOUNDS_CFG, "cfg", 12)]
     tuned_gbps = None
-    for name, thr, bounds, bname in variants:
-        log("encoding %s, %s bands" % (name, bname))
-        arc = lz.encode(x, args.log2_bs, thr, bounds, max_chain=args.max_chain, depth_passes=args.depth_passes)
+    for name, thr, bounds, bname, cap in variants:
+        log("encoding %s, %s bands, depth cap %d" % (name, bname, cap))
+        arc = lz.encode(x, args.log2_bs, thr, bounds, max_chain=args.max_chain, depth_passes=args.depth_passes,
+                        depth_cap=cap)
         info = lz.archive_info(arc)
         ent, _ = lz.entropy_size(arc)
         da = lz.DeviceArchive(arc, device=dev)
         out = torch.empty(n, dtype=torch.uint8, device=dev)
         mechs = [("G64 U2 schedule 1", 64, 2, 1, 0, 0)]
-        if name == "12/16/24/32" and bname == "cfg":
+        if name == "12/16/24/32" and bname == "cfg" and not cap:
             mechs += [("no tail", 64, 2, 1, lz.TAIL_OFF, 0), ("G32", 32, 2, 1, 0, 0), ("schedule 0", 64, 2, 0, 0, 0)]
             mechs += [("occupancy %d of 8" % k, 64, 2, 1, 0, k) for k in (6, 4, 3)]
         for mname, G, U, S, T, O in mechs:
@@ -889,13 +924,13 @@ def run_ablate(args, torch, lz):
             e1.synchronize()
             da.check()
             ms = e0.elapsed_time(e1) / steps
-            row = {"thr": name, "bands": bname, "mechanism": mname, "ms": round(ms, 4),
+            row = {"thr": name, "bands": bname, "depth_cap": cap, "mechanism": mname, "ms": round(ms, 4),
                    "gbps": round(n / ms / 1e6, 2), "depths": da.levels, "ratio_raw": round(n / arc.size, 4),
                    "ratio_entropy": round(n / ent, 4), "mean_match": round(info["mean_match"], 2),
                    "coverage": round(info["coverage"], 4)}
             log(json.dumps(row))
             rows.append(row)
-            if name == "12/16/24/32" and bname == "cfg" and mname.startswith("G64"):
+            if name == "12/16/24/32" and bname == "cfg" and not cap and mname.startswith("G64"):
                 tuned_gbps = row["gbps"]
         da.close()
         del out

@@ -88,6 +88,12 @@ typedef struct lz_params {
    * lz_encode_learned does with an in-memory selector. */
   uint32_t mode;
   const char* mlp_path;
+  /* Depth cap (an encode-side lever in the spirit of Sec. 4: fewer
+   * dependency depths, fewer decode passes): 0 = none; k = 1..65534: after
+   * the parse, a walk in output order turns every match whose dependency
+   * depth (as in lz_plan) would exceed k into literal bytes, so the archive
+   * has at most k depths.  Costs ratio where it acts. */
+  uint32_t depth_cap;
 } lz_params;
 
 /* Fills the defaults: 64 KiB blocks, thresholds 6/8/10/12, bounds 4 KiB /

@@ -589,6 +589,57 @@ static void parse_block(const EncCtx& c, uint64_t b, std::vector<BTok>& toks, st
   if (run) toks.push_back(BTok{run, 0, 0});
 }
 
+// Depth cap: walks the tokens of blocks [b0, b1) of a segment (input x =
+// the segment's first byte, segment-relative positions; token sources are
+// absolute, the segment starts at s0) in output order with the dependency
+// depth of every byte (literal bytes 0, a match 1 + the deepest byte it reads,
+// its own output excluded, as in compute_levels) and turns every match whose
+// depth would exceed `cap` into literal bytes, merged into the next token's
+// run.  Depths only fall when a match becomes literals, so the walk is exact:
+// the archive's deepest match ends at depth <= cap.  Blocks whose tokens
+// changed get their literal stream rebuilt from the input.
+static void cap_depths(const uint8_t* x, uint64_t s0, uint64_t b0, uint64_t b1, uint64_t bs, uint32_t cap,
+                       std::vector<BlockEnc>& blocks, uint16_t* dep) {
+  for (uint64_t i = 0; i < b1 - b0; ++i) {
+    BlockEnc& e = blocks[b0 + i];
+    const BTok* tk = (const BTok*)e.slo.data();
+    const size_t nt = e.slo.size() / sizeof(BTok);
+    std::vector<BTok> out;
+    out.reserve(nt);
+    bool changed = false;
+    uint64_t q = i * bs, acc = 0;
+    for (size_t j = 0; j < nt; ++j) {
+      std::fill(dep + q, dep + q + tk[j].lit_len, (uint16_t)0);
+      q += tk[j].lit_len;
+      acc += tk[j].lit_len;
+      if (!tk[j].mlen) continue;
+      const uint64_t a = tk[j].src - s0, z = std::min(a + tk[j].mlen, q);
+      uint32_t m = 0;
+      for (uint64_t r = a; r < z; ++r) m = std::max<uint32_t>(m, dep[r]);
+      if (m + 1 > cap) {
+        std::fill(dep + q, dep + q + tk[j].mlen, (uint16_t)0);
+        acc += tk[j].mlen;
+        changed = true;
+      } else {
+        std::fill(dep + q, dep + q + tk[j].mlen, (uint16_t)(m + 1));
+        out.push_back(BTok{acc, tk[j].mlen, tk[j].src});
+        acc = 0;
+      }
+      q += tk[j].mlen;
+    }
+    if (!changed) continue;
+    if (acc) out.push_back(BTok{acc, 0, 0});
+    e.lit.clear();
+    uint64_t r = i * bs;
+    for (const BTok& t : out) {
+      e.lit.insert(e.lit.end(), x + r, x + r + t.lit_len);
+      r += t.lit_len + t.mlen;
+    }
+    e.slo.resize(out.size() * sizeof(BTok));
+    memcpy(e.slo.data(), out.data(), out.size() * sizeof(BTok));
+  }
+}
+
 static int check_params(const lz_params* p, uint64_t n) {
   if (!p) return fail(LZ_E_INVAL, "null params");
   if (p->log2_bs < 4 || p->log2_bs > 24) return fail(LZ_E_INVAL, "log2_bs must be in [4,24]");
@@ -601,6 +652,7 @@ static int check_params(const lz_params* p, uint64_t n) {
   if (p->segment > 0xFFFFFFFFull - 16) return fail(LZ_E_INVAL, "segment must be below 4 GiB");
   if (!p->segment && n > 0xFFFFFFFFull - 16) return fail(LZ_E_INVAL, "inputs of 4 GiB or more need a segment");
   if (p->depth_passes > 8) return fail(LZ_E_INVAL, "depth_passes must be at most 8");
+  if (p->depth_cap >= kDepthMax) return fail(LZ_E_INVAL, "depth_cap must be below 65535");
   return 0;
 }
 
@@ -679,6 +731,10 @@ static int encode_impl(const uint8_t* in, uint64_t n, const lz_params* p, const 
           e.slo.resize(toks.size() * sizeof(BTok));
           memcpy(e.slo.data(), toks.data(), toks.size() * sizeof(BTok));
         });
+      }
+      if (p->depth_cap) {
+        if (!dep.p) dep.assign_zero(s1 - s0);
+        cap_depths(c.x, s0, b0, b1, bs, p->depth_cap, blocks, dep.p);
       }
       if (p->progress) p->progress(s1, n, p->progress_user);
     }

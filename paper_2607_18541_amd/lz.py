@@ -39,7 +39,7 @@ PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_
 class Params(ctypes.Structure):
     _fields_ = [("log2_bs", _u32), ("thr", _u32 * 4), ("bound", _u64 * 3), ("max_chain", _u32),
                 ("n_threads", _u32), ("segment", _u64), ("progress", PROGRESS_FN), ("progress_user", ctypes.c_void_p),
-                ("depth_passes", _u32), ("mode", _u32), ("mlp_path", ctypes.c_char_p)]
+                ("depth_passes", _u32), ("mode", _u32), ("mlp_path", ctypes.c_char_p), ("depth_cap", _u32)]
 
 
 class Info(ctypes.Structure):
@@ -181,7 +181,8 @@ def default_threads():
     return min(os.cpu_count() or 1, 16)
 
 
-def params(log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0, depth_passes=1):
+def params(log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0, depth_passes=1,
+           depth_cap=0):
     if not n_threads:
         n_threads = default_threads()
     p = Params()
@@ -195,19 +196,21 @@ def params(log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=
     p.n_threads = n_threads
     p.segment = segment
     p.depth_passes = depth_passes
+    p.depth_cap = depth_cap
     return p
 
 
 def encode(x, log2_bs=16, thr=BASE_THR, bounds=BOUNDS_CFG, max_chain=32, n_threads=0, segment=0, progress=None,
-           depth_passes=1, mlp_path=None):
+           depth_passes=1, mlp_path=None, depth_cap=0):
     """Greedy parse with per-distance-class thresholds into a container.
     progress(done, total), if given, is called after each segment;
     depth_passes (default 1) re-parses that many times breaking length ties
     by the lowest resulting dependency depth (0: nearest source); mlp_path,
     if given, selects learned mode: each block's tuple comes from the
-    selector saved there (thr is then unused)."""
+    selector saved there (thr is then unused); depth_cap k > 0 turns the
+    matches that would lie deeper than k into literals."""
     x = _u8(x)
-    p = params(log2_bs, thr, bounds, max_chain, n_threads, segment, depth_passes)
+    p = params(log2_bs, thr, bounds, max_chain, n_threads, segment, depth_passes, depth_cap)
     if mlp_path is not None:
         path = os.fsencode(mlp_path)
         p.mode = 1

@@ -301,3 +301,19 @@ def test_occupancy_control_decodes_exactly():
             da.decode(occupancy=bad)
         assert e.value.rc == lz.LZ_E_INVAL
     da.close()
+
+
+@pytest.mark.parametrize("cap", [1, 3, 8])
+def test_depth_capped_archives(cap):
+    """Archives encoded with a depth cap decode exactly, and the device plan
+    has the oracle's depth count (at most the cap)."""
+    x = synth.zipf_text(3 << 20, seed=2)
+    arc = lz.encode(x, 14, lz.BASE_THR, depth_cap=cap)
+    expect = oracle.decode(arc)
+    assert np.array_equal(expect, x)
+    _, d = oracle.levels(arc)
+    assert d <= cap
+    da = lz.DeviceArchive(arc, device=_dev())
+    assert da.levels == d, (da.levels, d)
+    da.close()
+    _check(arc, expect, SOME, f"cap{cap}")
