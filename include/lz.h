@@ -237,6 +237,14 @@ int lz_device_check(lz_dev* h, void* stream);
 
 uint64_t lz_device_n(const lz_dev* h);
 uint32_t lz_device_levels(const lz_dev* h); /* number of match depths (launches of schedule 1) */
+/* Number of matches the parse copies itself (the match phase of Sec. 2; a match
+ * whose source bytes are all literals has no dependency on other matches).
+ * A depth-1 match whose source lies inside one token's literal run and ends
+ * before its own output starts is read from the literal stream at an offset
+ * the plan computes at open; it takes no window of the depth passes.  Returns
+ * their count (0 when the archive has none, or h is null) and, when `bytes`
+ * is not null, stores their total length there. */
+uint64_t lz_device_fused(const lz_dev* h, uint64_t* bytes);
 void lz_device_close(lz_dev* h);
 
 /* ------------------------------------------------------------ entropy stage */

@@ -111,7 +111,8 @@ struct ArcDesc {
   const uint8_t* lit;
   uintptr_t lit_lo, lit_hi;  // readable bounds for literal windows
   uint64_t n;
-  uint32_t log2_bs, nb, min_match, pad;
+  uint32_t log2_bs, nb, min_match;
+  uint32_t n_fused;  // match-table slots below this are copied by the parse from the literal stream
   uint8_t* out;
   const uint8_t* msrc;  // base that match sources index (out, or ref in mode 2)
   uintptr_t msrc_lo, msrc_hi;
@@ -520,6 +521,8 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
   uint64_t t_next = 0, t_end = 0, blk_t_end = 0, pos = 0, bend = 0, litc = 0, xc = 0, yc = 0;
   uint64_t sp0 = 0, sp1 = 0;  // parse: output span of the current G tokens
   bool span_mode = false;     // parse: the span is written whole (dense literals)
+  bool span_drain = false;    // parse: a span write precedes this pass's match stores
+  u32x4 f_rec = u32x4{0u, 0u, 0u, 0u};  // parse: record of this lane's literal-sourced match
   // this lane's buffered token
   uint64_t l_dst = 0, l_src = 0, m_dst = 0, m_src = 0;
   uint32_t l_len = 0, m_len = 0, m_done = 0;
@@ -729,16 +732,26 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
             // whole-span blocks pay when literals fill a good part of the span;
             // sparse literal runs are copied run by run
             span_mode = 4 * lit_tot >= sp1 - sp0;
-            // record the match in plan order; only literal runs are copied here
+            // record the match in plan order; a literal-sourced match (slot
+            // below n_fused) is copied here instead, from the literal-stream
+            // offset its resident record holds
+            m_len = 0;
             if (valid && mlen > 0) {
               const uint64_t md = tdst + lit_len;
-              gst(D.mtab, sl, u32x4{(uint32_t)md, mlen, (uint32_t)src,
-                                    (uint32_t)((md >> 32) & 0xFFFFu) | (uint32_t)((src >> 32) << 16)});
+              if (sl < D.n_fused) {
+                // its record is checked when the copy needs it, so the load
+                // completes under the span write
+                f_rec = gld((const u32x4*)D.mtab, sl);
+                m_dst = md;
+                m_len = mlen;
+              } else {
+                gst(D.mtab, sl, u32x4{(uint32_t)md, mlen, (uint32_t)src,
+                                      (uint32_t)((md >> 32) & 0xFFFFu) | (uint32_t)((src >> 32) << 16)});
+              }
             }
             l_dst = tdst;
             l_len = lit_len;
             l_src = loff;
-            m_len = 0;
           } else {
             // a window's matches from the match table
             const u32x4 rr = gld((const u32x4*)D.mtab, tc);
@@ -761,18 +774,33 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
           l_pend = (MODE == kModeParse && span_mode) ? (sp1 > sp0) : (l_len > 0);
           progressed = true;
         }
-      } else if (MODE == kModeParse && span_mode) {
+      } else if (MODE == kModeParse && span_mode && group_bits<G>(__ballot(l_pend), gw) != 0) {
         // ------------------------------------------------ the span's aligned 16-byte blocks
         parse_span<G, kSpanUnroll>(sp0, sp1, l_dst, l_len, (uintptr_t)D.lit + l_src, D.lit_lo, D.lit_hi, out_b, gl, gslot,
                          s_base, s_desc);
         l_pend = false;
+        // literal-sourced matches then rewrite their bytes of that span: the
+        // copy's first stores wait until the span's stores have completed
+        span_drain = group_bits<G>(__ballot(m_rem > 0), gw) != 0;
         progressed = true;
       } else {
         // ------------------------------------------------ one pass over every pending segment
         // Matches of one level never read each other's output, so every lane
         // copies at once; a self-overlapping match (period d < length) writes
         // pieces d, 2d, 4d, ... each read from the already final prefix.
-        const uint32_t piece = m_rem ? (uint32_t)min<uint64_t>(m_rem, (m_dst - m_src) + m_done) : 0u;
+        // (the parse's matches read the literal stream at their record's
+        // offset and are copied whole)
+        if (MODE == kModeParse && m_rem) {
+          m_src = (uint64_t)f_rec.z | ((uint64_t)(f_rec.w >> 16) << 32);
+          if (f_rec.x != (uint32_t)m_dst || f_rec.y != m_len ||
+              (f_rec.w & 0xFFFFu) != (uint32_t)((m_dst >> 32) & 0xFFFFu) ||
+              (uintptr_t)D.lit + m_src + m_len > D.lit_hi) {
+            m_len = m_done;  // not this archive's record: skipped
+            atomicOr(A.err, 4u);
+          }
+        }
+        const uint32_t piece = (MODE == kModeParse) ? m_len - m_done
+                               : m_rem ? (uint32_t)min<uint64_t>(m_rem, (m_dst - m_src) + m_done) : 0u;
         const bool inc_l = l_pend;
         const bool inc_m = piece > 0;
         const uintptr_t a_dst = out_b + l_dst;
@@ -788,7 +816,8 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
         d.b_dst = b_dst;
         // a periodic match copies each piece from the start of its period; any
         // other match (or the part of it this window starts at) from src + done
-        d.b_src = (uintptr_t)D.msrc + m_src + ((m_dst - m_src < m_len) ? 0u : m_done);
+        d.b_src = (MODE == kModeParse) ? (uintptr_t)D.lit + m_src + m_done
+                                       : (uintptr_t)D.msrc + m_src + ((m_dst - m_src < m_len) ? 0u : m_done);
         d.b_len = inc_m ? piece : 0u;
         d.base = base;
         d.ca = ca;
@@ -814,15 +843,17 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
             const uint32_t k = r + i * G + gl;
             const Desc& e = s_desc[gslot + own[i]];
             const uint32_t q = k - e.base;
-            // match passes copy matches only, the parse literal runs only
-            const bool m = kOnlyMatch ? true : (MODE == kModeParse) ? false : (q >= e.ca);
+            // match passes copy matches only; the parse's match segments read
+            // the literal stream
+            const bool m = kOnlyMatch ? true : (q >= e.ca);
+            const bool m_out = m && MODE != kModeParse;
             const uintptr_t Dd = m ? e.b_dst : e.a_dst;
             const uintptr_t S = m ? e.b_src : e.a_src;
             const uint32_t L = m ? e.b_len : e.a_len;
             const uint32_t qq = m ? q - e.ca : q;
             const bool valid = k < C;
-            const uintptr_t lb = m ? D.msrc_lo : D.lit_lo, hb = m ? D.msrc_hi : D.lit_hi;
-            cs.from_out[i] = m;
+            const uintptr_t lb = m_out ? D.msrc_lo : D.lit_lo, hb = m_out ? D.msrc_hi : D.lit_hi;
+            cs.from_out[i] = m_out;
             cs.slow[i] = false;
             cs.sh[i] = 0;
             if (L >= 16) {
@@ -884,8 +915,16 @@ __global__ __launch_bounds__(MODE == kModeTail ? kWGTail : kWG) void k_lz(KArgs 
         for (uint32_t r = 0; r < C; r += G * U) {
           ChunkSet<U> cs;
           prep(r, cs);
+          if (MODE == kModeParse && span_drain) {
+            // the span's stores (and these loads) complete before any store of this pass
+            compiler_barrier();
+            __builtin_amdgcn_s_waitcnt(0);
+            compiler_barrier();
+            span_drain = false;
+          }
           commit(cs);
         }
+        span_drain = false;
         compiler_barrier();
         // ---------------------------------------------- retire segments
         if (inc_l) l_pend = false;
@@ -932,6 +971,8 @@ struct lz_dev {
   uint64_t n_seg = 0;
   u32x4* d_mtab = nullptr;
   uint64_t n_match = 0;
+  uint64_t n_fused = 0;  // literal-sourced matches, copied by the parse (slots [0, n_fused))
+  uint64_t fused_bytes = 0;
   std::vector<uint64_t> lvl_start;  // first window of each depth, n_levels + 1 entries
   std::vector<uint64_t> h_seg;      // host copies of the parse segments and windows (batch decodes merge them)
   std::vector<uint32_t> h_win;
@@ -1039,6 +1080,13 @@ struct Plan {
   // grains up to the range end read nothing below h.
   uint32_t log2_grain = kLog2Grain;
   std::vector<uint64_t> grain_low;
+  // Literal-sourced matches: slots [0, n_fused) hold depth-1 matches whose
+  // source is a stretch of one literal run and does not overlap their output.
+  // The parse copies them straight from the literal stream, so they take no
+  // window; fused_rec holds their records {dst lo, length, literal-stream
+  // offset lo, dst hi | offset hi << 16}, resident in the match table.
+  uint64_t n_fused = 0, fused_bytes = 0;
+  std::vector<uint32_t> fused_rec;
 };
 
 int build_plan(const lz::ArcView& v, Plan& P) {
@@ -1060,7 +1108,47 @@ int build_plan(const lz::ArcView& v, Plan& P) {
     }
   P.n_match = M;
   if (M > 0xFFFFFFF0ull) return lz::fail(LZ_E_INVAL, "too many matches for 32-bit plan indices");
-  std::vector<uint64_t> sstart(NL + 1, 0);  // first slot of each depth
+  // Depth-1 matches read literal bytes only.  Those whose source lies inside
+  // one token's literal run, and ends before their own output starts, read
+  // that run's bytes from the literal stream at a known offset (flit).
+  std::vector<uint64_t> flit(T + 1, UINT64_MAX);
+  if (cnt.size() > 1 && cnt[1]) {
+    std::vector<uint64_t> tdst(T + 1, 0), tlit(T + 1, 0);
+    std::vector<uint32_t> tll(T + 1, 0);
+    std::atomic<int> bad{0};
+    parallel_blocks(v, [&](uint64_t b) {
+      int r = lz::walk_block(v, b, [&](uint64_t t, const lz::Tok& k) {
+        tdst[t] = k.dst;
+        tlit[t] = k.lit_off;
+        tll[t] = (uint32_t)k.lit_len;
+      });
+      if (r) bad.store(r);
+    });
+    if (bad.load()) return lz::fail(LZ_E_CORRUPT, "archive fails validation");
+    parallel_blocks(v, [&](uint64_t b) {
+      (void)lz::walk_block(v, b, [&](uint64_t t, const lz::Tok& k) {
+        if (!k.mlen || depth[t] != 1) return;
+        const uint64_t md = k.dst + k.lit_len;
+        if (k.src + k.mlen > md) return;  // reads its own output
+        const uint64_t sb = k.src >> v.log2_bs;
+        // the last token of the source block starting at or before the source
+        const uint64_t* lo = tdst.data() + tab[4 * sb], * hi = tdst.data() + tab[4 * sb + 4];
+        const uint64_t* it = std::upper_bound(lo, hi, k.src);
+        if (it == lo) return;
+        const uint64_t s = (uint64_t)(it - tdst.data()) - 1;
+        if (k.src + k.mlen <= tdst[s] + tll[s]) flit[t] = tlit[s] + (k.src - tdst[s]);
+      });
+    });
+  }
+  uint64_t nF = 0;
+  for (uint64_t t = 0; t < T; ++t)
+    if (hasm[t] && flit[t] != UINT64_MAX) {
+      --cnt[depth[t]];
+      ++nF;
+    }
+  P.n_fused = nF;
+  std::vector<uint64_t> sstart(NL + 1, 0);  // first slot of each depth (after the fused slots)
+  sstart[0] = nF;
   for (uint64_t p = 0; p < NL; ++p) sstart[p + 1] = sstart[p] + cnt[p + 1];
   std::vector<uint64_t> cursor(sstart.begin(), sstart.end());
   P.slot.assign(T + 1, kNone);
@@ -1068,9 +1156,10 @@ int build_plan(const lz::ArcView& v, Plan& P) {
   std::vector<uint64_t> dst_of(M + 1, 0);
   std::vector<uint8_t> periodic(M + 1, 0);
   std::vector<uint64_t> blk_low(v.nb, UINT64_MAX);  // lowest match source of each block
+  uint64_t fc = 0;
   for (uint64_t t = 0; t < T; ++t)
     if (hasm[t]) {
-      P.slot[t] = (uint32_t)cursor[depth[t] - 1]++;
+      P.slot[t] = (uint32_t)(flit[t] != UINT64_MAX ? fc++ : cursor[depth[t] - 1]++);
       tok_of[P.slot[t]] = (uint32_t)t;
     }
   // lengths, and whether a match overlaps its own output
@@ -1088,6 +1177,16 @@ int build_plan(const lz::ArcView& v, Plan& P) {
       if (r) bad.store(r);
     });
     if (bad.load()) return lz::fail(LZ_E_CORRUPT, "archive fails validation");
+  }
+  P.fused_rec.resize(4 * nF);
+  for (uint64_t sl = 0; sl < nF; ++sl) {
+    const uint64_t md = dst_of[sl], lo = flit[tok_of[sl]];
+    uint32_t* r = &P.fused_rec[4 * sl];
+    r[0] = (uint32_t)md;
+    r[1] = len_of[sl];
+    r[2] = (uint32_t)lo;
+    r[3] = (uint32_t)((md >> 32) & 0xFFFFu) | (uint32_t)((lo >> 32) << 16);
+    P.fused_bytes += len_of[sl];
   }
   P.log2_grain = std::max<uint32_t>(kLog2Grain, v.log2_bs);
   const uint32_t lg = P.log2_grain;
@@ -1179,6 +1278,7 @@ ArcDesc arc_desc(const lz_dev* h, uint8_t* out, uint64_t out_cap) {
   d.log2_bs = v.log2_bs;
   d.nb = (uint32_t)v.nb;
   d.min_match = (uint32_t)v.min_match;
+  d.n_fused = (uint32_t)h->n_fused;
   d.out = out;
   d.msrc = out;
   d.msrc_lo = (uintptr_t)out;
@@ -1345,6 +1445,8 @@ int open_impl(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t d_cap
   h->n_seg = P.seg.size() / 8;
   h->d_mtab = (u32x4*)(base + L.mtab);
   h->n_match = P.n_match;
+  h->n_fused = P.n_fused;
+  h->fused_bytes = P.fused_bytes;
   h->lvl_start = P.lvl_start;
   h->h_seg = P.seg;
   h->h_win = P.win;
@@ -1369,6 +1471,7 @@ int open_impl(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t d_cap
       {h->d_lvls, P.lvls32.data(), 4 * P.lvls32.size()},
       {h->d_win, P.win.data(), 4 * P.win.size()},
       {h->d_seg, P.seg.data(), 8 * P.seg.size()},
+      {h->d_mtab, P.fused_rec.data(), 4 * P.fused_rec.size()},
   };
   uint64_t stage = v.total;
   for (const Piece& q : pieces) stage += (q.bytes + 255) & ~uint64_t(255);
@@ -1483,6 +1586,10 @@ int lz_entropy_decode_device(lz_dev* h, void* stream) {
 
 uint64_t lz_device_n(const lz_dev* h) { return h ? h->v.n : 0; }
 uint32_t lz_device_levels(const lz_dev* h) { return h ? (uint32_t)(h->lvl_start.size() ? h->lvl_start.size() - 1 : 0) : 0; }
+uint64_t lz_device_fused(const lz_dev* h, uint64_t* bytes) {
+  if (bytes) *bytes = h ? h->fused_bytes : 0;
+  return h ? h->n_fused : 0;
+}
 void lz_device_close(lz_dev* h) { delete h; }
 
 }  // extern "C"

@@ -86,6 +86,7 @@ def lib():
             "lz_device_check": (ctypes.c_int, [_vp, _vp]),
             "lz_device_n": (_u64, [_vp]),
             "lz_device_levels": (_u32, [_vp]),
+            "lz_device_fused": (_u64, [_vp, _p64]),
             "lz_device_close": (None, [_vp]),
             "lz_range_plan_create": (ctypes.c_int, [_vp, _u64, _vp, _vp, ctypes.POINTER(_vp)]),
             "lz_range_plan_scratch_bytes": (_u64, [_vp]),
@@ -333,6 +334,9 @@ class DeviceArchive:
         self.h = h
         self.n = int(lib().lz_device_n(h))
         self.levels = int(lib().lz_device_levels(h))
+        fb = _u64()
+        self.fused = int(lib().lz_device_fused(h, ctypes.byref(fb)))  # literal-sourced matches the parse copies
+        self.fused_bytes = int(fb.value)
         self.device_bytes = nb.value
 
     def decode(self, out=None, G=64, unroll=2, schedule=1, stream=None, check=True, tail=0, mapping=0, occupancy=0,
