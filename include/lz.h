@@ -221,9 +221,10 @@ int lz_device_open(const uint8_t* arc, uint64_t arc_size, void* d_buf, uint64_t 
 int lz_decode_device(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cfg* cfg, void* stream);
 
 /* The two stages of lz_decode_device as separate launch sequences (to time or
- * schedule them apart): stage 1 = the parse launch (literal bytes written, the
- * match table filled; where literals are dense the parse writes whole aligned
- * blocks of the output, so match bytes hold arbitrary values after stage 1
+ * schedule them apart): stage 1 = the parse launch (literal bytes and the
+ * literal-sourced matches of lz_device_fused written, the match table filled;
+ * where literals are dense the parse writes whole aligned blocks of the
+ * output, so the other match bytes hold arbitrary values after stage 1
  * alone), stage 2 = the match passes, which must follow stage 1 of the same
  * handle and output on the same stream; stage 0 = both. */
 int lz_decode_device_stage(lz_dev* h, uint8_t* d_out, uint64_t out_cap, const lz_decode_cfg* cfg, int stage,
