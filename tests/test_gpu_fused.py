@@ -1,5 +1,5 @@
 """GPU parity for the literal-sourced matches the parse copies itself: the
-plan's choice is pinned by a count written out here from the oracle's tokens
+plan's choice is pinned by a count derived from the oracle's tokens
 and dependency depths, and the bytes those matches write after the parse
 launch alone are compared with the input."""
 import numpy as np
@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 import synth
+from fused_ref import literal_sourced
 from paper_2607_18541_amd import lz
 
 torch = pytest.importorskip("torch")
@@ -17,24 +18,6 @@ def _dev():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     return torch.device("cuda:0")
-
-
-def literal_sourced(arc):
-    """Matches of dependency depth 1 whose source [src, src + len) lies inside
-    one token's literal run and ends at or before the match's own output:
-    returns (mask over tokens, output start of each match)."""
-    tk = oracle.tokens(arc)
-    depth, _ = oracle.levels(arc)
-    dst = tk["dst"].astype(np.int64)
-    ll = tk["lit_len"].astype(np.int64)
-    ml = tk["mlen"].astype(np.int64)
-    src = tk["src"].astype(np.int64)
-    md = dst + ll
-    t = np.searchsorted(dst, src, side="right") - 1
-    t = np.clip(t, 0, len(dst) - 1)
-    inside = (src >= dst[t]) & (src + ml <= dst[t] + ll[t])
-    mask = (ml > 0) & (depth == 1) & (src + ml <= md) & inside
-    return mask, md, ml
 
 
 CASES = [
