@@ -3,7 +3,10 @@ fields of the device match records and gathers past 2^32 are compared with
 the oracle.  A 4.38 GB token stream (geometric match lengths of mean 256,
 sources uniform over everything at least 64 KiB back, so most matches past
 2^32 read below it) gets a few planted matches: sources whose span straddles
-2^32 and a period-3 self-overlapping match cut at 2^32.  The whole decode,
+2^32, a period-3 self-overlapping match cut at 2^32, and matches written
+above 2^32 whose sources lie inside a literal run there (copied by the parse
+from the literal stream, so their records carry high destination bits).  The
+whole decode,
 ranges around and across 2^32 and a served request are checked byte by byte
 and by FNV-1a 64 against the oracle's execution of the same tokens."""
 import numpy as np
@@ -41,12 +44,25 @@ def _stream():
         t -= 1
     assert mstart[t] < B32 < mstart[t] + ml[t] or mstart[t] + ml[t] <= B32
     sr[t] = mstart[t] - 3
-    return n, ll, ml, sr, lit, far, int(mstart[t])
+    per_at = int(mstart[t])
+    # literal-sourced matches above 2^32: the next short match after a literal
+    # run of 8 bytes or more reads that run's first bytes
+    lit_src = []
+    runs = np.nonzero((mstart - ll > B32 + (96 << 20)) & (ll >= 8))[0][:8]
+    for r in runs:
+        run0 = int(mstart[r] - ll[r])
+        for t2 in range(int(r) + 2, int(r) + 4000):
+            if 1 <= ml[t2] <= ll[r] and t2 not in far:
+                sr[t2] = run0
+                lit_src.append(t2)
+                break
+    assert len(lit_src) == 8
+    return n, ll, ml, sr, lit, far, per_at, lit_src
 
 
 def test_decode_above_4gib_matches_oracle():
     dev = _dev()
-    n, ll, ml, sr, lit, far, per_at = _stream()
+    n, ll, ml, sr, lit, far, per_at, lit_src = _stream()
     print("building the 4.38 GB stream and its oracle output", flush=True)
     x = oracle.exec_tokens(n, ll, ml, sr, lit)
     arc = lz.build_archive(n, 16, ll, ml, sr, lit)
@@ -54,7 +70,8 @@ def test_decode_above_4gib_matches_oracle():
     assert np.array_equal(oracle.decode(arc), x), "the oracle's reader disagrees with its token execution"
     x_fnv = oracle.fnv1a64(x)
     da = lz.DeviceArchive(arc, device=dev)
-    print("device archive: %d depths" % da.levels, flush=True)
+    print("device archive: %d depths, %d literal-sourced matches" % (da.levels, da.fused), flush=True)
+    assert da.fused >= len(lit_src)
     exp = torch.from_numpy(x).to(dev)
     out = da.decode()
     torch.cuda.synchronize()
@@ -67,7 +84,7 @@ def test_decode_above_4gib_matches_oracle():
     rng = np.random.default_rng(42)
     cases = [(B32 - 1, 2), (B32 - 5000, 10000), (B32, 1), (B32 - (1 << 20), 2 << 20), (n - 1, 1), (n - (3 << 20), 3 << 20),
              (per_at - 4, 64), (B32 - 17, 33), (0, 4096)]
-    for t in far[:4]:
+    for t in list(far[:4]) + lit_src[:4]:
         a = int(np.concatenate([[0], np.cumsum(ll[:t].astype(np.int64) + ml[:t])])[-1] + ll[t])
         cases.append((a - 10, int(ml[t]) + 20))
     for _ in range(30):
