@@ -166,7 +166,7 @@ const char* lz_last_error(void);
 typedef struct lz_dev lz_dev; /* opaque handle of a device-resident archive */
 
 /* Decode configuration.  A decode is a parse launch (one group of G lanes per
- * 256-token segment of a block: token headers, literal bytes, match table)
+ * 128-token segment of a block: token headers, literal bytes, match table)
  * followed by the matches in order of their depth (lz_plan), cut into windows
  * of at most 64 matches and 3 KiB of match output (a longer match is split
  * over windows); the G lanes of a group cooperate on 64 / G parts of a window
@@ -187,7 +187,7 @@ typedef struct lz_dev lz_dev; /* opaque handle of a device-resident archive */
  * that), an occupancy control (Sec. 3.3); LZ_E_INVAL outside that range or
  * above what fits anyway.  Batches and range plans ignore it.
  * G and unroll select the match copy; the parse launch has its own group
- * size and unroll (parse_G, parse_unroll): a whole wave per 256-token
+ * size and unroll (parse_G, parse_unroll): a whole wave per 128-token
  * segment is the fastest parse at every G (measured: at G = 32 the parse
  * with 32-lane groups takes 1.07 ms of a 1.84 ms decode, with a wave 0.63).
  * NULL config = G 64, unroll 2, schedule 1, tail 0, mapping 0, occupancy 0,

@@ -4,7 +4,7 @@
 // width G; Sec. 3.1: lanes = G x N_blocks).  A decode is a parse launch
 // followed by the match passes:
 //
-//  parse  One group per segment of 256 tokens of one block: each lane reads
+//  parse  One group per segment of 128 tokens of one block: each lane reads
 //         one token header (cmd byte, source, plan slot), a group prefix count
 //         locates the length extensions, and prefix sums give every token's
 //         output position and literal offset, so G tokens are parsed per
@@ -85,7 +85,7 @@ constexpr int kModePure = 2;    // pre-decoded tokens, sources in a reference bu
 constexpr int kModeParse = 3;   // parse blocks, copy literals, fill the match table
 constexpr int kModeTail = 4;    // the last, small levels in one workgroup, a barrier between levels
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr uint64_t kSegTok = 256;    // tokens per parse segment
+constexpr uint64_t kSegTok = 128;    // tokens per parse segment
 constexpr uint32_t kWinBytes = 3072;  // a match window holds at most this many bytes ...
 constexpr uint32_t kWinMatches = 64;  // ... and at most this many matches
 constexpr uint32_t kLog2Grain = 20;  // and its matches lie in one aligned grain of max(2^20, block) bytes
